@@ -1,0 +1,374 @@
+"""FP64 reference solver for the pseudospectral P_N radiative transport step.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring): the product path never
+imports this module.
+
+What it computes (Powell, Cox & Arridge, "A pseudospectral method for
+solution of the radiative transport equation", arXiv:1801.06364):
+
+* the transport equation, eq. (1), with the Henyey-Greenstein phase
+  function, eq. (2);
+* radiance and source expanded in complex spherical harmonics with weights
+  sqrt((2l+1)/4pi), eqs. (3)-(4); the addition theorem, eq. (5), makes the
+  in-scattering diagonal, ``mu_s g^l psi_l^m``;
+* the coupled first-order system eq. (6), truncated at ``l > N`` (Sec. II.A);
+* spatial derivatives taken spectrally with the transform of eq. (8) on a
+  periodic grid (Sec. II, II.A);
+* the boundary layer of eq. (12): outside the real domain the scattering
+  is switched off, the source is zero and a smooth (half-cosine) isotropic
+  loss ``mu_b`` is applied (Sec. II.B, Sec. III.B);
+* time marching with the classic four-stage Runge-Kutta tableau (the paper
+  writes a first-order explicit step, eq. (11); the workloads here use RK4).
+
+Readings of the paper that this module takes (the paper is silent or its
+printed signs disagree with its own eqs. (1) and (6)):
+
+* sign: ``d psi/dt = c (-[s.grad psi] - (mu_t - mu_s g^l) psi + q)``, the
+  form eqs. (1) and (6) give; eqs. (9)-(11) print other signs;
+* wavenumbers ``k = 2 pi f / (n dx)`` with the Nyquist entry set to zero;
+* forward transform unnormalised with ``exp(-i k.r)`` (eq. 8), inverse
+  scaled by ``1/n^3``;
+* the layer depth of a voxel is its Chebyshev (max-norm) distance in voxels
+  from the real domain, and ``mu_b = mu0 + (mu1 - mu0)(1 - cos(pi d/W))/2``.
+
+Layout: moment fields are ``[a][z][y][x]`` with ``a = l*l + l + m``.
+The oracle runs in the COMPLEX basis of eq. (3); inputs and outputs are
+converted to and from the real basis (no Condon-Shortley phase) through a
+unitary matrix computed by quadrature.
+
+Everything here is float64 / complex128.
+"""
+from __future__ import annotations
+
+import math
+import os
+
+import numpy as np
+import scipy.fft as sfft
+from scipy.special import sph_harm_y
+
+WORKERS = os.cpu_count() or 1
+
+
+# ----------------------------------------------------------- indexing ---
+
+def sh_index(l: int, m: int) -> int:
+    """Flat moment index of (l, m): ``l*l + l + m``."""
+    return l * l + l + m
+
+
+def sh_lm(a: int):
+    """Inverse of :func:`sh_index`."""
+    l = int(math.isqrt(a))
+    return l, a - l * l - l
+
+
+# ------------------------------------------------ eq. (6) coefficients ---
+
+def alpha(l: int, m: int) -> float:
+    """alpha_l^m = sqrt((l+m)(l-m)), eq. (6)."""
+    v = (l + m) * (l - m)
+    assert v >= 0, (l, m)
+    return math.sqrt(v)
+
+
+def beta(l: int, m: int) -> float:
+    """beta_l^m = sqrt((l+m)(l+m-1)), eq. (6)."""
+    v = (l + m) * (l + m - 1)
+    assert v >= 0, (l, m)
+    return math.sqrt(v)
+
+
+def coupling_matrices(N: int):
+    """Complex-basis streaming matrices ``(Bx, By, Bz)`` of eq. (6).
+
+    Row ``(l, m)`` of ``B_j`` holds the coefficient of ``d/dj psi_{l'}^{m'}``
+    in the streaming part of eq. (6), divided by ``2l+1``, so that the
+    streaming term is ``sum_j B_j d/dj psi``. Terms that reach ``l' > N``
+    are dropped (P_N closure, Sec. II.A); terms that reach ``|m'| > l'`` have
+    zero coefficient and are skipped.
+    """
+    M = (N + 1) ** 2
+    Bx = np.zeros((M, M), complex)
+    By = np.zeros((M, M), complex)
+    Bz = np.zeros((M, M), complex)
+
+    def ok(l, m):
+        return 0 <= l <= N and -l <= m <= l
+
+    for l in range(N + 1):
+        w = 1.0 / (2 * l + 1)
+        for m in range(-l, l + 1):
+            a = sh_index(l, m)
+            # d/dz [ alpha_{l+1}^m psi_{l+1}^m + alpha_l^m psi_{l-1}^m ]
+            if ok(l + 1, m):
+                Bz[a, sh_index(l + 1, m)] += w * alpha(l + 1, m)
+            if ok(l - 1, m):
+                Bz[a, sh_index(l - 1, m)] += w * alpha(l, m)
+            # -1/2 (d/dx - i d/dy) [ beta_l^m psi_{l-1}^{m-1}
+            #                       - beta_{l+1}^{-m+1} psi_{l+1}^{m-1} ]
+            terms = []
+            if ok(l - 1, m - 1):
+                terms.append((sh_index(l - 1, m - 1), -0.5 * beta(l, m), -1j))
+            if ok(l + 1, m - 1):
+                terms.append((sh_index(l + 1, m - 1),
+                              0.5 * beta(l + 1, -m + 1), -1j))
+            # -1/2 (d/dx + i d/dy) [ -beta_l^{-m} psi_{l-1}^{m+1}
+            #                       + beta_{l+1}^{m+1} psi_{l+1}^{m+1} ]
+            if ok(l - 1, m + 1):
+                terms.append((sh_index(l - 1, m + 1), 0.5 * beta(l, -m), 1j))
+            if ok(l + 1, m + 1):
+                terms.append((sh_index(l + 1, m + 1),
+                              -0.5 * beta(l + 1, m + 1), 1j))
+            for b, coef, ycoef in terms:
+                Bx[a, b] += w * coef
+                By[a, b] += w * coef * ycoef
+    return Bx, By, Bz
+
+
+# ------------------------------------------------------- real basis -----
+
+def _sphere_quadrature(L: int):
+    """Nodes/weights exact for polynomials of degree <= L on the sphere:
+    Gauss-Legendre in cos(theta) times the trapezoid rule in phi."""
+    nt = L // 2 + 1
+    nph = L + 1
+    x, wx = np.polynomial.legendre.leggauss(nt)
+    theta = np.arccos(x)
+    phi = 2 * np.pi * np.arange(nph) / nph
+    T, P = np.meshgrid(theta, phi, indexing="ij")
+    Wt = np.outer(wx, np.full(nph, 2 * np.pi / nph))
+    return T.ravel(), P.ravel(), Wt.ravel()
+
+
+def complex_sh(N: int, theta, phi):
+    """Rows ``Y_l^m(theta, phi)`` for all ``a``, Condon-Shortley phase."""
+    M = (N + 1) ** 2
+    Y = np.zeros((M, theta.size), complex)
+    for l in range(N + 1):
+        for m in range(-l, l + 1):
+            Y[sh_index(l, m)] = sph_harm_y(l, m, theta, phi)
+    return Y
+
+
+def real_sh(N: int, theta, phi):
+    """Real harmonics without Condon-Shortley phase:
+    ``sqrt2 N P_l^m cos(m phi)`` (m>0), ``Y_l^0`` (m=0),
+    ``sqrt2 N P_l^|m| sin(|m| phi)`` (m<0)."""
+    M = (N + 1) ** 2
+    Y = np.zeros((M, theta.size))
+    for l in range(N + 1):
+        for m in range(-l, l + 1):
+            yc = sph_harm_y(l, abs(m), theta, phi)
+            if m > 0:
+                Y[sh_index(l, m)] = math.sqrt(2) * (-1) ** m * yc.real
+            elif m < 0:
+                Y[sh_index(l, m)] = math.sqrt(2) * (-1) ** m * yc.imag
+            else:
+                Y[sh_index(l, m)] = yc.real
+    return Y
+
+
+def real_basis_transform(N: int) -> np.ndarray:
+    """Unitary ``U`` with ``Y^R_a = sum_b U[a,b] Y_b``, by exact quadrature
+    of ``<Y^R_a, Y_b>`` over the sphere."""
+    T, P, Wq = _sphere_quadrature(2 * N + 2)
+    YR = real_sh(N, T, P)
+    Y = complex_sh(N, T, P)
+    return (YR * Wq) @ Y.conj().T
+
+
+def to_complex_basis(psi_real: np.ndarray, U: np.ndarray) -> np.ndarray:
+    """Complex-basis moments of a real-basis field: ``psi = U^T psi^R``
+    (same weights, so the radiance is unchanged)."""
+    return np.tensordot(U.T, psi_real, axes=(1, 0))
+
+
+def to_real_basis(psi: np.ndarray, U: np.ndarray) -> np.ndarray:
+    """Real-basis moments ``conj(U) psi``; the imaginary part of a physical
+    (real) radiance is zero up to rounding and is dropped."""
+    return np.tensordot(U.conj(), psi, axes=(1, 0)).real
+
+
+# --------------------------------------------------- grid and medium ----
+
+def wavenumbers(n: int, dx: float) -> np.ndarray:
+    """``k = 2 pi f / (n dx)`` in FFT order, Nyquist entry set to zero."""
+    k = 2 * np.pi * np.fft.fftfreq(n, d=dx)
+    if n % 2 == 0:
+        k[n // 2] = 0.0
+    return k
+
+
+def pml_depth(n: int, W: int) -> np.ndarray:
+    """Max-norm distance (voxels) of each voxel from the real domain
+    ``[W, n-W)^3``; zero inside it."""
+    i = np.arange(n)
+    d1 = np.maximum(np.maximum(W - i, i - (n - 1 - W)), 0)
+    return np.maximum(np.maximum(d1[:, None, None], d1[None, :, None]),
+                      d1[None, None, :])
+
+
+def pml_profile(n: int, W: int, mu0: float, mu1: float) -> np.ndarray:
+    """Half-cosine layer attenuation ``mu_b`` (Sec. II.B, Sec. III.B): rises
+    smoothly from ``mu0`` at the real-domain edge to ``mu1`` at depth ``W``.
+    Zero where the depth is zero (inside the real domain)."""
+    d = pml_depth(n, W).astype(float)
+    if W == 0:
+        return np.zeros_like(d)
+    mub = mu0 + (mu1 - mu0) * 0.5 * (1.0 - np.cos(np.pi * d / W))
+    return np.where(d > 0, mub, 0.0)
+
+
+def potentials(mu_a, mu_s, g, N: int, W: int, mu0: float, mu1: float):
+    """Per-degree loss ``Sigma_l(r)`` and real-domain mask (eqs. 6, 12).
+
+    Inside the real domain ``Sigma_l = mu_t - mu_s g^l`` with
+    ``mu_t = mu_a + mu_s``; in the layer ``Sigma_l = mu_b`` for every ``l``
+    (no scattering there)."""
+    n = mu_a.shape[0]
+    d = pml_depth(n, W)
+    omega = d == 0
+    mub = pml_profile(n, W, mu0, mu1)
+    Sig = np.empty((N + 1,) + mu_a.shape)
+    for l in range(N + 1):
+        inside = mu_a + mu_s - mu_s * g ** l
+        Sig[l] = np.where(omega, inside, mub)
+    return Sig, omega
+
+
+# --------------------------------------------------------- operator -----
+
+def _pairs(B):
+    """Non-zero (a, b) entries of the three streaming matrices."""
+    Bx, By, Bz = B
+    nz = (np.abs(Bx) + np.abs(By) + np.abs(Bz)) > 0
+    return [(a, b, Bx[a, b], By[a, b], Bz[a, b])
+            for a, b in zip(*np.nonzero(nz))]
+
+
+def operator(psi, Sig, q, B, k, c, workers=None):
+    """Right-hand side ``d psi/dt`` of the semi-discrete system (eq. 9 with
+    the sign reading above):
+    ``c * (-IFFT[sum_j i k_j B_j FFT(psi)] - Sigma_l psi + q)``."""
+    workers = workers or WORKERS
+    M = psi.shape[0]
+    N = int(math.isqrt(M)) - 1
+    psih = sfft.fftn(psi, axes=(1, 2, 3), workers=workers)
+    kz = k[:, None, None]
+    ky = k[None, :, None]
+    kx = k[None, None, :]
+    shat = np.zeros_like(psih)
+    for a, b, bx, by, bz in _pairs(B):
+        shat[a] += 1j * (kx * bx + ky * by + kz * bz) * psih[b]
+    del psih
+    s = sfft.ifftn(shat, axes=(1, 2, 3), workers=workers)
+    del shat
+    out = np.empty_like(psi)
+    for l in range(N + 1):
+        for m in range(-l, l + 1):
+            a = sh_index(l, m)
+            out[a] = -s[a] - Sig[l] * psi[a]
+            if q is not None:
+                out[a] += q[a]
+    out *= c
+    return out
+
+
+def rk4_step(psi, f, dt):
+    """Classic four-stage Runge-Kutta step (Butcher tableau 1/2, 1/2, 1;
+    weights 1/6, 1/3, 1/3, 1/6)."""
+    k = f(psi)
+    acc = k.copy()
+    k = f(psi + (0.5 * dt) * k)
+    acc += 2.0 * k
+    k = f(psi + (0.5 * dt) * k)
+    acc += 2.0 * k
+    k = f(psi + dt * k)
+    acc += k
+    return psi + (dt / 6.0) * acc
+
+
+def solve(n, N, dx, c, dt, mu_a, mu_s, g, psi0_real, q_real, W, mu0, mu1,
+          steps, det_index=(), workers=None, return_state=True):
+    """March ``steps`` RK4 steps from ``psi0_real`` (real-basis moments).
+
+    Returns a dict with ``fluence`` (psi_0^0 after the last step),
+    ``readings`` ``[steps][n_det]`` (psi_0^0 at the detector voxels after
+    every step), ``phi_int`` (sum over steps of ``dt * psi_0^0``),
+    ``residual`` ``[steps]`` (``||phi_n - phi_{n-1}|| / ||phi_n||``) and,
+    if asked, ``state`` (real-basis moments after the last step)."""
+    M = (N + 1) ** 2
+    B = coupling_matrices(N)
+    U = real_basis_transform(N)
+    k = wavenumbers(n, dx)
+    Sig, omega = potentials(mu_a, mu_s, g, N, W, mu0, mu1)
+    if psi0_real is None:
+        psi = np.zeros((M, n, n, n), complex)
+    else:
+        psi = to_complex_basis(np.asarray(psi0_real, float), U).astype(complex)
+    q = None
+    if q_real is not None:
+        q = to_complex_basis(np.asarray(q_real, float), U) * omega[None]
+    det = np.asarray(det_index, dtype=np.int64)
+    readings = np.zeros((steps, det.size))
+    residual = np.zeros(steps)
+    phi_int = np.zeros((n, n, n))
+    prev = psi[0].real.copy()
+
+    def f(y):
+        return operator(y, Sig, q, B, k, c, workers)
+
+    for s in range(steps):
+        psi = rk4_step(psi, f, dt)
+        phi = psi[0].real
+        readings[s] = phi.ravel()[det]
+        phi_int += dt * phi
+        nrm = np.linalg.norm(phi)
+        residual[s] = np.linalg.norm(phi - prev) / nrm if nrm > 0 else 0.0
+        prev = phi.copy()
+    out = dict(fluence=psi[0].real.copy(), readings=readings,
+               phi_int=phi_int, residual=residual)
+    if return_state:
+        out["state"] = to_real_basis(psi, U)
+    return out
+
+
+# ----------------------------------------- single-mode algebra (pins) ---
+
+def mode_matrix(N: int, kvec, sig_l, c: float) -> np.ndarray:
+    """Generator ``M(k) = -c (i k.B + diag(Sigma_l(a)))`` of one Fourier
+    mode in a homogeneous medium (complex basis)."""
+    Bx, By, Bz = coupling_matrices(N)
+    kx, ky, kz = kvec
+    M = (N + 1) ** 2
+    D = np.array([sig_l[sh_lm(a)[0]] for a in range(M)], float)
+    return -c * (1j * (kx * Bx + ky * By + kz * Bz) + np.diag(D))
+
+
+def rk4_poly(Z: np.ndarray) -> np.ndarray:
+    """Stability polynomial of classic RK4, ``I + Z + Z^2/2 + Z^3/6 + Z^4/24``."""
+    I = np.eye(Z.shape[0], dtype=complex)
+    Z2 = Z @ Z
+    Z3 = Z2 @ Z
+    return I + Z + Z2 / 2 + Z3 / 6 + Z3 @ Z / 24
+
+
+# --------------------------------------------------- phase function -----
+
+def hg_phase(mu, g):
+    """Henyey-Greenstein phase function of eq. (2), ``mu = s.s'``."""
+    return (1.0 - g * g) / (4 * np.pi * (1.0 + g * g - 2 * g * mu) ** 1.5)
+
+
+def hg_legendre_moments(g: float, L: int, nodes: int = 400) -> np.ndarray:
+    """``2 pi int p(mu) P_l(mu) dmu`` for l = 0..L by Gauss-Legendre
+    quadrature (the diagonal scattering factor the addition theorem, eq. 5,
+    puts on degree l)."""
+    x, w = np.polynomial.legendre.leggauss(nodes)
+    p = hg_phase(x, g)
+    out = np.zeros(L + 1)
+    for l in range(L + 1):
+        Pl = np.polynomial.legendre.Legendre.basis(l)(x)
+        out[l] = 2 * np.pi * np.sum(w * p * Pl)
+    return out
