@@ -1,0 +1,156 @@
+/*
+ * rte.h -- C-ABI of the MI355X pseudospectral P_N radiative-transport stepper.
+ *
+ * Method: S. Powell, B. T. Cox, S. R. Arridge, "A pseudospectral method for
+ * solution of the radiative transport equation" (arXiv:1801.06364).
+ *
+ *  - Radiance and source are expanded in spherical harmonics with weights
+ *    sqrt((2l+1)/4pi) (Sec. II, eqs. 3-4). This library stores REAL
+ *    harmonics (no Condon-Shortley phase) with those same weights, so moment
+ *    a = l*l + l + m holds psi_{l,m}; psi_{0,0} is the fluence and
+ *    (psi_{1,1}, psi_{1,-1}, psi_{1,0}) is the flux vector (Jx, Jy, Jz).
+ *  - Streaming couples degree l to l+-1 (eq. 6); it is applied spectrally
+ *    (Sec. II, eqs. 7-10) on a periodic grid with k = 2 pi f / (n dx) and the
+ *    Nyquist wavenumber set to zero.
+ *  - Loss and in-scatter are pointwise: Sigma_l = mu_a + mu_s (1 - g^l) in
+ *    the real domain (eqs. 5-6); in the absorbing boundary layer (eq. 12)
+ *    scattering and source are switched off and Sigma_l = mu_b, a half-cosine
+ *    profile rising from pml_mu0 at the real-domain edge to pml_mu1 at the
+ *    grid edge (Sec. II.B, Sec. III.B).
+ *  - Time integration is the classic four-stage Runge-Kutta method applied
+ *    to d psi/dt = c (-[s.grad psi] - Sigma_l psi + q) (the sign form that
+ *    eqs. 1 and 6 give), evaluated in the equivalent nested form
+ *    v <- u + dt/4 f(u); v <- u + dt/3 f(v); v <- u + dt/2 f(v);
+ *    u <- u + dt f(v), exact for this autonomous affine right-hand side.
+ *
+ * Grid: n^3 voxels, voxel (z, y, x) at r = (x, y, z) * dx; every field is
+ * stored [z][y][x] with x fastest; moment fields are [a][z][y][x]. The real
+ * domain is [W, n-W)^3 with W = pml_width.
+ *
+ * Memory: the library never allocates device memory. The caller passes one
+ * device workspace of at least rte_workspace_bytes() bytes (256-byte
+ * aligned) that must outlive the handle. Host arrays passed in are read
+ * during the call and not retained. All work is queued on the caller's HIP
+ * stream; calls that return host data synchronise that stream.
+ *
+ * Errors: every int-returning call returns RTE_OK (0) or a negative code;
+ * no exception crosses this boundary. A handle is not thread-safe; distinct
+ * handles are independent.
+ */
+#ifndef RTE_H
+#define RTE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  RTE_OK = 0,
+  RTE_EINVAL = -1,     /* bad argument or unsupported configuration         */
+  RTE_ENOMEM = -2,     /* workspace too small or misaligned                 */
+  RTE_EUNSTABLE = -3,  /* non-finite fluence or runaway growth detected     */
+  RTE_EDEVICE = -4     /* a HIP call failed                                 */
+};
+
+enum { RTE_FP32 = 0, RTE_FP64 = 1 };
+enum { RTE_FLUENCE_NOW = 0, RTE_FLUENCE_INTEGRATED = 1 };
+
+typedef struct rte_handle rte_handle;
+
+typedef struct {
+  int32_t n;               /* points per axis: 16, 32, 48, 64, 96 or 128      */
+  int32_t order_N;         /* P_N order, 0 <= N <= 7; M = (N+1)^2 moments     */
+  int32_t precision;       /* RTE_FP32 or RTE_FP64 for state, FFTs, stages;
+                              tables are computed in FP64 and rounded once;
+                              the integrated fluence is always FP64          */
+  int32_t pml_width;       /* W, absorbing-layer voxels on every face,
+                              0 <= W < n/2 (0: fully periodic, no layer)     */
+  double dx_mm;            /* grid spacing (mm), > 0                          */
+  double c_mm_ps;          /* speed of light in the medium (mm/ps), > 0       */
+  double dt_ps;            /* time step (ps); <= 0 selects 0.2 * dx / c       */
+  double pml_mu0;          /* layer attenuation at the real-domain edge       */
+  double pml_mu1;          /* layer attenuation at the grid edge (mm^-1)      */
+  int32_t n_det;           /* number of detector voxels (>= 0)                */
+  int32_t reserved0;
+  const int64_t* det_index;/* n_det linear voxel indices (z*n+y)*n+x, host    */
+  int64_t record_steps;    /* capacity of the per-step record (readings,
+                              residuals); later steps run unrecorded         */
+} rte_config;
+
+typedef struct {           /* host arrays, FP64, read during rte_create only   */
+  const double* mu_a;      /* n^3 absorption (mm^-1), >= 0                     */
+  const double* mu_s;      /* n^3 scattering (mm^-1), >= 0                     */
+  const double* g;         /* n^3 HG anisotropy, -1 < g < 1                    */
+  const double* psi0;      /* M*n^3 initial real-basis moments, or NULL (0)    */
+  const double* q;         /* M*n^3 time-constant source moments, or NULL;
+                              zeroed inside the absorbing layer (eq. 12)      */
+} rte_medium;
+
+/* Bytes of device workspace a configuration needs (0 if it is invalid). */
+size_t rte_workspace_bytes(const rte_config* cfg);
+
+/* Validate, build the FP64 tables (streaming coefficients of eq. 6 in the
+ * real basis, twiddles, wavenumbers, per-degree losses with the absorbing
+ * layer of eq. 12), carve the workspace and upload the medium and state.
+ * hip_stream is a hipStream_t (NULL = the default stream). On success
+ * *out receives a handle owned by the library until rte_destroy. */
+int rte_create(const rte_config* cfg, const rte_medium* med, void* dev_ws,
+               size_t ws_bytes, void* hip_stream, rte_handle** out);
+
+/* Queue nsteps >= 0 full RK4 steps (asynchronous). After each step the
+ * fluence psi_{0,0} at the detectors, the FP64 time-integrated fluence
+ * (+= dt * psi_{0,0}) and the relative fluence change
+ * ||phi_n - phi_{n-1}||_2 / ||phi_n||_2 are updated on the device. Once a
+ * non-finite value is seen the remaining queued steps do nothing. */
+int rte_step(rte_handle* h, int64_t nsteps);
+
+/* March until the relative fluence change of a step drops below steady_tol
+ * (> 0) or max_steps steps have run. The step that meets the tolerance is
+ * the last one applied (later queued steps are skipped on the device).
+ * *steps_taken receives the number of steps applied by this call.
+ * Returns RTE_EUNSTABLE if a non-finite value or runaway growth appears. */
+int rte_run(rte_handle* h, int64_t max_steps, double steady_tol,
+            int64_t* steps_taken);
+
+/* Copy the fluence psi_{0,0} (which = RTE_FLUENCE_NOW) or the integrated
+ * fluence (RTE_FLUENCE_INTEGRATED) to a caller-owned FP64 host buffer of
+ * len >= n^3 elements. Synchronises the stream. */
+int rte_fluence(rte_handle* h, int which, double* out, size_t len);
+
+/* Copy min(steps recorded, len / n_det) rows of detector readings
+ * [step][det] (FP64) into out; *rows receives the row count. */
+int rte_readings(rte_handle* h, double* out, size_t len, int64_t* rows);
+
+/* Copy the per-step relative fluence change (FP64) into out (len entries
+ * max); *rows receives the number written. */
+int rte_residuals(rte_handle* h, double* out, size_t len, int64_t* rows);
+
+/* Steps applied since creation (synchronises the stream). */
+int rte_steps_done(rte_handle* h, int64_t* steps);
+
+/* Read or overwrite the full real-basis moment state u (M*n^3, FP64 on the
+ * host, converted to/from the working precision). rte_set_state also
+ * resets the step count, the record and the integrated fluence. */
+int rte_get_state(rte_handle* h, double* out, size_t len);
+int rte_set_state(rte_handle* h, const double* in, size_t len);
+
+/* Dense real-basis streaming matrices B_x, B_y, B_z (each M*M, row-major,
+ * FP64) exactly as the library tabulates them from eq. (6). Host only, no
+ * device needed. */
+int rte_coupling_dense(int32_t order_N, double* bx, double* by, double* bz);
+
+/* Release the handle (and its captured graph). The workspace stays the
+ * caller's. Safe on NULL. */
+void rte_destroy(rte_handle* h);
+
+/* Static description of an error code. */
+const char* rte_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RTE_H */

@@ -1,0 +1,75 @@
+// Internal declarations shared by the host table builder and the HIP
+// runtime of the P_N stepper (not part of the public C-ABI).
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+namespace rte {
+
+constexpr int kMaxOrder = 7;                       // N <= 7
+constexpr int kMaxMoments = (kMaxOrder + 1) * (kMaxOrder + 1);
+constexpr int kMaxSlots = 12;                      // coupling slots per row
+
+constexpr int isqrt_c(int a) {
+  int l = 0;
+  while ((l + 1) * (l + 1) <= a) ++l;
+  return l;
+}
+
+// Candidate coupling partners of real-basis row (l, m). The streaming
+// operator of eq. (6) moves degree l to l +- 1 and order m to m or m +- 1;
+// in the real basis (cos / sin pairs) a row (l, m) can therefore only reach
+// (l +- 1, m') with m' in {m-1, m, m+1, -m-1, -m, -m+1}. The slots list those
+// partners (in range, de-duplicated, ascending l' then m'); the host table
+// stores one coefficient triple (Bx, By, Bz) per slot, possibly zero.
+struct SlotList {
+  int count;
+  int b[kMaxSlots];
+};
+
+constexpr SlotList slots_of(int N, int l, int m) {
+  SlotList s{0, {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}};
+  for (int dl = -1; dl <= 1; dl += 2) {
+    const int lp = l + dl;
+    if (lp < 0 || lp > N) continue;
+    const int cand[6] = {m - 1, m, m + 1, -m - 1, -m, -m + 1};
+    // ascending, de-duplicated
+    for (int mp = -lp; mp <= lp; ++mp) {
+      bool hit = false;
+      for (int c = 0; c < 6; ++c) hit = hit || (cand[c] == mp);
+      if (hit) s.b[s.count++] = lp * lp + lp + mp;
+    }
+  }
+  return s;
+}
+
+// ---------------------------------------------------------------- tables --
+
+// Real-basis streaming matrices (dense M x M, row-major, FP64) built from
+// the complex-basis coefficients of eq. (6) and the unitary change of basis
+// to real harmonics without Condon-Shortley phase. Returns false if N is out
+// of range or a non-zero entry falls outside the slot pattern.
+bool coupling_dense(int N, std::vector<double>& bx, std::vector<double>& by,
+                    std::vector<double>& bz);
+
+// Per-slot coefficient table [a][kMaxSlots][3] (FP64) for the kernels.
+bool coupling_slots(int N, std::vector<double>& tab);
+
+// Twiddles exp(-2 pi i t / n), t in [0, n), as interleaved (cos, sin) FP64.
+void twiddles(int n, std::vector<double>& tw);
+
+// Wavenumbers 2 pi f / (n dx) in FFT order with the Nyquist entry zero.
+void wavenumbers(int n, double dx, std::vector<double>& k);
+
+// Per-degree loss Sigma_l(r), [N+1][n^3], and the real-domain mask:
+// mu_a + mu_s (1 - g^l) inside [W, n-W)^3, mu_b (half-cosine layer) outside.
+void potentials(int n, int N, int W, double mu0, double mu1,
+                const double* mu_a, const double* mu_s, const double* g,
+                std::vector<double>& sig, std::vector<uint8_t>& inside);
+
+// Supported grid sizes for the in-LDS plane passes.
+bool grid_supported(int n);
+
+}  // namespace rte

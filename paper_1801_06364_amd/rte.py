@@ -1,0 +1,235 @@
+"""ctypes binding of librte.so (the C-ABI declared in include/rte.h).
+
+Argument marshalling only: every step of the transport solve runs in the
+HIP library. PyTorch supplies the device workspace and the HIP stream.
+The functions ``rte_*`` mirror the C entry points one to one; ``Solver``
+bundles a handle with the torch workspace that backs it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librte.so")
+
+RTE_OK, RTE_EINVAL, RTE_ENOMEM, RTE_EUNSTABLE, RTE_EDEVICE = 0, -1, -2, -3, -4
+RTE_FP32, RTE_FP64 = 0, 1
+RTE_FLUENCE_NOW, RTE_FLUENCE_INTEGRATED = 0, 1
+
+EXPORTS = (
+    "rte_workspace_bytes", "rte_create", "rte_step", "rte_run", "rte_fluence",
+    "rte_readings", "rte_residuals", "rte_steps_done", "rte_get_state",
+    "rte_set_state", "rte_coupling_dense", "rte_destroy", "rte_strerror",
+)
+
+
+class RteError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: {strerror(code)} ({code})")
+
+
+class rte_config(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32), ("order_N", C.c_int32), ("precision", C.c_int32),
+        ("pml_width", C.c_int32), ("dx_mm", C.c_double), ("c_mm_ps", C.c_double),
+        ("dt_ps", C.c_double), ("pml_mu0", C.c_double), ("pml_mu1", C.c_double),
+        ("n_det", C.c_int32), ("reserved0", C.c_int32),
+        ("det_index", C.POINTER(C.c_int64)), ("record_steps", C.c_int64),
+    ]
+
+
+class rte_medium(C.Structure):
+    _fields_ = [
+        ("mu_a", C.POINTER(C.c_double)), ("mu_s", C.POINTER(C.c_double)),
+        ("g", C.POINTER(C.c_double)), ("psi0", C.POINTER(C.c_double)),
+        ("q", C.POINTER(C.c_double)),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load librte.so; raise if it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with "
+                "`python -m paper_1801_06364_amd.build` (there is no CPU fallback)")
+        L = C.CDLL(LIB_PATH)
+        vp, i64p, dp = C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_double)
+        L.rte_workspace_bytes.argtypes = [C.POINTER(rte_config)]
+        L.rte_workspace_bytes.restype = C.c_size_t
+        L.rte_create.argtypes = [C.POINTER(rte_config), C.POINTER(rte_medium), vp,
+                                 C.c_size_t, vp, C.POINTER(vp)]
+        L.rte_create.restype = C.c_int
+        L.rte_step.argtypes = [vp, C.c_int64]
+        L.rte_step.restype = C.c_int
+        L.rte_run.argtypes = [vp, C.c_int64, C.c_double, i64p]
+        L.rte_run.restype = C.c_int
+        L.rte_fluence.argtypes = [vp, C.c_int, dp, C.c_size_t]
+        L.rte_fluence.restype = C.c_int
+        L.rte_readings.argtypes = [vp, dp, C.c_size_t, i64p]
+        L.rte_readings.restype = C.c_int
+        L.rte_residuals.argtypes = [vp, dp, C.c_size_t, i64p]
+        L.rte_residuals.restype = C.c_int
+        L.rte_steps_done.argtypes = [vp, i64p]
+        L.rte_steps_done.restype = C.c_int
+        L.rte_get_state.argtypes = [vp, dp, C.c_size_t]
+        L.rte_get_state.restype = C.c_int
+        L.rte_set_state.argtypes = [vp, dp, C.c_size_t]
+        L.rte_set_state.restype = C.c_int
+        L.rte_coupling_dense.argtypes = [C.c_int32, dp, dp, dp]
+        L.rte_coupling_dense.restype = C.c_int
+        L.rte_destroy.argtypes = [vp]
+        L.rte_destroy.restype = None
+        L.rte_strerror.argtypes = [C.c_int]
+        L.rte_strerror.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return lib().rte_strerror(code).decode()
+
+
+def _check(code: int, what: str):
+    if code != RTE_OK:
+        raise RteError(code, what)
+
+
+def _dptr(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def make_config(n, N, precision, dx, c, dt, W, mu0, mu1, det_index=None,
+                record_steps=0):
+    det = np.ascontiguousarray(det_index if det_index is not None else [], np.int64)
+    cfg = rte_config(n=n, order_N=N, precision=precision, pml_width=W, dx_mm=dx,
+                     c_mm_ps=c, dt_ps=dt, pml_mu0=mu0, pml_mu1=mu1,
+                     n_det=int(det.size), reserved0=0,
+                     det_index=det.ctypes.data_as(C.POINTER(C.c_int64)) if det.size else None,
+                     record_steps=int(record_steps))
+    return cfg, det
+
+
+# ---------------------------------------------------- raw entry points ---
+
+def rte_workspace_bytes(cfg: rte_config) -> int:
+    return int(lib().rte_workspace_bytes(C.byref(cfg)))
+
+
+def rte_coupling_dense(N: int):
+    M = (N + 1) ** 2
+    out = [np.zeros((M, M)) for _ in range(3)]
+    _check(lib().rte_coupling_dense(N, *[_dptr(o) for o in out]), "rte_coupling_dense")
+    return out
+
+
+class Solver:
+    """One device-resident solve behind an ``rte_handle``.
+
+    The torch tensor ``self.workspace`` owns the device memory; the handle
+    runs on ``self.stream`` (a torch stream, the current one by default).
+    """
+
+    def __init__(self, n, N, dx, c, dt, mu_a, mu_s, g, psi0=None, q=None, W=0,
+                 mu0=0.01, mu1=1.0, precision="f32", det_index=None,
+                 record_steps=0, stream=None, device="cuda"):
+        import torch
+        self.n, self.N, self.M = n, N, (N + 1) ** 2
+        prec = RTE_FP64 if precision in ("f64", RTE_FP64) else RTE_FP32
+        self.precision = prec
+        self.cfg, self._det = make_config(n, N, prec, dx, c, dt, W, mu0, mu1,
+                                          det_index, record_steps)
+        self.n_det = int(self._det.size)
+        nbytes = rte_workspace_bytes(self.cfg)
+        if nbytes == 0:
+            raise RteError(RTE_EINVAL, "rte_workspace_bytes")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        arrs = [_f64(mu_a), _f64(mu_s), _f64(g), _f64(psi0), _f64(q)]
+        med = rte_medium(*[_dptr(a) for a in arrs])
+        self._keep = arrs
+        h = C.c_void_p()
+        rc = lib().rte_create(C.byref(self.cfg), C.byref(med),
+                              C.c_void_p(self.workspace.data_ptr()), nbytes,
+                              C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        self._keep = None
+        _check(rc, "rte_create")
+        self.h = h
+
+    @classmethod
+    def from_workload(cls, wl, **kw):
+        args = dict(n=wl.n, N=wl.N, dx=wl.dx, c=wl.c, dt=wl.dt, mu_a=wl.mu_a,
+                    mu_s=wl.mu_s, g=wl.g, psi0=wl.psi0, q=wl.q, W=wl.W,
+                    mu0=wl.mu0, mu1=wl.mu1, precision=wl.precision,
+                    det_index=wl.det_index, record_steps=wl.steps)
+        args.update(kw)
+        return cls(**args)
+
+    # -- C-ABI wrappers ---------------------------------------------------
+    def step(self, k: int = 1):
+        _check(lib().rte_step(self.h, int(k)), "rte_step")
+
+    def run(self, max_steps: int, tol: float) -> int:
+        taken = C.c_int64(0)
+        rc = lib().rte_run(self.h, int(max_steps), float(tol), C.byref(taken))
+        _check(rc, "rte_run")
+        return int(taken.value)
+
+    def fluence(self, which: int = RTE_FLUENCE_NOW) -> np.ndarray:
+        out = np.zeros(self.n ** 3)
+        _check(lib().rte_fluence(self.h, which, _dptr(out), out.size), "rte_fluence")
+        return out.reshape(self.n, self.n, self.n)
+
+    def readings(self) -> np.ndarray:
+        cap = max(1, int(self.cfg.record_steps) * max(self.n_det, 1))
+        out = np.zeros(cap)
+        rows = C.c_int64(0)
+        _check(lib().rte_readings(self.h, _dptr(out), out.size, C.byref(rows)), "rte_readings")
+        return out[: rows.value * self.n_det].reshape(rows.value, self.n_det)
+
+    def residuals(self) -> np.ndarray:
+        out = np.zeros(max(1, int(self.cfg.record_steps)))
+        rows = C.c_int64(0)
+        _check(lib().rte_residuals(self.h, _dptr(out), out.size, C.byref(rows)), "rte_residuals")
+        return out[: rows.value].copy()
+
+    def steps_done(self) -> int:
+        s = C.c_int64(0)
+        _check(lib().rte_steps_done(self.h, C.byref(s)), "rte_steps_done")
+        return int(s.value)
+
+    def get_state(self) -> np.ndarray:
+        out = np.zeros(self.M * self.n ** 3)
+        _check(lib().rte_get_state(self.h, _dptr(out), out.size), "rte_get_state")
+        return out.reshape(self.M, self.n, self.n, self.n)
+
+    def set_state(self, psi: np.ndarray):
+        a = _f64(psi).ravel()
+        _check(lib().rte_set_state(self.h, _dptr(a), a.size), "rte_set_state")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.stream.synchronize()
+            lib().rte_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

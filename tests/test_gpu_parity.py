@@ -1,0 +1,230 @@
+"""GPU parity: the HIP stepper (through the C-ABI) against the FP64 oracle.
+
+Bars: relative L2 <= 1e-12 for the FP64 GPU path and <= 1e-5 for FP32, on
+the same seeded inputs. Sizes span several LDS tiles and both FFT radix
+families (powers of two and the radix-3 grids).
+"""
+import functools
+import os
+
+import numpy as np
+import pytest
+
+import rte_inputs as ri
+from oracle import pn
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+def rel(a, b):
+    a = np.asarray(a, float).ravel()
+    b = np.asarray(b, float).ravel()
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _solver(wl, **kw):
+    from paper_1801_06364_amd.rte import Solver
+    return Solver.from_workload(wl, **kw)
+
+
+@functools.lru_cache(maxsize=16)
+def _oracle(name, n, steps):
+    wl = ri.workload(name, n=n, steps=steps)
+    return pn.solve(wl.n, wl.N, wl.dx, wl.c, wl.dt, wl.mu_a, wl.mu_s, wl.g, wl.psi0,
+                    wl.q, wl.W, wl.mu0, wl.mu1, wl.steps, det_index=wl.det_index)
+
+
+CASES = [
+    # (workload recipe, n, steps)
+    ("p1_gauss", 32, 100),      # the full P_1 / 32^3 / 100-step workload
+    ("p7_spheres", 32, 12),     # P_7 inclusions + detectors, reduced grid
+    ("p3_adjoint", 48, 10),     # P_3, radix-3 grid
+    ("p5_steady", 32, 20),      # P_5 with the collimated slab source
+    ("p7_spheres", 16, 8),      # smallest grid
+    ("p3_adjoint", 96, 3),      # radix-3, larger
+]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("name,n,steps", CASES)
+def test_parity_against_oracle(torch_cuda, name, n, steps, prec):
+    print(f"\n[parity] {name} n={n} steps={steps} {prec}", flush=True)
+    wl = ri.workload(name, n=n, steps=steps, precision=prec)
+    ref = _oracle(name, n, steps)
+    s = _solver(wl)
+    s.step(steps)
+    tol = TOL[prec]
+    assert s.steps_done() == steps
+    st = s.get_state()
+    assert rel(s.fluence(), ref["fluence"]) <= tol
+    assert rel(st, ref["state"]) <= tol
+    for a in range(st.shape[0]):
+        if np.linalg.norm(ref["state"][a]) > 1e-3 * np.linalg.norm(ref["state"][0]):
+            assert rel(st[a], ref["state"][a]) <= 10 * tol, a
+    assert rel(s.fluence(1), ref["phi_int"]) <= tol
+    if wl.det_index.size:
+        assert rel(s.readings(), ref["readings"]) <= tol
+    res = s.residuals()
+    assert res.shape == (steps,)
+    assert np.allclose(res, ref["residual"], rtol=1e-3 if prec == "f32" else 1e-9, atol=1e-7)
+    s.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_single_fourier_mode_full_size(torch_cuda, prec):
+    """Homogeneous periodic medium at the full 128^3 / P_7 size: a single
+    Fourier mode evolves as R(dt M(k))^n (oracle's mode algebra, FP64),
+    compared element by element over the whole grid."""
+    n, N, dx, c = 128, 7, 0.25, 0.3
+    M = (N + 1) ** 2
+    steps = 5
+    dt = 0.2 * dx / c
+    rng = np.random.default_rng(42)
+    v = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+    f = (3, -5, 17)
+    mua, mus, g = 0.01, 10.0, 0.9
+    ma, ms, gg = ri.homogeneous_maps(n, mua, mus, g)
+    psi0 = ri.fourier_mode_ic(n, N, f, v)
+    sig = [mua + mus * (1 - g ** l) for l in range(N + 1)]
+    k = pn.wavenumbers(n, dx)
+    kv = (k[f[0]], k[f[1]], k[f[2]])
+    U = pn.real_basis_transform(N)
+    Rk = np.linalg.matrix_power(pn.rk4_poly(dt * pn.mode_matrix(N, kv, sig, c)), steps)
+    Rmk = np.linalg.matrix_power(pn.rk4_poly(dt * pn.mode_matrix(N, tuple(-t for t in kv), sig, c)), steps)
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    ph = np.exp(2j * np.pi * (f[0] * x + f[1] * y + f[2] * z) / n)
+    del z, y, x
+    ac = Rk @ (U.T @ v)
+    acm = Rmk @ (U.T @ v.conj())
+    aR = (U.conj() @ ac)          # real-basis coefficient of e^{ik.r}
+    aRm = (U.conj() @ acm)        # of e^{-ik.r}
+    s = _solver(ri.Workload("mode", n, N, prec, dx, c, dt, 0, 0.01, 1.0, steps, ma, ms, gg,
+                            psi0, None))
+    del psi0
+    s.step(steps)
+    st = s.get_state()
+    err2 = 0.0
+    ref2 = 0.0
+    for a in range(M):
+        ref = (0.5 * (aR[a] * ph + aRm[a] * ph.conj())).real
+        err2 += float(((st[a] - ref) ** 2).sum())
+        ref2 += float((ref ** 2).sum())
+    assert np.sqrt(err2 / ref2) <= TOL[prec]
+    s.close()
+
+
+def test_photon_number_conserved_on_gpu(torch_cuda):
+    """mu_a = 0, no absorbing layer: sum of psi_0^0 is invariant (FP64)."""
+    n, N = 64, 3
+    rng = np.random.default_rng(9)
+    mus = rng.uniform(1, 10, (n, n, n))
+    g = rng.uniform(0.5, 0.95, (n, n, n))
+    psi0 = ri.gaussian_ic(n, N, sigma=2.0)
+    wl = ri.Workload("cons", n, N, "f64", 0.25, 0.3, 0.2 * 0.25 / 0.3, 0, 0.01, 1.0, 50,
+                     np.zeros((n, n, n)), mus, g, psi0, None)
+    s = _solver(wl)
+    s.step(50)
+    tot = s.fluence().sum()
+    assert abs(tot - psi0[0].sum()) <= 1e-12 * psi0[0].sum()
+    s.close()
+
+
+def test_k0_decay_on_gpu(torch_cuda):
+    """Uniform state, homogeneous medium: every degree decays by the scalar
+    RK4 factor per step (closed form)."""
+    n, N = 16, 5
+    mua, mus, g = 0.05, 4.0, 0.7
+    dx, c = 0.5, 0.3
+    dt = 0.2 * dx / c
+    ma, ms, gg = ri.homogeneous_maps(n, mua, mus, g)
+    psi0 = np.ones(((N + 1) ** 2, n, n, n))
+    s = _solver(ri.Workload("k0", n, N, "f64", dx, c, dt, 0, 0.01, 1.0, 30, ma, ms, gg, psi0, None))
+    s.step(30)
+    st = s.get_state()
+    for l in range(N + 1):
+        zz = -c * dt * (mua + mus * (1 - g ** l))
+        R = 1 + zz + zz * zz / 2 + zz ** 3 / 6 + zz ** 4 / 24
+        for m in range(-l, l + 1):
+            assert np.allclose(st[l * l + l + m], R ** 30, rtol=1e-13)
+    s.close()
+
+
+def test_zeroth_order_and_zero_state(torch_cuda):
+    """Degenerate cases: N = 0 (no streaming coupling: pure local decay)
+    and an all-zero state with no source stays exactly zero."""
+    n = 32
+    wl = ri.workload("p1_gauss", n=n, steps=5)
+    wl.N = 0
+    wl.psi0 = wl.psi0[:1]
+    ref = pn.solve(n, 0, wl.dx, wl.c, wl.dt, wl.mu_a, wl.mu_s, wl.g, wl.psi0, None, wl.W,
+                   wl.mu0, wl.mu1, 5)
+    s = _solver(wl)
+    s.step(5)
+    assert rel(s.get_state(), ref["state"]) <= 1e-12
+    s.close()
+    wl = ri.workload("p1_gauss", n=n, steps=5)
+    s = _solver(wl, psi0=None)
+    s.step(5)
+    assert np.all(s.get_state() == 0.0)
+    s.close()
+
+
+def test_graph_and_direct_launch_bitwise_equal(torch_cuda):
+    """The captured-graph replay and plain launches run the same kernels in
+    the same order: results are bitwise identical, and so are two runs."""
+    wl = ri.workload("p7_spheres", n=32, steps=4, precision="f32")
+    outs = []
+    for env in ("0", "1", "0"):
+        os.environ["RTE_NO_GRAPH"] = env
+        s = _solver(wl, stream=torch_cuda.cuda.Stream())
+        s.step(4)
+        outs.append(s.get_state())
+        s.close()
+    os.environ.pop("RTE_NO_GRAPH", None)
+    assert np.array_equal(outs[0], outs[1])
+    assert np.array_equal(outs[0], outs[2])
+
+
+def test_steady_state_run_stops_at_tolerance(torch_cuda):
+    """rte_run stops at the first step whose relative fluence change is
+    below tol; the oracle's residual sequence crosses tol at that step."""
+    wl = ri.workload("p5_steady", n=16, steps=0, precision="f64")
+    s = _solver(wl, record_steps=4000)
+    taken = s.run(4000, 1e-4)
+    res = s.residuals()
+    assert taken == res.size
+    assert res[-1] < 1e-4 and np.all(res[:-1] >= 1e-4)
+    ref = pn.solve(wl.n, wl.N, wl.dx, wl.c, wl.dt, wl.mu_a, wl.mu_s, wl.g, None, wl.q, wl.W,
+                   wl.mu0, wl.mu1, taken)
+    assert rel(s.fluence(), ref["fluence"]) <= 1e-12
+    assert np.allclose(res, ref["residual"], rtol=1e-8, atol=1e-14)
+    s.close()
+
+
+def test_error_paths(torch_cuda):
+    """Invalid input and an over-CFL step are reported, not executed."""
+    from paper_1801_06364_amd import rte
+    wl = ri.workload("p1_gauss", n=16, steps=1)
+    with pytest.raises(rte.RteError) as e:
+        _solver(wl, det_index=np.array([16 ** 3], np.int64))
+    assert e.value.code == rte.RTE_EINVAL
+    bad = wl.mu_a.copy()
+    bad[0, 0, 0] = np.nan
+    with pytest.raises(rte.RteError):
+        _solver(wl, mu_a=bad)
+    s = _solver(wl, dt=40 * wl.dt, record_steps=2000)
+    with pytest.raises(rte.RteError) as e:
+        s.run(2000, 1e-9)
+    assert e.value.code == rte.RTE_EUNSTABLE
+    s.close()
