@@ -1,0 +1,199 @@
+#!/usr/bin/env python3
+"""Benchmark: RK4 steps of the P_7 / 128^3 / FP32 inclusion workload.
+
+One "step" is one full RK4 step (four stages, each: forward plane FFT pass,
+z-pass with the streaming coupling, inverse plane pass with the fused
+pointwise epilogue, plus the per-step readings/residual kernel) over the
+whole device-resident state. The metric counts voxel x harmonic x RK-stage
+updates per second. Prints one JSON line.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+                       [--workload p7_spheres] [--no-cpu-baseline]
+                       [--copy-probe]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, 8 TB/s
+METRIC = "voxel·harmonic RK-stage updates/s"
+
+DESCR = {
+    "p7_spheres": "P_7 (64 real moments), 128^3 grid, dx=0.25 mm, 16-voxel half-cosine "
+                  "absorbing layer, background mu_a=0.01 mu_s=10 g=0.9 with 5 seeded "
+                  "spherical inclusions, isotropic point pulse, 32 detectors, "
+                  "RK4 dt=0.2 dx/c (c=0.3 mm/ps)",
+    "p5_steady": "P_5 (36 moments), 256^3 log-normal medium, collimated slab source",
+    "p3_adjoint": "P_3 (16 moments), 96^3 inclusion phantom, Gaussian pulse",
+    "p1_gauss": "P_1 (4 moments), 32^3 homogeneous, Gaussian pulse",
+}
+
+
+def source_sha() -> str:
+    h = hashlib.sha256()
+    cs = os.path.join(ROOT, "paper_1801_06364_amd", "csrc")
+    for f in sorted(os.listdir(cs)):
+        with open(os.path.join(cs, f), "rb") as fh:
+            h.update(f.encode())
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def algorithmic_bytes(kind: str, n: int, M: int, N: int, s: int) -> float:
+    """Compulsory HBM bytes of one launch of each kernel class.
+
+    fwd_plane: read the stage input (M n^3 reals), write the half spectrum
+    (M n^2 (n/2+1) complex). zpass: read and write the half spectrum.
+    inv_plane: read the half spectrum, the stage input, u and the per-degree
+    loss maps ((N+1) n^3), write the stage output (stages 2-4; the first
+    stage reads u once, counted as the general case here).
+    """
+    V = n ** 3
+    spec = M * n * n * (n // 2 + 1) * 2 * s
+    if kind == "fwd_plane":
+        return M * V * s + spec
+    if kind == "zpass":
+        return 2 * spec
+    if kind == "inv_plane":
+        return spec + 3 * M * V * s + (N + 1) * V * s
+    return 0.0
+
+
+def cpu_baseline(wl, workers: int):
+    """Time the FP64 oracle on a bounded sample: one RK stage (one full
+    operator evaluation plus the stage update) of the same workload."""
+    import numpy as np
+    from oracle import pn
+    pn.WORKERS = workers
+    B = pn.coupling_matrices(wl.N)
+    U = pn.real_basis_transform(wl.N)
+    k = pn.wavenumbers(wl.n, wl.dx)
+    Sig, _ = pn.potentials(wl.mu_a, wl.mu_s, wl.g, wl.N, wl.W, wl.mu0, wl.mu1)
+    psi = pn.to_complex_basis(wl.psi0, U).astype(complex)
+    t0 = time.perf_counter()
+    f = pn.operator(psi, Sig, None, B, k, wl.c, workers)
+    psi = psi + (0.5 * wl.dt) * f
+    el = time.perf_counter() - t0
+    del f, psi
+    upd = wl.n ** 3 * wl.M
+    return {"value": upd / el, "unit": "updates/s", "cores": workers, "kind": "oracle",
+            "sample": f"one RK stage (operator + stage update) of the full {wl.n}^3 P_{wl.N} "
+                      f"workload in FP64, complex SH basis; {upd} updates in {el:.1f} s; "
+                      f"scipy.fft workers={workers}, NumPy elementwise single-threaded"}
+
+
+def traffic_for(kind: str, workload: str):
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    rec = t.get(workload, {}).get(kind)
+    if not rec or t.get("source_sha") != source_sha():
+        return None
+    return rec["bytes_per_launch"]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="p7_spheres")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--profile-steps", type=int, default=5)
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the hot path is a single-GPU solve; "
+              "multi-GPU runs are not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import rte_inputs as ri
+    from paper_1801_06364_amd.rte import Solver
+
+    wl = ri.workload(a.workload, steps=a.steps + a.warmup)
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    s = Solver.from_workload(wl, stream=stream)
+    print(f"[bench] {a.workload} n={wl.n} N={wl.N} {wl.precision} created", file=sys.stderr,
+          flush=True)
+    s.step(a.warmup)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    s.step(a.steps)
+    ev1.record(stream)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1)
+    done = s.steps_done()
+    assert done == a.steps + a.warmup, (done, a.steps + a.warmup)
+    fl = s.fluence()
+    assert np.all(np.isfinite(fl))
+    print(f"[bench] timed {a.steps} steps: {ms:.2f} ms (wall {wall:.3f} s)", file=sys.stderr,
+          flush=True)
+
+    upd_step = wl.n ** 3 * wl.M * 4
+    value = upd_step * a.steps / (ms / 1e3)
+    sbytes = 8 if wl.precision == "f64" else 4
+
+    prof = s.profile_kernels(a.profile_steps)
+    per = {k: (t / c if c else 0.0) for k, (t, c) in prof.items()}
+    dom = max(("fwd_plane", "zpass", "inv_plane"), key=lambda k: prof[k][0])
+    alg = algorithmic_bytes(dom, wl.n, wl.M, wl.N, sbytes)
+    achieved = alg / (per[dom] / 1e3) / 1e9
+    tb = traffic_for(dom, a.workload)
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                "traffic": tb, "algorithmic_bytes": alg,
+                "avg_launch_ms": per[dom]}
+    s.close()
+
+    if a.copy_probe:
+        x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        x.fill_(1.0)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print("[bench] copy probe: 3 x 1 GiB device copy done", file=sys.stderr, flush=True)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "updates/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms / a.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": wl.precision, "data": "synthetic",
+        "config": {"workload": f"{a.workload}: {DESCR.get(a.workload, '')}", "n": wl.n,
+                   "order_N": wl.N, "moments": wl.M, "precision": wl.precision,
+                   "updates_per_step": upd_step, "parallelism": "single GPU"},
+        "kernel_ms_per_launch": per,
+        "roofline": roofline,
+    }
+    if not a.no_cpu_baseline:
+        workers = int(os.environ.get("OMP_NUM_THREADS", "0")) or min(16, os.cpu_count() or 1)
+        wlc = ri.workload(a.workload, steps=1)
+        out["cpu_baseline"] = cpu_baseline(wlc, workers)
+        print(f"[bench] cpu baseline: {out['cpu_baseline']['value']:.3e} updates/s",
+              file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -296,7 +296,8 @@ def solve(n, N, dx, c, dt, mu_a, mu_s, g, psi0_real, q_real, W, mu0, mu1,
     Returns a dict with ``fluence`` (psi_0^0 after the last step),
     ``readings`` ``[steps][n_det]`` (psi_0^0 at the detector voxels after
     every step), ``phi_int`` (sum over steps of ``dt * psi_0^0``),
-    ``residual`` ``[steps]`` (``||phi_n - phi_{n-1}|| / ||phi_n||``) and,
+    ``residual`` ``[steps]`` (``||phi_n - phi_{n-1}|| / ||phi_n||``),
+    ``peak`` ``[steps]`` (max |psi_0^0| over the grid after every step) and,
     if asked, ``state`` (real-basis moments after the last step)."""
     M = (N + 1) ** 2
     B = coupling_matrices(N)
@@ -313,6 +314,7 @@ def solve(n, N, dx, c, dt, mu_a, mu_s, g, psi0_real, q_real, W, mu0, mu1,
     det = np.asarray(det_index, dtype=np.int64)
     readings = np.zeros((steps, det.size))
     residual = np.zeros(steps)
+    peak = np.zeros(steps)
     phi_int = np.zeros((n, n, n))
     prev = psi[0].real.copy()
 
@@ -323,12 +325,13 @@ def solve(n, N, dx, c, dt, mu_a, mu_s, g, psi0_real, q_real, W, mu0, mu1,
         psi = rk4_step(psi, f, dt)
         phi = psi[0].real
         readings[s] = phi.ravel()[det]
+        peak[s] = np.abs(phi).max()
         phi_int += dt * phi
         nrm = np.linalg.norm(phi)
         residual[s] = np.linalg.norm(phi - prev) / nrm if nrm > 0 else 0.0
         prev = phi.copy()
     out = dict(fluence=psi[0].real.copy(), readings=readings,
-               phi_int=phi_int, residual=residual)
+               phi_int=phi_int, residual=residual, peak=peak)
     if return_state:
         out["state"] = to_real_basis(psi, U)
     return out

@@ -412,7 +412,7 @@ hipError_t set_lds_limits(rte_handle* h) {
 }
 
 template <typename T, int E, int N>
-hipError_t enqueue_step_t(rte_handle* h) {
+hipError_t enqueue_step_t(rte_handle* h, hipEvent_t* ev) {
   using V = typename cplx_of<T>::type;
   const Geo& g = h->geo;
   const Layout& L = h->lay;
@@ -434,13 +434,20 @@ hipError_t enqueue_step_t(rte_handle* h) {
   const dim3 blk(256);
   const int planes = g.M * g.n;
   const int zblocks = g.n * g.ntile;
+  int mark = 0;
+  auto rec = [&]() {
+    if (ev) (void)hipEventRecord(ev[mark++], h->stream);
+  };
+  rec();
   for (int s = 0; s < 4; ++s) {
     const double hs = alphas[s] * dt * c;
     const T* src = s == 0 ? u : v;
     hipLaunchKernelGGL((k_fwd_plane<T, E>), dim3(planes), blk, h->lds_plane, h->stream, src, spec, tw,
                        g, ctl);
+    rec();
     hipLaunchKernelGGL((k_zpass<T, E, N>), dim3(zblocks), blk, h->lds_z, h->stream, spec, tw, kv, coef,
                        g, T(hs / n3), ctl);
+    rec();
     if (s == 0)
       hipLaunchKernelGGL((k_inv_plane<T, E, true, false>), dim3(planes), blk, h->lds_plane, h->stream,
                          spec, src, u, v, sig, q, qflag, phi, partial, tw, g, T(hs), dt, ctl);
@@ -450,10 +457,12 @@ hipError_t enqueue_step_t(rte_handle* h) {
     else
       hipLaunchKernelGGL((k_inv_plane<T, E, false, true>), dim3(planes), blk, h->lds_plane, h->stream,
                          spec, src, u, u, sig, q, qflag, phi, partial, tw, g, T(hs), dt, ctl);
+    rec();
   }
   hipLaunchKernelGGL((k_end_step<T>), dim3(1), blk, 0, h->stream, u, h->at<long long>(L.det),
                      h->cfg.n_det, h->at<double>(L.readings), h->at<double>(L.resid),
                      (long long)h->cfg.record_steps, partial, g.n, ctl);
+  rec();
   return hipGetLastError();
 }
 
@@ -482,7 +491,11 @@ hipError_t dispatch(rte_handle* h) {
 }
 
 template <typename T, int E, int N> struct StepFn {
-  static hipError_t call(rte_handle* h) { return enqueue_step_t<T, E, N>(h); }
+  static hipError_t call(rte_handle* h) { return enqueue_step_t<T, E, N>(h, nullptr); }
+};
+thread_local hipEvent_t* g_prof_events = nullptr;
+template <typename T, int E, int N> struct ProfStepFn {
+  static hipError_t call(rte_handle* h) { return enqueue_step_t<T, E, N>(h, g_prof_events); }
 };
 template <typename T, int E, int N> struct LdsFn {
   static hipError_t call(rte_handle* h) { return set_lds_limits<T, E, N>(h); }
@@ -821,6 +834,42 @@ int rte_coupling_dense(int32_t order_N, double* bx, double* by, double* bz) {
   std::memcpy(by, Y.data(), Y.size() * 8);
   std::memcpy(bz, Z.data(), Z.size() * 8);
   return RTE_OK;
+}
+
+int rte_profile_kernels(rte_handle* h, int64_t nsteps, double* ms, int64_t* counts) {
+  using namespace rte;
+  if (!h || !ms || !counts || nsteps < 0) return RTE_EINVAL;
+  constexpr int kLaunches = 13;
+  hipEvent_t ev[kLaunches + 1];
+  for (int i = 0; i <= kLaunches; ++i)
+    if (hipEventCreate(&ev[i]) != hipSuccess) return RTE_EDEVICE;
+  for (int c = 0; c < 4; ++c) {
+    ms[c] = 0.0;
+    counts[c] = 0;
+  }
+  int rc = RTE_OK;
+  for (int64_t s = 0; s < nsteps && rc == RTE_OK; ++s) {
+    g_prof_events = ev;
+    hipError_t e = dispatch<ProfStepFn>(h);
+    g_prof_events = nullptr;
+    if (e == hipSuccess) e = hipEventSynchronize(ev[kLaunches]);
+    if (e != hipSuccess) {
+      rc = RTE_EDEVICE;
+      break;
+    }
+    for (int i = 0; i < kLaunches; ++i) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, ev[i], ev[i + 1]) != hipSuccess) {
+        rc = RTE_EDEVICE;
+        break;
+      }
+      const int cls = i == kLaunches - 1 ? 3 : i % 3;
+      ms[cls] += t;
+      counts[cls] += 1;
+    }
+  }
+  for (int i = 0; i <= kLaunches; ++i) (void)hipEventDestroy(ev[i]);
+  return rc;
 }
 
 void rte_destroy(rte_handle* h) {

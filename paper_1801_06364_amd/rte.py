@@ -23,8 +23,10 @@ RTE_FLUENCE_NOW, RTE_FLUENCE_INTEGRATED = 0, 1
 EXPORTS = (
     "rte_workspace_bytes", "rte_create", "rte_step", "rte_run", "rte_fluence",
     "rte_readings", "rte_residuals", "rte_steps_done", "rte_get_state",
-    "rte_set_state", "rte_coupling_dense", "rte_destroy", "rte_strerror",
+    "rte_set_state", "rte_coupling_dense", "rte_profile_kernels", "rte_destroy",
+    "rte_strerror",
 )
+KERNEL_CLASSES = ("fwd_plane", "zpass", "inv_plane", "end_step")
 
 
 class RteError(RuntimeError):
@@ -87,6 +89,8 @@ def lib():
         L.rte_set_state.restype = C.c_int
         L.rte_coupling_dense.argtypes = [C.c_int32, dp, dp, dp]
         L.rte_coupling_dense.restype = C.c_int
+        L.rte_profile_kernels.argtypes = [vp, C.c_int64, dp, i64p]
+        L.rte_profile_kernels.restype = C.c_int
         L.rte_destroy.argtypes = [vp]
         L.rte_destroy.restype = None
         L.rte_strerror.argtypes = [C.c_int]
@@ -221,6 +225,16 @@ class Solver:
     def set_state(self, psi: np.ndarray):
         a = _f64(psi).ravel()
         _check(lib().rte_set_state(self.h, _dptr(a), a.size), "rte_set_state")
+
+    def profile_kernels(self, nsteps: int):
+        """Per-kernel-class milliseconds (summed) and launch counts over
+        ``nsteps`` steps timed with HIP events on the handle's stream."""
+        ms = np.zeros(4)
+        cnt = np.zeros(4, np.int64)
+        _check(lib().rte_profile_kernels(self.h, int(nsteps), _dptr(ms),
+                                         cnt.ctypes.data_as(C.POINTER(C.c_int64))),
+               "rte_profile_kernels")
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNEL_CLASSES)}
 
     def close(self):
         if getattr(self, "h", None):

@@ -74,7 +74,11 @@ def test_parity_against_oracle(torch_cuda, name, n, steps, prec):
             assert rel(st[a], ref["state"][a]) <= 10 * tol, a
     assert rel(s.fluence(1), ref["phi_int"]) <= tol
     if wl.det_index.size:
-        assert rel(s.readings(), ref["readings"]) <= tol
+        # a reading is one voxel of a field whose rounding error is set by the
+        # whole field (the spectral operator couples every voxel), so the
+        # bound is tol times the field's peak at that step
+        err = np.abs(s.readings() - ref["readings"])
+        assert np.all(err <= tol * ref["peak"][:, None]), err.max()
     res = s.residuals()
     assert res.shape == (steps,)
     assert np.allclose(res, ref["residual"], rtol=1e-3 if prec == "f32" else 1e-9, atol=1e-7)
