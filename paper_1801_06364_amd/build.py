@@ -15,7 +15,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librte.so")
 
-SOURCES = ["rte_lib.hip", "rte_tables.cpp"]
+SOURCES = ["rte_lib.hip", "rte_tables.cpp"] + [
+    f"rte_n{n}.hip" for n in (16, 32, 48, 64, 96, 128)]
+BUILD_DIR = os.path.join(HERE, "_build")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -24,7 +26,6 @@ FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     # packed FP32 instructions are kept out of the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",
@@ -33,17 +34,34 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP/C++ source of the library into librte.so."""
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Compile every HIP/C++ source of the library (in parallel, one object
+    per translation unit) and link librte.so."""
+    from concurrent.futures import ThreadPoolExecutor
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    jobs = jobs or min(8, os.cpu_count() or 1)
+
+    def compile_one(src):
+        obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
+        cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        return src, obj, res
+
+    with ThreadPoolExecutor(jobs) as ex:
+        results = list(ex.map(compile_one, SOURCES))
+    bad = [(src, r) for src, _, r in results if r.returncode != 0]
+    for src, r in bad:
+        sys.stderr.write(f"--- {src}\n" + r.stdout + r.stderr)
+    if bad:
+        raise RuntimeError("hipcc failed building librte.so")
     tmp = LIB + ".tmp"
-    cmd = [HIPCC] + FLAGS + srcs + ["-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC"] + [o for _, o, _ in results] + ["-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building librte.so")
+        raise RuntimeError("hipcc failed linking librte.so")
     os.replace(tmp, LIB)
     return LIB
 

@@ -1,17 +1,17 @@
 // Device building blocks for the P_N stepper on gfx950: complex helpers,
-// radix-2/3/4/8 butterflies and a Stockham auto-sort FFT executed by a
-// group of P lanes of one wavefront on data staged in LDS.
+// radix-2/3/4/8 butterflies and a Stockham auto-sort FFT of compile-time
+// length executed by a group of P lanes of one wavefront on data staged in
+// LDS.
 //
 // An FFT of length L is owned by P = L / E lanes of ONE 64-lane wavefront;
 // each lane holds E elements in registers per stage (E = 8 for powers of
-// two, 24 when L has a factor 3). Because every stage only exchanges data
-// among lanes of the same wavefront, stages synchronise with a wavefront
-// barrier instead of a workgroup barrier.
+// two, 24 when L has a factor 3). Every stage only exchanges data among
+// lanes of the same wavefront, so stages synchronise with a wavefront
+// barrier instead of a workgroup barrier. Lengths, radices, strides and
+// twiddle spans are template constants, so all index arithmetic folds.
 #pragma once
 
 #include <hip/hip_runtime.h>
-
-#include <type_traits>
 
 namespace rte {
 
@@ -44,6 +44,33 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
+
+// ------------------------------------------------------------ plans ----
+// Radix sequence for length L = 2^a 3^b (b <= 1): a radix-3 stage first,
+// then radix-8 stages, then one radix-4 or radix-2 stage for the rest.
+constexpr int plan_count(int L) {
+  int c = 0, m = L;
+  if (m % 3 == 0) { ++c; m /= 3; }
+  while (m % 8 == 0) { ++c; m /= 8; }
+  if (m == 4 || m == 2) ++c;
+  return c;
+}
+constexpr int plan_radix(int L, int st) {
+  int m = L, s = 0;
+  if (m % 3 == 0) { if (s == st) return 3; ++s; m /= 3; }
+  while (m % 8 == 0) { if (s == st) return 8; ++s; m /= 8; }
+  if (m == 4) return 4;
+  if (m == 2) return 2;
+  return 0;
+}
+constexpr bool plan_ok(int L) {
+  int m = L;
+  if (m % 3 == 0) m /= 3;
+  while (m % 8 == 0) m /= 8;
+  return m == 1 || m == 2 || m == 4;
+}
+// Elements per lane: must be a multiple of every radix of the plan.
+constexpr int elems_per_lane(int L) { return (L % 3 == 0) ? 24 : (L >= 8 ? 8 : L); }
 
 // In-register DFT of size R: v[q] <- sum_r v[r] exp(DIR 2 pi i q r / R).
 template <typename V, int R, int DIR> struct Bfly;
@@ -111,85 +138,75 @@ template <typename V, int DIR> struct Bfly<V, 8, DIR> {
 };
 
 // One Stockham stage of radix R on an FFT of length L stored at
-// buf[i * stride]. Lane p (of P) performs butterflies j = p + i P,
-// i < E / R. tw holds exp(-2 pi i t / ntab), t < ntab, and twmul = ntab / L.
-template <typename V, int E, int R, int DIR>
-__device__ __forceinline__ void fft_stage(V* buf, int stride, int L, int P, int p,
-                                          int Ns, const V* tw, int twmul, bool act) {
+// buf[i * S]. Lane p (of P = L/E) performs butterflies j = p + i P,
+// i < E / R, after the previous stages have combined spans of NS.
+// tw holds exp(-2 pi i t / NTAB), t < NTAB.
+template <typename V, int L, int R, int NS, int S, int NTAB, int DIR>
+__device__ __forceinline__ void fft_stage(V* buf, int p, const V* tw, bool act) {
+  constexpr int E = elems_per_lane(L);
+  constexpr int P = L / E;
   constexpr int NB = E / R;
+  constexpr int LR = L / R;
+  constexpr int SPAN = (NTAB / (NS * R));
+  static_assert(E % R == 0, "radix must divide elements per lane");
   V v[NB][R];
-  const int LR = L / R;
   if (act) {
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
       const int j = p + i * P;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[i][r] = buf[(j + r * LR) * stride];
+      for (int r = 0; r < R; ++r) v[i][r] = buf[(j + r * LR) * S];
     }
   }
   wave_sync();
   if (act) {
-    const int span = (L / (Ns * R)) * twmul;
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
       const int j = p + i * P;
-      const int k = j % Ns;
-      if (Ns > 1) {
+      const int k = j % NS;
+      if constexpr (NS > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          V w = tw[r * k * span];
+          V w = tw[r * k * SPAN];
           if constexpr (DIR > 0) w.y = -w.y;
           v[i][r] = cmul(v[i][r], w);
         }
       }
       Bfly<V, R, DIR>::run(v[i]);
-      const int o = (j / Ns) * Ns * R + k;
+      const int o = (j / NS) * NS * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[(o + r * Ns) * stride] = v[i][r];
+      for (int r = 0; r < R; ++r) buf[(o + r * NS) * S] = v[i][r];
     }
   }
   wave_sync();
 }
 
-// Full FFT: plan holds the radices, 4 bits each, first stage lowest.
-template <typename V, int E, int DIR>
-__device__ __forceinline__ void fft_lds(V* buf, int stride, int L, int P, int p,
-                                        unsigned plan, const V* tw, int twmul, bool act) {
-  int Ns = 1;
-#pragma unroll 1
-  for (int st = 0; st < 6; ++st) {
-    const int R = (plan >> (4 * st)) & 15;
-    if (R == 0) break;
-    if (R == 8) {
-      if constexpr (E % 8 == 0) fft_stage<V, E, 8, DIR>(buf, stride, L, P, p, Ns, tw, twmul, act);
-    } else if (R == 4) {
-      if constexpr (E % 4 == 0) fft_stage<V, E, 4, DIR>(buf, stride, L, P, p, Ns, tw, twmul, act);
-    } else if (R == 2) {
-      if constexpr (E % 2 == 0) fft_stage<V, E, 2, DIR>(buf, stride, L, P, p, Ns, tw, twmul, act);
-    } else if (R == 3) {
-      if constexpr (E % 3 == 0) fft_stage<V, E, 3, DIR>(buf, stride, L, P, p, Ns, tw, twmul, act);
-    }
-    Ns *= R;
+template <typename V, int L, int S, int NTAB, int DIR, int ST = 0, int NS = 1>
+__device__ __forceinline__ void fft_stages(V* buf, int p, const V* tw, bool act) {
+  if constexpr (ST < plan_count(L)) {
+    constexpr int R = plan_radix(L, ST);
+    fft_stage<V, L, R, NS, S, NTAB, DIR>(buf, p, tw, act);
+    fft_stages<V, L, S, NTAB, DIR, ST + 1, NS * R>(buf, p, tw, act);
   }
 }
 
-// Run `count` FFTs (index f, base pointer base_of(f)) with every wavefront
-// of the workgroup holding 64 / P of them at a time.
-template <typename V, int E, int DIR, typename BaseOf>
-__device__ __forceinline__ void fft_batch(int count, int stride, int L, unsigned plan,
-                                          const V* tw, int twmul, BaseOf base_of) {
-  const int P = L / E;
+// Run COUNT FFTs of length L (element stride S, FFT f based at base_of(f))
+// with every wavefront of the workgroup holding 64 / P of them at a time.
+template <typename V, int L, int S, int NTAB, int DIR, int COUNT, typename BaseOf>
+__device__ __forceinline__ void fft_batch(const V* tw, BaseOf base_of) {
+  static_assert(plan_ok(L), "unsupported FFT length");
+  constexpr int P = L / elems_per_lane(L);
+  static_assert(64 % P == 0, "an FFT must fit one wavefront");
+  constexpr int PER_WAVE = 64 / P;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int per_wave = 64 / P;
-  const int per_round = (blockDim.x >> 6) * per_wave;
+  const int per_round = (blockDim.x >> 6) * PER_WAVE;
   const int g = lane / P;
   const int p = lane - g * P;
-  for (int f0 = 0; f0 < count; f0 += per_round) {
-    const int f = f0 + wave * per_wave + g;
-    const bool act = (g < per_wave) && (f < count);
-    V* base = base_of(act ? f : 0);
-    fft_lds<V, E, DIR>(base, stride, L, P, p, plan, tw, twmul, act);
+  for (int f0 = 0; f0 < COUNT; f0 += per_round) {
+    const int f = f0 + wave * PER_WAVE + g;
+    const bool act = f < COUNT;
+    fft_stages<V, L, S, NTAB, DIR>(base_of(act ? f : 0), p, tw, act);
   }
 }
 

@@ -72,4 +72,51 @@ void potentials(int n, int N, int W, double mu0, double mu1,
 // Supported grid sizes for the in-LDS plane passes.
 bool grid_supported(int n);
 
+// ------------------------------------------------------- step launcher --
+
+// Device control block: step counter and run/stop flags shared by every
+// kernel of a step (kernels return at once when stop != 0).
+struct Ctl {
+  long long step;       // steps applied since creation / last set_state
+  int stop;             // 0 run, 1 converged (tol met), 2 unstable
+  int pad;
+  double tol;           // relative fluence change that stops a run (0: off)
+  double growth_limit;  // ||phi||^2 above this flags runaway growth
+  double last_resid;
+  double last_norm2;
+};
+
+// Everything one RK4 step needs, as plain device pointers (carved from the
+// caller's workspace) and scalars. Field pointers are of the working
+// precision (float or double) and complex spectra interleave (re, im).
+struct StepArgs {
+  int prec;                 // 0 = FP32, 1 = FP64
+  int N, M;                 // order and moment count
+  void* stream;             // hipStream_t
+  void* u;                  // state [M][n^3]
+  void* v;                  // stage state [M][n^3]
+  void* spec;               // half spectrum [M][n][n][n/2+1] complex
+  const void* tw;           // twiddles exp(-2 pi i t / n), n complex
+  const void* kv;           // wavenumbers, n
+  const void* coef;         // streaming slots [M][kMaxSlots][3]
+  const void* sig;          // per-degree loss [N+1][n^3]
+  const void* q;            // source [M][n^3] or nullptr
+  const int* qflag;         // per z-plane: source present
+  double* phi_int;          // integrated fluence [n^3]
+  double* partial;          // per z-plane fluence-change partial sums [n][2]
+  double* readings;         // [cap][ndet]
+  double* resid;            // [cap]
+  const long long* det;     // [ndet]
+  int ndet;
+  long long cap;
+  void* ctl;                // device control block
+  double c, dt;
+};
+
+// Per-grid-size entry points (one translation unit per n). enqueue_step
+// queues the 13 kernels of one RK4 step; if ev is non-null it records an
+// event before the first and after every launch (14 events).
+int launch_enqueue_step(int n, const StepArgs& a, void* ev);
+int launch_prepare(int n, const StepArgs& a);
+
 }  // namespace rte

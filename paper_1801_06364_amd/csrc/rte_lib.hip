@@ -1,19 +1,7 @@
-// MI355X (gfx950) P_N pseudospectral transport stepper: kernels, runtime and
-// the C-ABI declared in include/rte.h.
-//
-// One RK stage evaluates f(v) = c (w - Sigma_l v + q) with
-// w = -IFFT[ i (k.B) FFT(v) ] (eqs. 6, 9, 10 with the sign form of eqs. 1
-// and 6) in three sweeps over HBM:
-//   F  (k_fwd_plane)  per (moment, z-plane): x real-to-complex FFT and y FFT
-//                     of the plane in LDS, written to the half spectrum;
-//   Z  (k_zpass)      per (ky, kx-tile) column, all moments in LDS: z FFT,
-//                     the streaming coupling of eq. (10) in the real basis,
-//                     inverse z FFT;
-//   P  (k_inv_plane)  per (moment, z-plane): inverse y FFT, complex-to-real
-//                     x FFT and the fused pointwise epilogue (loss, source,
-//                     boundary layer, RK combine; after the last stage also
-//                     integrated fluence and the fluence-change partials).
-// A one-block kernel closes each step (detector readings, residual, flags).
+// MI355X (gfx950) P_N pseudospectral transport stepper: runtime (handle,
+// workspace carve-up, table upload, graph capture, run control) and the
+// C-ABI declared in include/rte.h. The kernels live in rte_kernels.h, one
+// translation unit per grid size.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -24,293 +12,9 @@
 #include <vector>
 
 #include "../../include/rte.h"
-#include "rte_fft.h"
 #include "rte_internal.h"
 
 namespace rte {
-
-// ------------------------------------------------------------- control ---
-
-struct Ctl {
-  long long step;       // steps applied since creation / last set_state
-  int stop;             // 0 run, 1 converged (tol met), 2 unstable
-  int pad;
-  double tol;           // relative fluence change that stops a run (0: off)
-  double growth_limit;  // ||phi||^2 above this flags runaway growth
-  double last_resid;
-  double last_norm2;
-};
-
-struct Geo {
-  int n, H, Kp, M, N;   // H = n/2, Kp = n/2 + 1
-  unsigned plan_row;    // radices of the length-H row FFT
-  unsigned plan_col;    // radices of the length-n column FFT
-  int TT;               // kx columns per Z-pass workgroup
-  int ntile;            // Z-pass tiles per ky
-};
-
-__host__ __device__ inline size_t spec_off(const Geo& g, int b, int z, int ky, int kx) {
-  return ((size_t(b) * g.n + z) * g.n + ky) * g.Kp + kx;
-}
-
-// ---------------------------------------------------------- F: forward ---
-
-template <typename T, int E>
-__global__ void __launch_bounds__(256)
-k_fwd_plane(const T* __restrict__ src, typename cplx_of<T>::type* __restrict__ spec,
-            const typename cplx_of<T>::type* __restrict__ twg, Geo g, const Ctl* __restrict__ ctl) {
-  using V = typename cplx_of<T>::type;
-  if (ctl->stop) return;
-  extern __shared__ __align__(16) unsigned char smem[];
-  V* tw = reinterpret_cast<V*>(smem);
-  V* pl = tw + g.n;
-  const int n = g.n, H = g.H, Kp = g.Kp;
-  const int plane = blockIdx.x;            // b * n + z
-  for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = twg[i];
-  const T* s = src + size_t(plane) * n * n;
-  for (int i = threadIdx.x; i < n * H; i += blockDim.x) {
-    const int y = i / H, j = i - y * H;
-    pl[y * Kp + j] = *reinterpret_cast<const V*>(s + size_t(y) * n + 2 * j);
-  }
-  __syncthreads();
-  // x: n packed rows of length H
-  fft_batch<V, E, -1>(n, 1, H, g.plan_row, tw, 2, [&](int f) { return pl + f * Kp; });
-  __syncthreads();
-  // real-to-complex split: X_k from Z_k and Z_{H-k}
-  const int half = H / 2;
-  for (int i = threadIdx.x; i < n * (half + 1); i += blockDim.x) {
-    const int y = i / (half + 1), k = i - y * (half + 1);
-    V* row = pl + y * Kp;
-    if (k == 0) {
-      const V z0 = row[0];
-      row[0] = cmk<V>(z0.x + z0.y, T(0));
-      row[H] = cmk<V>(z0.x - z0.y, T(0));
-    } else {
-      const int m = H - k;
-      const V zk = row[k], zm = row[m];
-      const V zmc = cconj(zm), zkc = cconj(zk);
-      // X_k = (Z_k + conj Z_m)/2 - i w_k (Z_k - conj Z_m)/2,  w_k = exp(-2 pi i k / n)
-      const V ek = cscale(cadd(zk, zmc), T(0.5));
-      const V ok = cmul_i<V, -1>(cscale(csub(zk, zmc), T(0.5)));
-      row[k] = cadd(ek, cmul(tw[k], ok));
-      if (m != k) {
-        const V em = cscale(cadd(zm, zkc), T(0.5));
-        const V om = cmul_i<V, -1>(cscale(csub(zm, zkc), T(0.5)));
-        row[m] = cadd(em, cmul(tw[m], om));
-      }
-    }
-  }
-  __syncthreads();
-  // y: Kp columns of length n, stride Kp
-  fft_batch<V, E, -1>(Kp, Kp, n, g.plan_col, tw, 1, [&](int f) { return pl + f; });
-  __syncthreads();
-  const int b = plane / n, z = plane - b * n;
-  V* dst = spec + spec_off(g, b, z, 0, 0);
-  for (int i = threadIdx.x; i < n * Kp; i += blockDim.x) dst[i] = pl[i];
-}
-
-// ------------------------------------------------- Z: z FFT + coupling ---
-
-template <typename V, typename T, int N, int A, int S>
-struct RowAcc {
-  static __device__ __forceinline__ void run(const V* in, const T* __restrict__ c, T kx, T ky,
-                                             T kz, T& re, T& im) {
-    constexpr int l = isqrt_c(A);
-    constexpr int m = A - l * l - l;
-    constexpr SlotList sl = slots_of(N, l, m);
-    if constexpr (S < sl.count) {
-      constexpr int b = sl.b[S];
-      const T* t = c + (A * kMaxSlots + S) * 3;
-      const T cf = t[0] * kx + t[1] * ky + t[2] * kz;
-      re += cf * in[b].x;
-      im += cf * in[b].y;
-      RowAcc<V, T, N, A, S + 1>::run(in, c, kx, ky, kz, re, im);
-    }
-  }
-};
-
-template <typename V, typename T, int N, int A>
-struct Rows {
-  static __device__ __forceinline__ void run(const V* in, V* out, int ostride,
-                                             const T* __restrict__ c, T kx, T ky, T kz, T sc) {
-    if constexpr (A < (N + 1) * (N + 1)) {
-      T re = 0, im = 0;
-      RowAcc<V, T, N, A, 0>::run(in, c, kx, ky, kz, re, im);
-      // w_hat = -i * sc * sum_b (k.B)[a,b] u_hat_b
-      out[A * ostride] = cmk<V>(sc * im, -sc * re);
-      Rows<V, T, N, A + 1>::run(in, out, ostride, c, kx, ky, kz, sc);
-    }
-  }
-};
-
-template <typename T, int E, int N>
-__global__ void __launch_bounds__(256)
-k_zpass(typename cplx_of<T>::type* __restrict__ spec, const typename cplx_of<T>::type* __restrict__ twg,
-        const T* __restrict__ kv, const T* __restrict__ coef, Geo g, T sc,
-        const Ctl* __restrict__ ctl) {
-  using V = typename cplx_of<T>::type;
-  constexpr int M = (N + 1) * (N + 1);
-  if (ctl->stop) return;
-  extern __shared__ __align__(16) unsigned char smem[];
-  V* tw = reinterpret_cast<V*>(smem);
-  V* col = tw + g.n;
-  const int n = g.n, TT = g.TT;
-  const int ky = blockIdx.x / g.ntile;
-  const int kx0 = (blockIdx.x - ky * g.ntile) * TT;
-  const int tc = min(TT, g.Kp - kx0);
-  for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = twg[i];
-  for (int i = threadIdx.x; i < M * TT * n; i += blockDim.x) {
-    const int t = i % TT;
-    const int kz = (i / TT) % n;
-    const int b = i / (TT * n);
-    if (t < tc) col[(b * TT + t) * n + kz] = spec[spec_off(g, b, kz, ky, kx0 + t)];
-  }
-  __syncthreads();
-  const int nfft = M * TT;
-  auto base = [&](int f) { return col + f * n; };
-  fft_batch<V, E, -1>(nfft, 1, n, g.plan_col, tw, 1, base);
-  __syncthreads();
-  const T kyv = kv[ky];
-  for (int pt = threadIdx.x; pt < TT * n; pt += blockDim.x) {
-    const int t = pt / n, kz = pt - t * n;
-    if (t >= tc) continue;
-    V in[M];
-#pragma unroll
-    for (int b = 0; b < M; ++b) in[b] = col[(b * TT + t) * n + kz];
-    Rows<V, T, N, 0>::run(in, col + t * n + kz, TT * n, coef, kv[kx0 + t], kyv, kv[kz], sc);
-  }
-  __syncthreads();
-  fft_batch<V, E, +1>(nfft, 1, n, g.plan_col, tw, 1, base);
-  __syncthreads();
-  for (int i = threadIdx.x; i < M * TT * n; i += blockDim.x) {
-    const int t = i % TT;
-    const int kz = (i / TT) % n;
-    const int b = i / (TT * n);
-    if (t < tc) spec[spec_off(g, b, kz, ky, kx0 + t)] = col[(b * TT + t) * n + kz];
-  }
-}
-
-// ------------------------------------------- P: inverse + epilogue -------
-
-template <typename T, int E, bool FIRST, bool LAST>
-__global__ void __launch_bounds__(256)
-k_inv_plane(const typename cplx_of<T>::type* __restrict__ spec, const T* vin, T* u, T* dst,
-            const T* __restrict__ sig, const T* __restrict__ q, const int* __restrict__ qflag,
-            double* __restrict__ phi_int, double* __restrict__ partial,
-            const typename cplx_of<T>::type* __restrict__ twg, Geo g, T h, double dt,
-            const Ctl* __restrict__ ctl) {
-  using V = typename cplx_of<T>::type;
-  if (ctl->stop) return;
-  extern __shared__ __align__(16) unsigned char smem[];
-  V* tw = reinterpret_cast<V*>(smem);
-  V* pl = tw + g.n;
-  const int n = g.n, H = g.H, Kp = g.Kp;
-  const int plane = blockIdx.x;
-  const int b = plane / n, z = plane - b * n;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = twg[i];
-  const V* srcp = spec + spec_off(g, b, z, 0, 0);
-  for (int i = threadIdx.x; i < n * Kp; i += blockDim.x) pl[i] = srcp[i];
-  __syncthreads();
-  fft_batch<V, E, +1>(Kp, Kp, n, g.plan_col, tw, 1, [&](int f) { return pl + f; });
-  __syncthreads();
-  // complex-to-real merge: Z_k = (X_k + conj X_{H-k}) + i conj(w_k) (X_k - conj X_{H-k})
-  const int half = H / 2;
-  for (int i = threadIdx.x; i < n * (half + 1); i += blockDim.x) {
-    const int y = i / (half + 1), k = i - y * (half + 1);
-    V* row = pl + y * Kp;
-    const int m = H - k;
-    const V xk = row[k], xm = row[m];
-    const V xmc = cconj(xm), xkc = cconj(xk);
-    const V zk = cadd(cadd(xk, xmc), cmul_i<V, +1>(cmul(cconj(tw[k]), csub(xk, xmc))));
-    if (k == 0) {
-      row[0] = zk;
-    } else {
-      row[k] = zk;
-      if (m != k) row[m] = cadd(cadd(xm, xkc), cmul_i<V, +1>(cmul(cconj(tw[m]), csub(xm, xkc))));
-    }
-  }
-  __syncthreads();
-  fft_batch<V, E, +1>(n, 1, H, g.plan_row, tw, 2, [&](int f) { return pl + f * Kp; });
-  __syncthreads();
-  // epilogue on (x_{2j}, x_{2j+1}) pairs
-  const int l = isqrt_c(b);
-  const size_t poff = size_t(plane) * n * n;
-  const size_t voff = size_t(z) * n * n;
-  const T* sg = sig + size_t(l) * n * n * n + voff;
-  const bool hasq = (q != nullptr) && qflag[z];
-  double acc_d = 0.0, acc_o = 0.0;
-  for (int i = threadIdx.x; i < n * H; i += blockDim.x) {
-    const int y = i / H, j = i - y * H;
-    const size_t e = size_t(y) * n + 2 * j;
-    const V w = pl[y * Kp + j];
-    const V uu = *reinterpret_cast<const V*>(u + poff + e);
-    const V vv = FIRST ? uu : *reinterpret_cast<const V*>(vin + poff + e);
-    const V ss = *reinterpret_cast<const V*>(sg + e);
-    T src0 = -ss.x * vv.x, src1 = -ss.y * vv.y;
-    if (hasq) {
-      const V qq = *reinterpret_cast<const V*>(q + poff + e);
-      src0 += qq.x;
-      src1 += qq.y;
-    }
-    const V o = cmk<V>(uu.x + w.x + h * src0, uu.y + w.y + h * src1);
-    *reinterpret_cast<V*>(dst + poff + e) = o;
-    if (LAST && b == 0) {
-      double2* pi = reinterpret_cast<double2*>(phi_int + voff + e);
-      double2 acc = *pi;
-      acc.x += dt * double(o.x);
-      acc.y += dt * double(o.y);
-      *pi = acc;
-      const double d0 = double(o.x) - double(uu.x), d1 = double(o.y) - double(uu.y);
-      acc_d += d0 * d0 + d1 * d1;
-      acc_o += double(o.x) * double(o.x) + double(o.y) * double(o.y);
-    }
-  }
-  if (LAST && b == 0) {
-    __syncthreads();
-    double* red = reinterpret_cast<double*>(smem);
-    red[threadIdx.x] = acc_d;
-    red[blockDim.x + threadIdx.x] = acc_o;
-    __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-      if (threadIdx.x < s) {
-        red[threadIdx.x] += red[threadIdx.x + s];
-        red[blockDim.x + threadIdx.x] += red[blockDim.x + threadIdx.x + s];
-      }
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-      partial[2 * z] = red[0];
-      partial[2 * z + 1] = red[blockDim.x];
-    }
-  }
-}
-
-// ------------------------------------------------------- end of step ---
-
-template <typename T>
-__global__ void __launch_bounds__(256)
-k_end_step(const T* __restrict__ u, const long long* __restrict__ det, int ndet,
-           double* __restrict__ readings, double* __restrict__ resid, long long cap,
-           const double* __restrict__ partial, int n, Ctl* ctl) {
-  if (ctl->stop) return;
-  const long long s = ctl->step;
-  if (s < cap)
-    for (int p = threadIdx.x; p < ndet; p += blockDim.x) readings[s * ndet + p] = double(u[det[p]]);
-  if (threadIdx.x == 0) {
-    double d2 = 0.0, o2 = 0.0;
-    for (int z = 0; z < n; ++z) {
-      d2 += partial[2 * z];
-      o2 += partial[2 * z + 1];
-    }
-    const double r = o2 > 0.0 ? sqrt(d2 / o2) : 0.0;
-    if (s < cap) resid[s] = r;
-    ctl->last_resid = r;
-    ctl->last_norm2 = o2;
-    ctl->step = s + 1;
-    if (!isfinite(d2) || !isfinite(o2) || o2 > ctl->growth_limit) ctl->stop = 2;
-    else if (ctl->tol > 0.0 && r < ctl->tol) ctl->stop = 1;
-  }
-}
 
 // ------------------------------------------------------------ runtime ---
 
@@ -364,23 +68,49 @@ inline Layout layout_of(const rte_config* c, bool has_q) {
   return L;
 }
 
-inline unsigned fft_plan(int L) {
-  unsigned plan = 0;
-  int sh = 0, m = L;
-  auto push = [&](int r) { plan |= unsigned(r) << sh; sh += 4; m /= r; };
-  if (m % 3 == 0) push(3);
-  while (m % 8 == 0) push(8);
-  if (m == 4) push(4);
-  if (m == 2) push(2);
-  return m == 1 ? plan : 0u;
+int enqueue_step_n16(const StepArgs& a, void* ev);
+int enqueue_step_n32(const StepArgs& a, void* ev);
+int enqueue_step_n48(const StepArgs& a, void* ev);
+int enqueue_step_n64(const StepArgs& a, void* ev);
+int enqueue_step_n96(const StepArgs& a, void* ev);
+int enqueue_step_n128(const StepArgs& a, void* ev);
+int prepare_n16(const StepArgs& a);
+int prepare_n32(const StepArgs& a);
+int prepare_n48(const StepArgs& a);
+int prepare_n64(const StepArgs& a);
+int prepare_n96(const StepArgs& a);
+int prepare_n128(const StepArgs& a);
+
+int launch_enqueue_step(int n, const StepArgs& a, void* ev) {
+  switch (n) {
+    case 16: return enqueue_step_n16(a, ev);
+    case 32: return enqueue_step_n32(a, ev);
+    case 48: return enqueue_step_n48(a, ev);
+    case 64: return enqueue_step_n64(a, ev);
+    case 96: return enqueue_step_n96(a, ev);
+    case 128: return enqueue_step_n128(a, ev);
+    default: return int(hipErrorInvalidValue);
+  }
+}
+
+int launch_prepare(int n, const StepArgs& a) {
+  switch (n) {
+    case 16: return prepare_n16(a);
+    case 32: return prepare_n32(a);
+    case 48: return prepare_n48(a);
+    case 64: return prepare_n64(a);
+    case 96: return prepare_n96(a);
+    case 128: return prepare_n128(a);
+    default: return int(hipErrorInvalidValue);
+  }
 }
 
 }  // namespace rte
 
 struct rte_handle {
   rte_config cfg;
-  rte::Geo geo;
   rte::Layout lay;
+  rte::StepArgs args;
   int n, N, M, prec;
   double dt;
   bool has_q;
@@ -390,116 +120,10 @@ struct rte_handle {
   hipGraphExec_t exec;
   bool graph_ready;
   bool use_graph;
-  size_t lds_plane, lds_z;
   template <typename P> P* at(size_t off) const { return reinterpret_cast<P*>(ws + off); }
 };
 
 namespace rte {
-
-template <typename T, int E, int N>
-hipError_t set_lds_limits(rte_handle* h) {
-  hipError_t e = hipSuccess;
-  auto set = [&](const void* f, size_t bytes) {
-    if (e == hipSuccess)
-      e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
-  };
-  set(reinterpret_cast<const void*>(&k_fwd_plane<T, E>), h->lds_plane);
-  set(reinterpret_cast<const void*>(&k_inv_plane<T, E, true, false>), h->lds_plane);
-  set(reinterpret_cast<const void*>(&k_inv_plane<T, E, false, false>), h->lds_plane);
-  set(reinterpret_cast<const void*>(&k_inv_plane<T, E, false, true>), h->lds_plane);
-  set(reinterpret_cast<const void*>(&k_zpass<T, E, N>), h->lds_z);
-  return e;
-}
-
-template <typename T, int E, int N>
-hipError_t enqueue_step_t(rte_handle* h, hipEvent_t* ev) {
-  using V = typename cplx_of<T>::type;
-  const Geo& g = h->geo;
-  const Layout& L = h->lay;
-  T* u = h->at<T>(L.u);
-  T* v = h->at<T>(L.v);
-  V* spec = h->at<V>(L.spec);
-  const V* tw = h->at<V>(L.tw);
-  const T* kv = h->at<T>(L.kv);
-  const T* coef = h->at<T>(L.coef);
-  const T* sig = h->at<T>(L.sig);
-  const T* q = h->has_q ? h->at<T>(L.q) : nullptr;
-  const int* qflag = h->at<int>(L.qflag);
-  double* phi = h->at<double>(L.phi_int);
-  double* partial = h->at<double>(L.partial);
-  Ctl* ctl = h->at<Ctl>(L.ctl);
-  const double c = h->cfg.c_mm_ps, dt = h->dt;
-  const double n3 = double(g.n) * g.n * g.n;
-  const double alphas[4] = {0.25, 1.0 / 3.0, 0.5, 1.0};
-  const dim3 blk(256);
-  const int planes = g.M * g.n;
-  const int zblocks = g.n * g.ntile;
-  int mark = 0;
-  auto rec = [&]() {
-    if (ev) (void)hipEventRecord(ev[mark++], h->stream);
-  };
-  rec();
-  for (int s = 0; s < 4; ++s) {
-    const double hs = alphas[s] * dt * c;
-    const T* src = s == 0 ? u : v;
-    hipLaunchKernelGGL((k_fwd_plane<T, E>), dim3(planes), blk, h->lds_plane, h->stream, src, spec, tw,
-                       g, ctl);
-    rec();
-    hipLaunchKernelGGL((k_zpass<T, E, N>), dim3(zblocks), blk, h->lds_z, h->stream, spec, tw, kv, coef,
-                       g, T(hs / n3), ctl);
-    rec();
-    if (s == 0)
-      hipLaunchKernelGGL((k_inv_plane<T, E, true, false>), dim3(planes), blk, h->lds_plane, h->stream,
-                         spec, src, u, v, sig, q, qflag, phi, partial, tw, g, T(hs), dt, ctl);
-    else if (s < 3)
-      hipLaunchKernelGGL((k_inv_plane<T, E, false, false>), dim3(planes), blk, h->lds_plane, h->stream,
-                         spec, src, u, v, sig, q, qflag, phi, partial, tw, g, T(hs), dt, ctl);
-    else
-      hipLaunchKernelGGL((k_inv_plane<T, E, false, true>), dim3(planes), blk, h->lds_plane, h->stream,
-                         spec, src, u, u, sig, q, qflag, phi, partial, tw, g, T(hs), dt, ctl);
-    rec();
-  }
-  hipLaunchKernelGGL((k_end_step<T>), dim3(1), blk, 0, h->stream, u, h->at<long long>(L.det),
-                     h->cfg.n_det, h->at<double>(L.readings), h->at<double>(L.resid),
-                     (long long)h->cfg.record_steps, partial, g.n, ctl);
-  rec();
-  return hipGetLastError();
-}
-
-// Dispatch over precision, E (radix-3 grids use E = 24) and the order N.
-template <template <typename, int, int> class Fn>
-hipError_t dispatch(rte_handle* h) {
-  const bool three = (h->n % 3) == 0;
-#define RTE_CASE_N(T, E)                                   \
-  switch (h->N) {                                          \
-    case 0: return Fn<T, E, 0>::call(h);                   \
-    case 1: return Fn<T, E, 1>::call(h);                   \
-    case 2: return Fn<T, E, 2>::call(h);                   \
-    case 3: return Fn<T, E, 3>::call(h);                   \
-    case 4: return Fn<T, E, 4>::call(h);                   \
-    case 5: return Fn<T, E, 5>::call(h);                   \
-    case 6: return Fn<T, E, 6>::call(h);                   \
-    case 7: return Fn<T, E, 7>::call(h);                   \
-    default: return hipErrorInvalidValue;                  \
-  }
-  if (h->prec == RTE_FP64) {
-    if (three) { RTE_CASE_N(double, 24) } else { RTE_CASE_N(double, 8) }
-  } else {
-    if (three) { RTE_CASE_N(float, 24) } else { RTE_CASE_N(float, 8) }
-  }
-#undef RTE_CASE_N
-}
-
-template <typename T, int E, int N> struct StepFn {
-  static hipError_t call(rte_handle* h) { return enqueue_step_t<T, E, N>(h, nullptr); }
-};
-thread_local hipEvent_t* g_prof_events = nullptr;
-template <typename T, int E, int N> struct ProfStepFn {
-  static hipError_t call(rte_handle* h) { return enqueue_step_t<T, E, N>(h, g_prof_events); }
-};
-template <typename T, int E, int N> struct LdsFn {
-  static hipError_t call(rte_handle* h) { return set_lds_limits<T, E, N>(h); }
-};
 
 int to_code(hipError_t e) { return e == hipSuccess ? RTE_OK : RTE_EDEVICE; }
 
@@ -615,7 +239,7 @@ int enqueue_steps(rte_handle* h, int64_t k) {
   if (h->use_graph && !h->graph_ready) {
     hipError_t e = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-      hipError_t e2 = dispatch<StepFn>(h);
+      hipError_t e2 = hipError_t(launch_enqueue_step(h->n, h->args, nullptr));
       e = hipStreamEndCapture(h->stream, &h->graph);
       if (e2 != hipSuccess) e = e2;
     }
@@ -628,7 +252,8 @@ int enqueue_steps(rte_handle* h, int64_t k) {
     }
   }
   for (int64_t i = 0; i < k; ++i) {
-    hipError_t e = h->graph_ready ? hipGraphLaunch(h->exec, h->stream) : dispatch<StepFn>(h);
+    hipError_t e = h->graph_ready ? hipGraphLaunch(h->exec, h->stream)
+                                  : hipError_t(launch_enqueue_step(h->n, h->args, nullptr));
     if (e != hipSuccess) return RTE_EDEVICE;
   }
   return RTE_OK;
@@ -685,31 +310,31 @@ int rte_create(const rte_config* cfg, const rte_medium* med, void* dev_ws, size_
   h->graph_ready = false;
   const char* ng = std::getenv("RTE_NO_GRAPH");
   h->use_graph = (h->stream != nullptr) && !(ng && ng[0] == '1');
-  Geo& g = h->geo;
-  g.n = n;
-  g.H = n / 2;
-  g.Kp = n / 2 + 1;
-  g.M = M;
-  g.N = N;
-  g.plan_row = fft_plan(n / 2);
-  g.plan_col = fft_plan(n);
-  const size_t cs = cfg->precision == RTE_FP64 ? 16 : 8;
-  const size_t col_bytes = size_t(M) * n * cs;
-  int TT = 1;
-  while (TT < 16 && TT * 2 <= g.Kp && (size_t(2 * TT) * col_bytes + n * cs) <= 64 * 1024) TT *= 2;
-  g.TT = TT;
-  g.ntile = (g.Kp + TT - 1) / TT;
-  h->lds_plane = (size_t(n) * g.Kp + n) * cs;
-  h->lds_z = size_t(TT) * col_bytes + n * cs;
-  if (h->lds_z > 160 * 1024 || g.plan_row == 0 || g.plan_col == 0) {
-    delete h;
-    return RTE_EINVAL;
-  }
-  // the reduction in the last inverse pass reuses the plane LDS
-  h->lds_plane = std::max(h->lds_plane, size_t(2 * 256 * 8));
-
-  hipError_t e = dispatch<LdsFn>(h);
-  int rc = to_code(e);
+  StepArgs& A = h->args;
+  A.prec = h->prec;
+  A.N = N;
+  A.M = M;
+  A.stream = h->stream;
+  A.u = h->ws + L.u;
+  A.v = h->ws + L.v;
+  A.spec = h->ws + L.spec;
+  A.tw = h->ws + L.tw;
+  A.kv = h->ws + L.kv;
+  A.coef = h->ws + L.coef;
+  A.sig = h->ws + L.sig;
+  A.q = has_q ? h->ws + L.q : nullptr;
+  A.qflag = h->at<int>(L.qflag);
+  A.phi_int = h->at<double>(L.phi_int);
+  A.partial = h->at<double>(L.partial);
+  A.readings = h->at<double>(L.readings);
+  A.resid = h->at<double>(L.resid);
+  A.det = h->at<long long>(L.det);
+  A.ndet = cfg->n_det;
+  A.cap = cfg->record_steps;
+  A.ctl = h->ws + L.ctl;
+  A.c = cfg->c_mm_ps;
+  A.dt = h->dt;
+  int rc = to_code(hipError_t(launch_prepare(n, A)));
   if (!rc) rc = h->prec == RTE_FP64 ? upload_tables_t<double>(h, med, sig, inside, coef)
                                     : upload_tables_t<float>(h, med, sig, inside, coef);
   if (!rc) rc = h->prec == RTE_FP64 ? upload_state_t<double>(h, med->psi0) : upload_state_t<float>(h, med->psi0);
@@ -849,9 +474,7 @@ int rte_profile_kernels(rte_handle* h, int64_t nsteps, double* ms, int64_t* coun
   }
   int rc = RTE_OK;
   for (int64_t s = 0; s < nsteps && rc == RTE_OK; ++s) {
-    g_prof_events = ev;
-    hipError_t e = dispatch<ProfStepFn>(h);
-    g_prof_events = nullptr;
+    hipError_t e = hipError_t(launch_enqueue_step(h->n, h->args, ev));
     if (e == hipSuccess) e = hipEventSynchronize(ev[kLaunches]);
     if (e != hipSuccess) {
       rc = RTE_EDEVICE;

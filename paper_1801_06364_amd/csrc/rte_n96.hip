@@ -1,0 +1,6 @@
+// Kernels of the P_N stepper specialised for a 96^3 grid.
+#include "rte_kernels.h"
+
+namespace rte {
+RTE_DEFINE_SIZE(96)
+}  // namespace rte
