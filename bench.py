@@ -2,7 +2,7 @@
 """Benchmark: RK4 steps of the P_7 / 128^3 / FP32 inclusion workload.
 
 One "step" is one full RK4 step (four stages, each: forward plane FFT pass,
-z-pass with the streaming coupling, inverse plane pass with the fused
+z-derivative pass, moment-coupling pass, inverse plane pass with the fused
 pointwise epilogue, plus the per-step readings/residual kernel) over the
 whole device-resident state. The metric counts voxel x harmonic x RK-stage
 updates per second. Prints one JSON line.
@@ -50,20 +50,24 @@ def source_sha() -> str:
 def algorithmic_bytes(kind: str, n: int, M: int, N: int, s: int) -> float:
     """Compulsory HBM bytes of one launch of each kernel class.
 
-    fwd_plane: read the stage input (M n^3 reals), write the half spectrum
-    (M n^2 (n/2+1) complex). zpass: read and write the half spectrum.
-    inv_plane: read the half spectrum, the stage input, u and the per-degree
-    loss maps ((N+1) n^3), write the stage output (stages 2-4; the first
-    stage reads u once, counted as the general case here).
+    The packed xy spectrum of one moment field holds n^2 (n/2) complex
+    values, the same bytes as the real field (M n^3 s for all moments).
+    fwd_plane: read the stage input, write the spectrum.
+    zderiv: read the spectrum, write its z derivative.
+    couple: read the spectrum and the derivative, write the coupled spectrum.
+    inv_plane: read the coupled spectrum, the stage input, u and the
+    per-degree loss maps ((N+1) n^3), write the stage output (stages 2-4;
+    the first stage reads u once).
     """
-    V = n ** 3
-    spec = M * n * n * (n // 2 + 1) * 2 * s
+    F = M * n ** 3 * s
     if kind == "fwd_plane":
-        return M * V * s + spec
-    if kind == "zpass":
-        return 2 * spec
+        return 2 * F
+    if kind == "zderiv":
+        return 2 * F
+    if kind == "couple":
+        return 3 * F
     if kind == "inv_plane":
-        return spec + 3 * M * V * s + (N + 1) * V * s
+        return 4 * F + (N + 1) * n ** 3 * s
     return 0.0
 
 
@@ -156,7 +160,7 @@ def main():
 
     prof = s.profile_kernels(a.profile_steps)
     per = {k: (t / c if c else 0.0) for k, (t, c) in prof.items()}
-    dom = max(("fwd_plane", "zpass", "inv_plane"), key=lambda k: prof[k][0])
+    dom = max(("fwd_plane", "zderiv", "couple", "inv_plane"), key=lambda k: prof[k][0])
     alg = algorithmic_bytes(dom, wl.n, wl.M, wl.N, sbytes)
     achieved = alg / (per[dom] / 1e3) / 1e9
     tb = traffic_for(dom, a.workload)

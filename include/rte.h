@@ -143,10 +143,11 @@ int rte_set_state(rte_handle* h, const double* in, size_t len);
 int rte_coupling_dense(int32_t order_N, double* bx, double* by, double* bz);
 
 /* Run nsteps steps with plain launches, timing every kernel with HIP
- * events on the handle's stream, and add the summed milliseconds of each
- * kernel class to ms[0..3]: forward plane pass, z-pass, inverse plane pass
- * with epilogue, end-of-step bookkeeping. counts[0..3] receives the number
- * of launches timed per class. Synchronises the stream. */
+ * events on the handle's stream, and store the summed milliseconds of each
+ * kernel class in ms[0..4]: forward plane pass, z-derivative pass, moment
+ * coupling pass, inverse plane pass with epilogue, end-of-step bookkeeping.
+ * counts[0..4] receives the number of launches timed per class.
+ * Synchronises the stream. */
 int rte_profile_kernels(rte_handle* h, int64_t nsteps, double* ms, int64_t* counts);
 
 /* Release the handle (and its captured graph). The workspace stays the

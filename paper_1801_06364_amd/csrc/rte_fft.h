@@ -191,8 +191,9 @@ __device__ __forceinline__ void fft_stages(V* buf, int p, const V* tw, bool act)
 }
 
 // Run COUNT FFTs of length L (element stride S, FFT f based at base_of(f))
-// with every wavefront of the workgroup holding 64 / P of them at a time.
-template <typename V, int L, int S, int NTAB, int DIR, int COUNT, typename BaseOf>
+// with every wavefront of a BLOCK-thread workgroup holding 64 / P of them at
+// a time.
+template <typename V, int L, int S, int NTAB, int DIR, int COUNT, int BLOCK, typename BaseOf>
 __device__ __forceinline__ void fft_batch(const V* tw, BaseOf base_of) {
   static_assert(plan_ok(L), "unsupported FFT length");
   constexpr int P = L / elems_per_lane(L);
@@ -200,13 +201,35 @@ __device__ __forceinline__ void fft_batch(const V* tw, BaseOf base_of) {
   constexpr int PER_WAVE = 64 / P;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int per_round = (blockDim.x >> 6) * PER_WAVE;
+  constexpr int per_round = (BLOCK / 64) * PER_WAVE;
   const int g = lane / P;
   const int p = lane - g * P;
   for (int f0 = 0; f0 < COUNT; f0 += per_round) {
     const int f = f0 + wave * PER_WAVE + g;
     const bool act = f < COUNT;
     fft_stages<V, L, S, NTAB, DIR>(base_of(act ? f : 0), p, tw, act);
+  }
+}
+
+// Element-wise copy of COUNT items by a BLOCK-thread workgroup with up to
+// 16 loads per thread in flight before the matching stores, so global
+// latency overlaps instead of serialising load -> store pairs.
+template <int COUNT, int BLOCK, typename Ld, typename St>
+__device__ __forceinline__ void staged_copy(Ld ld, St st) {
+  constexpr int ITER = (COUNT + BLOCK - 1) / BLOCK;
+  constexpr int CHUNK = ITER < 16 ? ITER : 16;
+  for (int it0 = 0; it0 < ITER; it0 += CHUNK) {
+    decltype(ld(0)) tmp[CHUNK];
+#pragma unroll
+    for (int c = 0; c < CHUNK; ++c) {
+      const int i = int(threadIdx.x) + (it0 + c) * BLOCK;
+      if (it0 + c < ITER && (COUNT % BLOCK == 0 || i < COUNT)) tmp[c] = ld(i);
+    }
+#pragma unroll
+    for (int c = 0; c < CHUNK; ++c) {
+      const int i = int(threadIdx.x) + (it0 + c) * BLOCK;
+      if (it0 + c < ITER && (COUNT % BLOCK == 0 || i < COUNT)) st(i, tmp[c]);
+    }
   }
 }
 

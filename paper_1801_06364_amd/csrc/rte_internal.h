@@ -95,7 +95,9 @@ struct StepArgs {
   void* stream;             // hipStream_t
   void* u;                  // state [M][n^3]
   void* v;                  // stage state [M][n^3]
-  void* spec;               // half spectrum [M][n][n][n/2+1] complex
+  void* spec;               // xy spectrum [M][n][n][n/2] complex (kx = 0 packs
+                            // the real kx = 0 and kx = n/2 columns)
+  void* dspec;              // its z derivative, same layout
   const void* tw;           // twiddles exp(-2 pi i t / n), n complex
   const void* kv;           // wavenumbers, n
   const void* coef;         // streaming slots [M][kMaxSlots][3]
@@ -114,8 +116,9 @@ struct StepArgs {
 };
 
 // Per-grid-size entry points (one translation unit per n). enqueue_step
-// queues the 13 kernels of one RK4 step; if ev is non-null it records an
-// event before the first and after every launch (14 events).
+// queues the 17 kernels of one RK4 step (4 per stage + end of step); if ev
+// is non-null it records an event before the first and after every launch
+// (18 events).
 int launch_enqueue_step(int n, const StepArgs& a, void* ev);
 int launch_prepare(int n, const StepArgs& a);
 

@@ -1,15 +1,17 @@
 // Kernels of one RK stage of the P_N stepper, specialised at compile time
 // for the grid size NN (points per axis) and the working precision T.
 //
-// One RK stage evaluates f(v) = c (w - Sigma_l v + q) with
-// w = -IFFT[ i (k.B) FFT(v) ] (eqs. 6, 9, 10 with the sign form of eqs. 1
-// and 6) in three sweeps over HBM:
+// One RK stage evaluates f(v) = c (w - Sigma_l v + q) with the streaming
+// term w = -(Bx d/dx + By d/dy + Bz d/dz) v of eq. (6), evaluated
+// spectrally (eqs. 7-10; sign form of eqs. 1 and 6). Since the B_j are
+// constant matrices, the z derivative can be taken per moment before the
+// moments are mixed, which keeps every sweep over HBM coalesced:
 //   F  k_fwd_plane  per (moment, z-plane): x real-to-complex FFT and y FFT of
-//                   the plane in LDS, written to the half spectrum
-//                   [b][z][ky][kx], kx in [0, n/2];
-//   Z  k_zpass      per (ky, kx-tile): all moments of TT spectral columns in
-//                   LDS; z FFT, the streaming coupling of eq. (10) in the real
-//                   basis, inverse z FFT;
+//                   the plane in LDS -> xy spectrum S [b][z][ky][kx];
+//   D  k_zderiv     per (moment, ky, 16 kx columns): z FFT, times i k_z,
+//                   inverse z FFT -> D = d/dz S (xy spectral, z physical);
+//   C  k_couple     per spectral point, all moments in registers:
+//                   W = -i (kx Bx + ky By) S - Bz D, written over S;
 //   P  k_inv_plane  per (moment, z-plane): inverse y FFT, complex-to-real x
 //                   FFT and the fused pointwise epilogue (loss, in-scatter,
 //                   boundary layer, source, RK combine; after the last stage
@@ -17,8 +19,8 @@
 // k_end_step closes each step (detector readings, residual, stop flags).
 //
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
-// L2. Tiles that share cache lines (neighbouring kx columns in Z, the moments
-// of one z-plane that read the same loss map in P) are remapped so that
+// L2. Tiles that share data (neighbouring kx tiles in D, the moments of one
+// z-plane that read the same loss map in P) are remapped so that
 // consecutive logical tiles run on the same XCD.
 #pragma once
 
@@ -30,10 +32,22 @@
 #ifndef RTE_ZBUDGET
 #define RTE_ZBUDGET (64 * 1024)
 #endif
+#ifndef RTE_PBLOCK
+#define RTE_PBLOCK 512
+#endif
+#ifndef RTE_ZBLOCK
+#define RTE_ZBLOCK 256
+#endif
+#ifndef RTE_CBLOCK
+#define RTE_CBLOCK 256
+#endif
 
 namespace rte {
 
-constexpr int kBlock = 256;
+constexpr int kBlock = 256;        // end-of-step kernel
+constexpr int kPBlock = RTE_PBLOCK;  // plane passes
+constexpr int kZBlock = RTE_ZBLOCK;  // z-derivative pass
+constexpr int kCBlock = RTE_CBLOCK;  // coupling pass
 constexpr int kXcds = 8;
 
 // Physical block id -> logical tile: XCD x (= bid % 8) receives a contiguous
@@ -47,65 +61,52 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblocks) {
 template <int NN> struct GridC {
   static constexpr int n = NN;
   static constexpr int H = NN / 2;
-  static constexpr int Kp = NN / 2 + 1;
   static constexpr int E = elems_per_lane(NN);
   static_assert(elems_per_lane(NN / 2) == elems_per_lane(NN), "row/column lane shape");
 };
 
-// kx columns per Z-pass workgroup: largest power of two (<= 16) whose
-// columns of all moments fit the LDS budget.
-template <typename T, int NN, int N>
-constexpr int z_tile() {
-  constexpr long col = long((N + 1) * (N + 1)) * NN * 2 * sizeof(T);
-  int tt = 1;
-  while (tt < 16 && 2 * tt <= NN / 2 + 1 && (2 * tt) * col + NN * 2 * long(sizeof(T)) <= RTE_ZBUDGET) tt *= 2;
-  return tt;
-}
-
 template <typename T, int NN>
 constexpr size_t plane_lds() {
   using G = GridC<NN>;
-  const size_t b = (size_t(NN) * G::Kp + NN) * 2 * sizeof(T);
-  return b < 2 * kBlock * 8 ? 2 * kBlock * 8 : b;
+  // twiddles (n) + plane with odd row pitch n/2 + 1
+  const size_t b = (size_t(NN) * (G::H + 1) + NN) * 2 * sizeof(T);
+  return b < 2 * kPBlock * 8 ? 2 * kPBlock * 8 : b;
 }
-template <typename T, int NN, int N>
-constexpr size_t z_lds() {
-  return (size_t(z_tile<T, NN, N>()) * (N + 1) * (N + 1) * NN + NN) * 2 * sizeof(T);
-}
-
 // ---------------------------------------------------------- F: forward ---
 
+// The x transform of a real row has real kx = 0 and kx = n/2 entries; both
+// have zero x wavenumber (the Nyquist one by the Nyquist rule), so every
+// later operator treats them alike and they travel packed as one complex
+// column kx = 0 holding (X_0, X_{n/2}). The half spectrum is therefore
+// exactly n/2 columns wide: [b][z][ky][kx], kx in [0, n/2).
 template <typename T, int NN>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kPBlock)
 k_fwd_plane(const T* __restrict__ src, typename cplx_of<T>::type* __restrict__ spec,
             const typename cplx_of<T>::type* __restrict__ twg, const Ctl* __restrict__ ctl) {
   using V = typename cplx_of<T>::type;
   using G = GridC<NN>;
-  constexpr int n = NN, H = G::H, Kp = G::Kp;
+  constexpr int n = NN, H = G::H, LP = H + 1;   // LDS row pitch (odd: no bank aliasing)
   if (ctl->stop) return;
   extern __shared__ __align__(16) unsigned char smem[];
   V* tw = reinterpret_cast<V*>(smem);
   V* pl = tw + n;
   const int plane = blockIdx.x;            // b * n + z
-  for (int i = threadIdx.x; i < n; i += kBlock) tw[i] = twg[i];
-  const T* s = src + size_t(plane) * n * n;
-  for (int i = threadIdx.x; i < n * H; i += kBlock) {
-    const int y = i / H, j = i - y * H;
-    pl[y * Kp + j] = *reinterpret_cast<const V*>(s + y * n + 2 * j);
-  }
+  for (int i = threadIdx.x; i < n; i += kPBlock) tw[i] = twg[i];
+  const V* s = reinterpret_cast<const V*>(src + size_t(plane) * n * n);
+  staged_copy<n * H, kPBlock>([&](int i) { return s[i]; },
+                              [&](int i, V x) { pl[(i / H) * LP + (i % H)] = x; });
   __syncthreads();
   // x: n packed rows of length H (twiddle table of length n, stride 2)
-  fft_batch<V, H, 1, 2 * H, -1, n>(tw, [&](int f) { return pl + f * Kp; });
+  fft_batch<V, H, 1, 2 * H, -1, n, kPBlock>(tw, [&](int f) { return pl + f * LP; });
   __syncthreads();
   // real-to-complex split: X_k from Z_k and Z_{H-k}
   constexpr int half = H / 2;
-  for (int i = threadIdx.x; i < n * (half + 1); i += kBlock) {
+  for (int i = threadIdx.x; i < n * (half + 1); i += kPBlock) {
     const int y = i / (half + 1), k = i - y * (half + 1);
-    V* row = pl + y * Kp;
+    V* row = pl + y * LP;
     if (k == 0) {
       const V z0 = row[0];
-      row[0] = cmk<V>(z0.x + z0.y, T(0));
-      row[H] = cmk<V>(z0.x - z0.y, T(0));
+      row[0] = cmk<V>(z0.x + z0.y, z0.x - z0.y);   // packed (X_0, X_{n/2})
     } else {
       const int m = H - k;
       const V zk = row[k], zm = row[m];
@@ -122,102 +123,153 @@ k_fwd_plane(const T* __restrict__ src, typename cplx_of<T>::type* __restrict__ s
     }
   }
   __syncthreads();
-  // y: Kp columns of length n, stride Kp
-  fft_batch<V, n, Kp, n, -1, Kp>(tw, [&](int f) { return pl + f; });
+  // y: H columns of length n, stride LP
+  fft_batch<V, n, LP, n, -1, H, kPBlock>(tw, [&](int f) { return pl + f; });
   __syncthreads();
-  V* dst = spec + size_t(plane) * n * Kp;
-  for (int i = threadIdx.x; i < n * Kp; i += kBlock) dst[i] = pl[i];
+  V* dst = spec + size_t(plane) * n * H;
+  staged_copy<n * H, kPBlock>([&](int i) { return pl[(i / H) * LP + (i % H)]; },
+                              [&](int i, V x) { dst[i] = x; });
 }
 
-// ------------------------------------------------- Z: z FFT + coupling ---
+// ------------------------------------------- D: z derivative per moment ---
 
+// Columns (b, ky, kx0..kx0+TZ) of the xy spectrum, all z, in LDS with a
+// padded column pitch; forward z FFT, times i k_z / n (Nyquist k_z = 0),
+// inverse z FFT, written to the derivative buffer. TZ = 16 complex FP32 is
+// one 128-byte line per (b, z, ky) row segment.
+constexpr int zd_width(int H) {
+  int t = 16;
+  while (t > 1 && H % t != 0) t /= 2;
+  return t;
+}
+template <typename T, int NN> struct ZdShape {
+  static constexpr int TZ = zd_width(NN / 2);   // largest power of two <= 16 dividing n/2
+  static constexpr int PITCH = NN + 1;
+  static constexpr int NTILE = (NN / 2) / TZ;
+  static_assert(NTILE * TZ == NN / 2, "tiles must cover the half spectrum");
+};
+
+template <typename T, int NN>
+constexpr size_t zd_lds() {
+  using Z = ZdShape<T, NN>;
+  return (size_t(Z::TZ) * Z::PITCH + NN) * 2 * sizeof(T);
+}
+
+template <typename T, int NN>
+__global__ void __launch_bounds__(kZBlock)
+k_zderiv(const typename cplx_of<T>::type* __restrict__ spec, typename cplx_of<T>::type* __restrict__ dspec,
+         const typename cplx_of<T>::type* __restrict__ twg, const T* __restrict__ kv,
+         const Ctl* __restrict__ ctl) {
+  using V = typename cplx_of<T>::type;
+  using Z = ZdShape<T, NN>;
+  constexpr int n = NN, H = NN / 2, TZ = Z::TZ, PITCH = Z::PITCH;
+  if (ctl->stop) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  V* tw = reinterpret_cast<V*>(smem);
+  V* col = tw + n;
+  // logical tile = (b * n + ky) * NTILE + kx-tile; neighbours share an XCD
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int bky = tile / Z::NTILE;
+  const int kx0 = (tile - bky * Z::NTILE) * TZ;
+  const int b = bky / n, ky = bky - b * n;
+  for (int i = threadIdx.x; i < n; i += kZBlock) tw[i] = twg[i];
+  // element (z, t) at spec[((b n + z) n + ky) H + kx0 + t]
+  const size_t base = (size_t(b) * n * n + ky) * H + kx0;
+  staged_copy<n * TZ, kZBlock>(
+      [&](int i) { return spec[base + size_t(i / TZ) * n * H + (i % TZ)]; },
+      [&](int i, V x) { col[(i % TZ) * PITCH + i / TZ] = x; });
+  __syncthreads();
+  fft_batch<V, n, 1, n, -1, TZ, kZBlock>(tw, [&](int f) { return col + f * PITCH; });
+  __syncthreads();
+  const T inv_n = T(1) / T(n);
+  for (int i = threadIdx.x; i < n * TZ; i += kZBlock) {
+    const int t = i / n, kz = i - t * n;
+    V* e = col + t * PITCH + kz;
+    const T k = kv[kz] * inv_n;
+    const V x = *e;
+    *e = cmk<V>(-k * x.y, k * x.x);     // times i k_z / n
+  }
+  __syncthreads();
+  fft_batch<V, n, 1, n, +1, TZ, kZBlock>(tw, [&](int f) { return col + f * PITCH; });
+  __syncthreads();
+  staged_copy<n * TZ, kZBlock>(
+      [&](int i) { return col[(i % TZ) * PITCH + i / TZ]; },
+      [&](int i, V x) { dspec[base + size_t(i / TZ) * n * H + (i % TZ)] = x; });
+}
+
+// --------------------------------------------------- C: moment coupling ---
+
+// For one spectral point (kx, ky, z) with all moments' xy spectra S_b in
+// registers and the z derivatives D_b in memory, the streaming term of
+// eq. (10) in the real basis is
+//   W_a = s * ( -i (kx Bx + ky By)[a,b] S_b  -  Bz[a,b] D_b ),
+// with Bz non-zero only between equal orders m.
 template <typename V, typename T, int N, int A, int S>
 struct RowAcc {
-  static __device__ __forceinline__ void run(const V* in, const T* __restrict__ c, T kx, T ky,
-                                             T kz, T& re, T& im) {
+  static __device__ __forceinline__ void run(const V* in, const V* __restrict__ dcol, size_t mstride,
+                                             const T* __restrict__ c, T kx, T ky, T& re, T& im,
+                                             T& dre, T& dim) {
     constexpr int l = isqrt_c(A);
     constexpr int m = A - l * l - l;
     constexpr SlotList sl = slots_of(N, l, m);
     if constexpr (S < sl.count) {
       constexpr int b = sl.b[S];
+      constexpr int lb = isqrt_c(b);
+      constexpr int mb = b - lb * lb - lb;
       const T* t = c + (A * kMaxSlots + S) * 3;
-      const T cf = t[0] * kx + t[1] * ky + t[2] * kz;
+      const T cf = t[0] * kx + t[1] * ky;
       re += cf * in[b].x;
       im += cf * in[b].y;
-      RowAcc<V, T, N, A, S + 1>::run(in, c, kx, ky, kz, re, im);
+      if constexpr (mb == m) {
+        const V d = dcol[b * mstride];
+        dre += t[2] * d.x;
+        dim += t[2] * d.y;
+      }
+      RowAcc<V, T, N, A, S + 1>::run(in, dcol, mstride, c, kx, ky, re, im, dre, dim);
     }
   }
 };
 
-template <typename V, typename T, int N, int A, int OSTRIDE>
+template <typename V, typename T, int N, int A>
 struct Rows {
-  static __device__ __forceinline__ void run(const V* in, V* out, const T* __restrict__ c, T kx,
-                                             T ky, T kz, T sc) {
+  static __device__ __forceinline__ void run(const V* in, V* out, const V* __restrict__ dcol,
+                                             size_t mstride, const T* __restrict__ c, T kx, T ky,
+                                             T sc) {
     if constexpr (A < (N + 1) * (N + 1)) {
-      T re = 0, im = 0;
-      RowAcc<V, T, N, A, 0>::run(in, c, kx, ky, kz, re, im);
-      // w_hat = -i * sc * sum_b (k.B)[a,b] u_hat_b
-      out[A * OSTRIDE] = cmk<V>(sc * im, -sc * re);
-      Rows<V, T, N, A + 1, OSTRIDE>::run(in, out, c, kx, ky, kz, sc);
+      T re = 0, im = 0, dre = 0, dim = 0;
+      RowAcc<V, T, N, A, 0>::run(in, dcol, mstride, c, kx, ky, re, im, dre, dim);
+      // -i (re + i im) - (dre + i dim)
+      out[A * mstride] = cmk<V>(sc * (im - dre), sc * (-re - dim));
+      Rows<V, T, N, A + 1>::run(in, out, dcol, mstride, c, kx, ky, sc);
     }
   }
 };
 
+// One thread per spectral point of the (z, ky) rows; the moments of a point
+// are strided by n^2 H in the spectrum. Coalesced along kx.
 template <typename T, int NN, int N>
-__global__ void __launch_bounds__(kBlock)
-k_zpass(typename cplx_of<T>::type* __restrict__ spec, const typename cplx_of<T>::type* __restrict__ twg,
-        const T* __restrict__ kv, const T* __restrict__ coef, T sc, const Ctl* __restrict__ ctl) {
+__global__ void __launch_bounds__(kCBlock)
+k_couple(typename cplx_of<T>::type* __restrict__ spec, const typename cplx_of<T>::type* __restrict__ dspec,
+         const T* __restrict__ kv, const T* __restrict__ coef, T sc, const Ctl* __restrict__ ctl) {
   using V = typename cplx_of<T>::type;
-  using G = GridC<NN>;
-  constexpr int n = NN, Kp = G::Kp;
+  constexpr int n = NN, H = NN / 2;
   constexpr int M = (N + 1) * (N + 1);
-  constexpr int TT = z_tile<T, NN, N>();
-  constexpr int NTILE = (Kp + TT - 1) / TT;
+  constexpr size_t MS = size_t(n) * n * H;      // moment stride
   if (ctl->stop) return;
-  extern __shared__ __align__(16) unsigned char smem[];
-  V* tw = reinterpret_cast<V*>(smem);
-  V* col = tw + n;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int ky = tile / NTILE;
-  const int kx0 = (tile - ky * NTILE) * TT;
-  const int tc = min(TT, Kp - kx0);
-  for (int i = threadIdx.x; i < n; i += kBlock) tw[i] = twg[i];
-  // column element (b, kz, t) at spec[((b n + kz) n + ky) Kp + kx0 + t]
-  V* gbase = spec + size_t(ky) * Kp + kx0;
-  for (int i = threadIdx.x; i < M * TT * n; i += kBlock) {
-    const int t = i % TT;
-    const int kz = (i / TT) % n;
-    const int b = i / (TT * n);
-    if (t < tc) col[(b * TT + t) * n + kz] = gbase[(size_t(b) * n + kz) * n * Kp + t];
-  }
-  __syncthreads();
-  auto base = [&](int f) { return col + f * n; };
-  fft_batch<V, n, 1, n, -1, M * TT>(tw, base);
-  __syncthreads();
-  const T kyv = kv[ky];
-  for (int pt = threadIdx.x; pt < TT * n; pt += kBlock) {
-    const int t = pt / n, kz = pt - t * n;
-    if (t >= tc) continue;
-    V in[M];
+  const int pt = blockIdx.x * kCBlock + threadIdx.x;   // (z * n + ky) * H + kx
+  if (pt >= n * n * H) return;
+  const int kx = pt % H;
+  const int ky = (pt / H) % n;
+  V in[M];
 #pragma unroll
-    for (int b = 0; b < M; ++b) in[b] = col[(b * TT + t) * n + kz];
-    Rows<V, T, N, 0, TT * n>::run(in, col + t * n + kz, coef, kv[kx0 + t], kyv, kv[kz], sc);
-  }
-  __syncthreads();
-  fft_batch<V, n, 1, n, +1, M * TT>(tw, base);
-  __syncthreads();
-  for (int i = threadIdx.x; i < M * TT * n; i += kBlock) {
-    const int t = i % TT;
-    const int kz = (i / TT) % n;
-    const int b = i / (TT * n);
-    if (t < tc) gbase[(size_t(b) * n + kz) * n * Kp + t] = col[(b * TT + t) * n + kz];
-  }
+  for (int b = 0; b < M; ++b) in[b] = spec[b * MS + pt];
+  Rows<V, T, N, 0>::run(in, spec + pt, dspec + pt, MS, coef, kv[kx], kv[ky], sc);
 }
 
 // ------------------------------------------- P: inverse + epilogue -------
 
 template <typename T, int NN, bool FIRST, bool LAST>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kPBlock)
 k_inv_plane(const typename cplx_of<T>::type* __restrict__ spec, const T* vin, T* u, T* dst,
             const T* __restrict__ sig, const T* __restrict__ q, const int* __restrict__ qflag,
             double* __restrict__ phi_int, double* __restrict__ partial,
@@ -225,7 +277,7 @@ k_inv_plane(const typename cplx_of<T>::type* __restrict__ spec, const T* vin, T*
             const Ctl* __restrict__ ctl) {
   using V = typename cplx_of<T>::type;
   using G = GridC<NN>;
-  constexpr int n = NN, H = G::H, Kp = G::Kp;
+  constexpr int n = NN, H = G::H, LP = H + 1;
   if (ctl->stop) return;
   extern __shared__ __align__(16) unsigned char smem[];
   V* tw = reinterpret_cast<V*>(smem);
@@ -235,30 +287,32 @@ k_inv_plane(const typename cplx_of<T>::type* __restrict__ spec, const T* vin, T*
   const int lt = xcd_tile(blockIdx.x, gridDim.x);
   const int z = lt / M, b = lt - z * M;
   const int plane = b * n + z;
-  for (int i = threadIdx.x; i < n; i += kBlock) tw[i] = twg[i];
-  const V* srcp = spec + size_t(plane) * n * Kp;
-  for (int i = threadIdx.x; i < n * Kp; i += kBlock) pl[i] = srcp[i];
+  for (int i = threadIdx.x; i < n; i += kPBlock) tw[i] = twg[i];
+  const V* srcp = spec + size_t(plane) * n * H;
+  staged_copy<n * H, kPBlock>([&](int i) { return srcp[i]; },
+                              [&](int i, V x) { pl[(i / H) * LP + (i % H)] = x; });
   __syncthreads();
-  fft_batch<V, n, Kp, n, +1, Kp>(tw, [&](int f) { return pl + f; });
+  fft_batch<V, n, LP, n, +1, H, kPBlock>(tw, [&](int f) { return pl + f; });
   __syncthreads();
-  // complex-to-real merge: Z_k = (X_k + conj X_{H-k}) + i conj(w_k) (X_k - conj X_{H-k})
+  // complex-to-real merge: Z_k = (X_k + conj X_{H-k}) + i conj(w_k) (X_k - conj X_{H-k});
+  // column 0 carries the real pair (X_0, X_{n/2}).
   constexpr int half = H / 2;
-  for (int i = threadIdx.x; i < n * (half + 1); i += kBlock) {
+  for (int i = threadIdx.x; i < n * (half + 1); i += kPBlock) {
     const int y = i / (half + 1), k = i - y * (half + 1);
-    V* row = pl + y * Kp;
-    const int m = H - k;
-    const V xk = row[k], xm = row[m];
-    const V xmc = cconj(xm), xkc = cconj(xk);
-    const V zk = cadd(cadd(xk, xmc), cmul_i<V, +1>(cmul(cconj(tw[k]), csub(xk, xmc))));
+    V* row = pl + y * LP;
     if (k == 0) {
-      row[0] = zk;
+      const V p0 = row[0];
+      row[0] = cmk<V>(p0.x + p0.y, p0.x - p0.y);
     } else {
-      row[k] = zk;
+      const int m = H - k;
+      const V xk = row[k], xm = row[m];
+      const V xmc = cconj(xm), xkc = cconj(xk);
+      row[k] = cadd(cadd(xk, xmc), cmul_i<V, +1>(cmul(cconj(tw[k]), csub(xk, xmc))));
       if (m != k) row[m] = cadd(cadd(xm, xkc), cmul_i<V, +1>(cmul(cconj(tw[m]), csub(xm, xkc))));
     }
   }
   __syncthreads();
-  fft_batch<V, H, 1, 2 * H, +1, n>(tw, [&](int f) { return pl + f * Kp; });
+  fft_batch<V, H, 1, 2 * H, +1, n, kPBlock>(tw, [&](int f) { return pl + f * LP; });
   __syncthreads();
   // epilogue on (x_{2j}, x_{2j+1}) pairs
   const int l = isqrt_c(b);
@@ -267,10 +321,11 @@ k_inv_plane(const typename cplx_of<T>::type* __restrict__ spec, const T* vin, T*
   const T* sg = sig + size_t(l) * n * n * n + voff;
   const bool hasq = (q != nullptr) && qflag[z];
   double acc_d = 0.0, acc_o = 0.0;
-  for (int i = threadIdx.x; i < n * H; i += kBlock) {
+#pragma unroll 4
+  for (int i = threadIdx.x; i < n * H; i += kPBlock) {
     const int y = i / H, j = i - y * H;
     const int e = y * n + 2 * j;
-    const V w = pl[y * Kp + j];
+    const V w = pl[y * LP + j];
     const V uu = *reinterpret_cast<const V*>(u + poff + e);
     const V vv = FIRST ? uu : *reinterpret_cast<const V*>(vin + poff + e);
     const V ss = *reinterpret_cast<const V*>(sg + e);
@@ -297,18 +352,18 @@ k_inv_plane(const typename cplx_of<T>::type* __restrict__ spec, const T* vin, T*
     __syncthreads();
     double* red = reinterpret_cast<double*>(smem);
     red[threadIdx.x] = acc_d;
-    red[kBlock + threadIdx.x] = acc_o;
+    red[kPBlock + threadIdx.x] = acc_o;
     __syncthreads();
-    for (int s = kBlock / 2; s > 0; s >>= 1) {
+    for (int s = kPBlock / 2; s > 0; s >>= 1) {
       if (threadIdx.x < s) {
         red[threadIdx.x] += red[threadIdx.x + s];
-        red[kBlock + threadIdx.x] += red[kBlock + threadIdx.x + s];
+        red[kPBlock + threadIdx.x] += red[kPBlock + threadIdx.x + s];
       }
       __syncthreads();
     }
     if (threadIdx.x == 0) {
       partial[2 * z] = red[0];
-      partial[2 * z + 1] = red[kBlock];
+      partial[2 * z + 1] = red[kPBlock];
     }
   }
 }
@@ -352,33 +407,33 @@ hipError_t prepare_t(const StepArgs& a) {
   set(reinterpret_cast<const void*>(&k_inv_plane<T, NN, true, false>), plane_lds<T, NN>());
   set(reinterpret_cast<const void*>(&k_inv_plane<T, NN, false, false>), plane_lds<T, NN>());
   set(reinterpret_cast<const void*>(&k_inv_plane<T, NN, false, true>), plane_lds<T, NN>());
-  set(reinterpret_cast<const void*>(&k_zpass<T, NN, N>), z_lds<T, NN, N>());
+  set(reinterpret_cast<const void*>(&k_zderiv<T, NN>), zd_lds<T, NN>());
   return e;
 }
 
 template <typename T, int NN, int N>
 hipError_t enqueue_t(const StepArgs& a, hipEvent_t* ev) {
   using V = typename cplx_of<T>::type;
-  using G = GridC<NN>;
+  using Z = ZdShape<T, NN>;
   constexpr int M = (N + 1) * (N + 1);
-  constexpr int TT = z_tile<T, NN, N>();
-  constexpr int NTILE = (G::Kp + TT - 1) / TT;
   hipStream_t st = reinterpret_cast<hipStream_t>(a.stream);
   T* u = static_cast<T*>(a.u);
   T* v = static_cast<T*>(a.v);
   V* spec = static_cast<V*>(a.spec);
+  V* dspec = static_cast<V*>(a.dspec);
   const V* tw = static_cast<const V*>(a.tw);
   const T* kv = static_cast<const T*>(a.kv);
   const T* coef = static_cast<const T*>(a.coef);
   const T* sig = static_cast<const T*>(a.sig);
   const T* q = static_cast<const T*>(a.q);
   const Ctl* cctl = static_cast<const Ctl*>(a.ctl);
-  const double n3 = double(NN) * NN * NN;
+  const double n2 = double(NN) * NN;
   const double alphas[4] = {0.25, 1.0 / 3.0, 0.5, 1.0};
-  const dim3 blk(kBlock);
+  const dim3 blk(kBlock), pblk(kPBlock), zblk(kZBlock), cblk(kCBlock);
   const int planes = M * NN;
-  const int zblocks = NN * NTILE;
-  const size_t lp = plane_lds<T, NN>(), lz = z_lds<T, NN, N>();
+  const int zblocks = M * NN * Z::NTILE;
+  const int cblocks = (NN * NN * (NN / 2) + kCBlock - 1) / kCBlock;
+  const size_t lp = plane_lds<T, NN>(), lz = zd_lds<T, NN>();
   int mark = 0;
   auto rec = [&]() {
     if (ev) (void)hipEventRecord(ev[mark++], st);
@@ -387,19 +442,21 @@ hipError_t enqueue_t(const StepArgs& a, hipEvent_t* ev) {
   for (int s = 0; s < 4; ++s) {
     const double hs = alphas[s] * a.dt * a.c;
     const T* src = s == 0 ? u : v;
-    hipLaunchKernelGGL((k_fwd_plane<T, NN>), dim3(planes), blk, lp, st, src, spec, tw, cctl);
+    hipLaunchKernelGGL((k_fwd_plane<T, NN>), dim3(planes), pblk, lp, st, src, spec, tw, cctl);
     rec();
-    hipLaunchKernelGGL((k_zpass<T, NN, N>), dim3(zblocks), blk, lz, st, spec, tw, kv, coef, T(hs / n3),
+    hipLaunchKernelGGL((k_zderiv<T, NN>), dim3(zblocks), zblk, lz, st, spec, dspec, tw, kv, cctl);
+    rec();
+    hipLaunchKernelGGL((k_couple<T, NN, N>), dim3(cblocks), cblk, 0, st, spec, dspec, kv, coef, T(hs / n2),
                        cctl);
     rec();
     if (s == 0)
-      hipLaunchKernelGGL((k_inv_plane<T, NN, true, false>), dim3(planes), blk, lp, st, spec, src, u, v, sig,
+      hipLaunchKernelGGL((k_inv_plane<T, NN, true, false>), dim3(planes), pblk, lp, st, spec, src, u, v, sig,
                          q, a.qflag, a.phi_int, a.partial, tw, M, T(hs), a.dt, cctl);
     else if (s < 3)
-      hipLaunchKernelGGL((k_inv_plane<T, NN, false, false>), dim3(planes), blk, lp, st, spec, src, u, v,
+      hipLaunchKernelGGL((k_inv_plane<T, NN, false, false>), dim3(planes), pblk, lp, st, spec, src, u, v,
                          sig, q, a.qflag, a.phi_int, a.partial, tw, M, T(hs), a.dt, cctl);
     else
-      hipLaunchKernelGGL((k_inv_plane<T, NN, false, true>), dim3(planes), blk, lp, st, spec, src, u, u, sig,
+      hipLaunchKernelGGL((k_inv_plane<T, NN, false, true>), dim3(planes), pblk, lp, st, spec, src, u, u, sig,
                          q, a.qflag, a.phi_int, a.partial, tw, M, T(hs), a.dt, cctl);
     rec();
   }

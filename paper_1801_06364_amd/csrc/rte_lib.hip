@@ -22,7 +22,7 @@ constexpr size_t kAlign = 256;
 inline size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t u, v, spec, sig, q, qflag, tw, kv, coef, det, readings, resid, partial, phi_int, ctl, total;
+  size_t u, v, spec, dspec, sig, q, qflag, tw, kv, coef, det, readings, resid, partial, phi_int, ctl, total;
 };
 
 inline bool config_ok(const rte_config* c) {
@@ -51,7 +51,8 @@ inline Layout layout_of(const rte_config* c, bool has_q) {
   size_t o = 0;
   L.u = o; o = up(o + M * V * s);
   L.v = o; o = up(o + M * V * s);
-  L.spec = o; o = up(o + M * n * n * (n / 2 + 1) * 2 * s);
+  L.spec = o; o = up(o + M * n * n * (n / 2) * 2 * s);
+  L.dspec = o; o = up(o + M * n * n * (n / 2) * 2 * s);
   L.sig = o; o = up(o + size_t(c->order_N + 1) * V * s);
   L.q = o; o = up(o + (has_q ? M * V * s : 0));
   L.qflag = o; o = up(o + n * sizeof(int));
@@ -318,6 +319,7 @@ int rte_create(const rte_config* cfg, const rte_medium* med, void* dev_ws, size_
   A.u = h->ws + L.u;
   A.v = h->ws + L.v;
   A.spec = h->ws + L.spec;
+  A.dspec = h->ws + L.dspec;
   A.tw = h->ws + L.tw;
   A.kv = h->ws + L.kv;
   A.coef = h->ws + L.coef;
@@ -464,11 +466,12 @@ int rte_coupling_dense(int32_t order_N, double* bx, double* by, double* bz) {
 int rte_profile_kernels(rte_handle* h, int64_t nsteps, double* ms, int64_t* counts) {
   using namespace rte;
   if (!h || !ms || !counts || nsteps < 0) return RTE_EINVAL;
-  constexpr int kLaunches = 13;
+  constexpr int kLaunches = 17;
+  constexpr int kClasses = 5;
   hipEvent_t ev[kLaunches + 1];
   for (int i = 0; i <= kLaunches; ++i)
     if (hipEventCreate(&ev[i]) != hipSuccess) return RTE_EDEVICE;
-  for (int c = 0; c < 4; ++c) {
+  for (int c = 0; c < kClasses; ++c) {
     ms[c] = 0.0;
     counts[c] = 0;
   }
@@ -486,7 +489,7 @@ int rte_profile_kernels(rte_handle* h, int64_t nsteps, double* ms, int64_t* coun
         rc = RTE_EDEVICE;
         break;
       }
-      const int cls = i == kLaunches - 1 ? 3 : i % 3;
+      const int cls = i == kLaunches - 1 ? kClasses - 1 : i % 4;
       ms[cls] += t;
       counts[cls] += 1;
     }

@@ -26,7 +26,7 @@ EXPORTS = (
     "rte_set_state", "rte_coupling_dense", "rte_profile_kernels", "rte_destroy",
     "rte_strerror",
 )
-KERNEL_CLASSES = ("fwd_plane", "zpass", "inv_plane", "end_step")
+KERNEL_CLASSES = ("fwd_plane", "zderiv", "couple", "inv_plane", "end_step")
 
 
 class RteError(RuntimeError):
@@ -229,8 +229,8 @@ class Solver:
     def profile_kernels(self, nsteps: int):
         """Per-kernel-class milliseconds (summed) and launch counts over
         ``nsteps`` steps timed with HIP events on the handle's stream."""
-        ms = np.zeros(4)
-        cnt = np.zeros(4, np.int64)
+        ms = np.zeros(len(KERNEL_CLASSES))
+        cnt = np.zeros(len(KERNEL_CLASSES), np.int64)
         _check(lib().rte_profile_kernels(self.h, int(nsteps), _dptr(ms),
                                          cnt.ctypes.data_as(C.POINTER(C.c_int64))),
                "rte_profile_kernels")
