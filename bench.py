@@ -170,14 +170,24 @@ def main():
                 "avg_launch_ms": per[dom]}
     s.close()
 
-    if a.copy_probe:
-        x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
-        y = torch.empty_like(x)
-        x.fill_(1.0)
-        for _ in range(3):
-            y.copy_(x)
-        torch.cuda.synchronize()
-        print("[bench] copy probe: 3 x 1 GiB device copy done", file=sys.stderr, flush=True)
+    # device-to-device copy of 1 GiB: the practical streaming bandwidth of this
+    # GPU, reported beside the published peak (it is not used as the peak)
+    x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    x.fill_(1.0)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    c0 = torch.cuda.Event(enable_timing=True)
+    c1 = torch.cuda.Event(enable_timing=True)
+    reps = 3 if a.copy_probe else 5
+    c0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    c1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * x.numel() * 4 * reps / (c0.elapsed_time(c1) / 1e3) / 1e9
+    roofline["copy_kernel_GBs"] = copy_gbs
+    del x, y
 
     out = {
         "metric": METRIC, "value": value, "unit": "updates/s", "n_gpus": 1,

@@ -230,12 +230,30 @@ struct RowAcc {
   }
 };
 
+template <typename V, int L, int N>
+__device__ __forceinline__ void load_shell(V* in, const V* __restrict__ sp, size_t mstride) {
+  if constexpr (L <= N) {
+#pragma unroll
+    for (int b = L * L; b < (L + 1) * (L + 1); ++b) in[b] = sp[b * mstride];
+  }
+}
+
+// Outputs in shell order a = l^2 + l + m. Output shell l reads input
+// shells l - 1 and l + 1 only, so input shell l + 1 is loaded when output
+// shell l starts (before output shell l + 1 overwrites it in place); at most
+// three shells are live in registers.
 template <typename V, typename T, int N, int A>
 struct Rows {
-  static __device__ __forceinline__ void run(const V* in, V* out, const V* __restrict__ dcol,
+  static __device__ __forceinline__ void run(V* in, V* out, const V* __restrict__ dcol,
                                              size_t mstride, const T* __restrict__ c, T kx, T ky,
                                              T sc) {
     if constexpr (A < (N + 1) * (N + 1)) {
+      constexpr int l = isqrt_c(A);
+      if constexpr (A == l * l && l >= 1) {
+        // keep the scheduler from hoisting later shells' loads (register pressure)
+        __builtin_amdgcn_sched_barrier(0);
+        load_shell<V, l + 1, N>(in, out, mstride);
+      }
       T re = 0, im = 0, dre = 0, dim = 0;
       RowAcc<V, T, N, A, 0>::run(in, dcol, mstride, c, kx, ky, re, im, dre, dim);
       // -i (re + i im) - (dre + i dim)
@@ -261,8 +279,8 @@ k_couple(typename cplx_of<T>::type* __restrict__ spec, const typename cplx_of<T>
   const int kx = pt % H;
   const int ky = (pt / H) % n;
   V in[M];
-#pragma unroll
-  for (int b = 0; b < M; ++b) in[b] = spec[b * MS + pt];
+  load_shell<V, 0, N>(in, spec + pt, MS);
+  load_shell<V, 1, N>(in, spec + pt, MS);
   Rows<V, T, N, 0>::run(in, spec + pt, dspec + pt, MS, coef, kv[kx], kv[ky], sc);
 }
 
