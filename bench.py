@@ -56,8 +56,9 @@ def algorithmic_bytes(kind: str, n: int, M: int, N: int, s: int) -> float:
     zderiv: read the spectrum, write its z derivative.
     couple: read the spectrum and the derivative, write the coupled spectrum.
     inv_plane: read the coupled spectrum, the stage input, u and the
-    per-degree loss maps ((N+1) n^3), write the stage output (stages 2-4;
-    the first stage reads u once).
+    per-degree loss maps ((N+1) n^3), write the stage output; averaged over
+    the four RK stages (the first stage reads u once, the last one also
+    updates the FP64 integrated fluence, 16 bytes per voxel).
     """
     F = M * n ** 3 * s
     if kind == "fwd_plane":
@@ -66,8 +67,10 @@ def algorithmic_bytes(kind: str, n: int, M: int, N: int, s: int) -> float:
         return 2 * F
     if kind == "couple":
         return 3 * F
-    if kind == "inv_plane":
-        return 4 * F + (N + 1) * n ** 3 * s
+    if kind in ("inv_plane", "inv_rows"):
+        return 3.75 * F + (N + 1) * n ** 3 * s + 16 * n ** 3 / 4
+    if kind in ("fwd_rows", "y_fwd", "y_inv"):
+        return 2 * F
     return 0.0
 
 
@@ -160,7 +163,7 @@ def main():
 
     prof = s.profile_kernels(a.profile_steps)
     per = {k: (t / c if c else 0.0) for k, (t, c) in prof.items()}
-    dom = max(("fwd_plane", "zderiv", "couple", "inv_plane"), key=lambda k: prof[k][0])
+    dom = max((k for k in prof if k != "end_step"), key=lambda k: prof[k][0])
     alg = algorithmic_bytes(dom, wl.n, wl.M, wl.N, sbytes)
     achieved = alg / (per[dom] / 1e3) / 1e9
     tb = traffic_for(dom, a.workload)

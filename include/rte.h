@@ -61,7 +61,7 @@ enum { RTE_FLUENCE_NOW = 0, RTE_FLUENCE_INTEGRATED = 1 };
 typedef struct rte_handle rte_handle;
 
 typedef struct {
-  int32_t n;               /* points per axis: 16, 32, 48, 64, 96 or 128      */
+  int32_t n;               /* points per axis: 16, 32, 48, 64, 96, 128, 256   */
   int32_t order_N;         /* P_N order, 0 <= N <= 7; M = (N+1)^2 moments     */
   int32_t precision;       /* RTE_FP32 or RTE_FP64 for state, FFTs, stages;
                               tables are computed in FP64 and rounded once;
@@ -144,10 +144,12 @@ int rte_coupling_dense(int32_t order_N, double* bx, double* by, double* bz);
 
 /* Run nsteps steps with plain launches, timing every kernel with HIP
  * events on the handle's stream, and store the summed milliseconds of each
- * kernel class in ms[0..4]: forward plane pass, z-derivative pass, moment
- * coupling pass, inverse plane pass with epilogue, end-of-step bookkeeping.
- * counts[0..4] receives the number of launches timed per class.
- * Synchronises the stream. */
+ * kernel class in ms[0..8] and the launch counts in counts[0..8]. Classes:
+ * 0 forward plane pass, 1 z-derivative pass, 2 moment coupling pass,
+ * 3 inverse plane pass with epilogue, 4 end-of-step bookkeeping; on grids
+ * split into row and pencil passes (n = 256): 5 forward row pass,
+ * 6 forward y pencil pass, 7 inverse y pencil pass, 8 inverse row pass with
+ * epilogue. Synchronises the stream. */
 int rte_profile_kernels(rte_handle* h, int64_t nsteps, double* ms, int64_t* counts);
 
 /* Release the handle (and its captured graph). The workspace stays the

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librte.so")
 
 SOURCES = ["rte_lib.hip", "rte_tables.cpp"] + [
-    f"rte_n{n}.hip" for n in (16, 32, 48, 64, 96, 128)]
+    f"rte_n{n}.hip" for n in (16, 32, 48, 64, 96, 128, 256)]
 BUILD_DIR = os.path.join(HERE, "_build")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

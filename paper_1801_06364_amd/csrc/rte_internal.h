@@ -115,11 +115,26 @@ struct StepArgs {
   double c, dt;
 };
 
+// Kernel classes timed by the profiling entry point.
+enum {
+  PROF_FWD_PLANE = 0, PROF_ZDERIV, PROF_COUPLE, PROF_INV_PLANE, PROF_END,
+  PROF_FWD_ROWS, PROF_Y_FWD, PROF_Y_INV, PROF_INV_ROWS, PROF_CLASSES
+};
+constexpr int kMaxProfLaunches = 32;
+
+// Event record of one profiled step: ev0 before the first launch, ev[i]
+// after launch i, whose kernel class is cls[i].
+struct ProfRec {
+  void* ev0;
+  void* ev[kMaxProfLaunches];
+  int cls[kMaxProfLaunches];
+  int count;
+};
+
 // Per-grid-size entry points (one translation unit per n). enqueue_step
-// queues the 17 kernels of one RK4 step (4 per stage + end of step); if ev
-// is non-null it records an event before the first and after every launch
-// (18 events).
-int launch_enqueue_step(int n, const StepArgs& a, void* ev);
+// queues the kernels of one RK4 step; pr (a ProfRec*) is null except when
+// profiling.
+int launch_enqueue_step(int n, const StepArgs& a, void* pr);
 int launch_prepare(int n, const StepArgs& a);
 
 }  // namespace rte

@@ -131,12 +131,19 @@ k_fwd_plane(const T* __restrict__ src, typename cplx_of<T>::type* __restrict__ s
                               [&](int i, V x) { dst[i] = x; });
 }
 
-// ------------------------------------------- D: z derivative per moment ---
+// ------------------------------------------------ pencil passes (D, Y) ---
 
-// Columns (b, ky, kx0..kx0+TZ) of the xy spectrum, all z, in LDS with a
-// padded column pitch; forward z FFT, times i k_z / n (Nyquist k_z = 0),
-// inverse z FFT, written to the derivative buffer. TZ = 16 complex FP32 is
-// one 128-byte line per (b, z, ky) row segment.
+// Pencils of 16 (or fewer) kx columns of the xy spectrum along one axis, all
+// points of that axis, staged in LDS with a padded column pitch (a 16-wide
+// FP32 complex row segment is one 128-byte line).
+//   PENCIL_ZDERIV: axis z; forward FFT, times i k_z / n (Nyquist k_z = 0),
+//                  inverse FFT, written to the derivative buffer
+//                  (tile = (b, ky, kx-tile));
+//   PENCIL_YFWD / PENCIL_YINV: axis y, forward / inverse FFT in place
+//                  (tile = (b, z, kx-tile); used where a whole plane does
+//                  not fit in LDS).
+enum { PENCIL_ZDERIV = 0, PENCIL_YFWD = 1, PENCIL_YINV = 2 };
+
 constexpr int zd_width(int H) {
   int t = 16;
   while (t > 1 && H % t != 0) t /= 2;
@@ -155,46 +162,116 @@ constexpr size_t zd_lds() {
   return (size_t(Z::TZ) * Z::PITCH + NN) * 2 * sizeof(T);
 }
 
-template <typename T, int NN>
+template <typename T, int NN, int MODE>
 __global__ void __launch_bounds__(kZBlock)
-k_zderiv(const typename cplx_of<T>::type* __restrict__ spec, typename cplx_of<T>::type* __restrict__ dspec,
+k_pencil(const typename cplx_of<T>::type* src, typename cplx_of<T>::type* dst,   // may alias (in place)
          const typename cplx_of<T>::type* __restrict__ twg, const T* __restrict__ kv,
          const Ctl* __restrict__ ctl) {
   using V = typename cplx_of<T>::type;
   using Z = ZdShape<T, NN>;
   constexpr int n = NN, H = NN / 2, TZ = Z::TZ, PITCH = Z::PITCH;
+  // element stride along the pencil axis in the [b][z][ky][kx] spectrum
+  constexpr size_t AX = MODE == PENCIL_ZDERIV ? size_t(n) * H : size_t(H);
   if (ctl->stop) return;
   extern __shared__ __align__(16) unsigned char smem[];
   V* tw = reinterpret_cast<V*>(smem);
   V* col = tw + n;
-  // logical tile = (b * n + ky) * NTILE + kx-tile; neighbours share an XCD
+  // logical tile = (b * n + w) * NTILE + kx-tile, w = ky (z pencils) or z
+  // (y pencils); neighbouring tiles share an XCD
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int bky = tile / Z::NTILE;
-  const int kx0 = (tile - bky * Z::NTILE) * TZ;
-  const int b = bky / n, ky = bky - b * n;
+  const int bw = tile / Z::NTILE;
+  const int kx0 = (tile - bw * Z::NTILE) * TZ;
+  const int b = bw / n, w = bw - b * n;
+  const size_t base = MODE == PENCIL_ZDERIV ? (size_t(b) * n * n + w) * H + kx0
+                                            : (size_t(b) * n + w) * size_t(n) * H + kx0;
   for (int i = threadIdx.x; i < n; i += kZBlock) tw[i] = twg[i];
-  // element (z, t) at spec[((b n + z) n + ky) H + kx0 + t]
-  const size_t base = (size_t(b) * n * n + ky) * H + kx0;
   staged_copy<n * TZ, kZBlock>(
-      [&](int i) { return spec[base + size_t(i / TZ) * n * H + (i % TZ)]; },
+      [&](int i) { return src[base + size_t(i / TZ) * AX + (i % TZ)]; },
       [&](int i, V x) { col[(i % TZ) * PITCH + i / TZ] = x; });
   __syncthreads();
-  fft_batch<V, n, 1, n, -1, TZ, kZBlock>(tw, [&](int f) { return col + f * PITCH; });
-  __syncthreads();
-  const T inv_n = T(1) / T(n);
-  for (int i = threadIdx.x; i < n * TZ; i += kZBlock) {
-    const int t = i / n, kz = i - t * n;
-    V* e = col + t * PITCH + kz;
-    const T k = kv[kz] * inv_n;
-    const V x = *e;
-    *e = cmk<V>(-k * x.y, k * x.x);     // times i k_z / n
+  if constexpr (MODE == PENCIL_YINV) {
+    fft_batch<V, n, 1, n, +1, TZ, kZBlock>(tw, [&](int f) { return col + f * PITCH; });
+  } else {
+    fft_batch<V, n, 1, n, -1, TZ, kZBlock>(tw, [&](int f) { return col + f * PITCH; });
   }
-  __syncthreads();
-  fft_batch<V, n, 1, n, +1, TZ, kZBlock>(tw, [&](int f) { return col + f * PITCH; });
+  if constexpr (MODE == PENCIL_ZDERIV) {
+    __syncthreads();
+    const T inv_n = T(1) / T(n);
+    for (int i = threadIdx.x; i < n * TZ; i += kZBlock) {
+      const int t = i / n, kz = i - t * n;
+      V* e = col + t * PITCH + kz;
+      const T k = kv[kz] * inv_n;
+      const V x = *e;
+      *e = cmk<V>(-k * x.y, k * x.x);     // times i k_z / n
+    }
+    __syncthreads();
+    fft_batch<V, n, 1, n, +1, TZ, kZBlock>(tw, [&](int f) { return col + f * PITCH; });
+  }
   __syncthreads();
   staged_copy<n * TZ, kZBlock>(
       [&](int i) { return col[(i % TZ) * PITCH + i / TZ]; },
-      [&](int i, V x) { dspec[base + size_t(i / TZ) * n * H + (i % TZ)] = x; });
+      [&](int i, V x) { dst[base + size_t(i / TZ) * AX + (i % TZ)] = x; });
+}
+
+// --------------------------------------------- row passes (large grids) ---
+
+// Forward x transform of RB rows (rows r = (b n + z) n + y of the real
+// field) per workgroup: real-to-complex with the kx = 0 / n/2 packing, into
+// the spectrum buffer as [b][z][y][kx].
+template <int NN> struct RowShape {
+  static constexpr int RB = 16;                       // rows per workgroup
+  static_assert(NN % RB == 0, "rows of a block must share a plane");
+};
+
+template <typename T, int NN>
+constexpr size_t rows_lds() {
+  const size_t b = (size_t(RowShape<NN>::RB) * (NN / 2 + 1) + NN) * 2 * sizeof(T);
+  return b < 2 * kPBlock * 8 ? 2 * kPBlock * 8 : b;
+}
+
+template <typename T, int NN>
+__global__ void __launch_bounds__(kZBlock)
+k_rows_fwd(const T* __restrict__ src, typename cplx_of<T>::type* __restrict__ spec,
+           const typename cplx_of<T>::type* __restrict__ twg, const Ctl* __restrict__ ctl) {
+  using V = typename cplx_of<T>::type;
+  constexpr int n = NN, H = NN / 2, LP = H + 1, RB = RowShape<NN>::RB;
+  if (ctl->stop) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  V* tw = reinterpret_cast<V*>(smem);
+  V* pl = tw + n;
+  const size_t r0 = size_t(blockIdx.x) * RB;
+  for (int i = threadIdx.x; i < n; i += kZBlock) tw[i] = twg[i];
+  const V* s = reinterpret_cast<const V*>(src + r0 * n);
+  staged_copy<RB * H, kZBlock>([&](int i) { return s[i]; },
+                               [&](int i, V x) { pl[(i / H) * LP + (i % H)] = x; });
+  __syncthreads();
+  fft_batch<V, H, 1, 2 * H, -1, RB, kZBlock>(tw, [&](int f) { return pl + f * LP; });
+  __syncthreads();
+  constexpr int half = H / 2;
+  for (int i = threadIdx.x; i < RB * (half + 1); i += kZBlock) {
+    const int y = i / (half + 1), k = i - y * (half + 1);
+    V* row = pl + y * LP;
+    if (k == 0) {
+      const V z0 = row[0];
+      row[0] = cmk<V>(z0.x + z0.y, z0.x - z0.y);   // packed (X_0, X_{n/2})
+    } else {
+      const int m = H - k;
+      const V zk = row[k], zm = row[m];
+      const V zmc = cconj(zm), zkc = cconj(zk);
+      const V ek = cscale(cadd(zk, zmc), T(0.5));
+      const V ok = cmul_i<V, -1>(cscale(csub(zk, zmc), T(0.5)));
+      row[k] = cadd(ek, cmul(tw[k], ok));
+      if (m != k) {
+        const V em = cscale(cadd(zm, zkc), T(0.5));
+        const V om = cmul_i<V, -1>(cscale(csub(zm, zkc), T(0.5)));
+        row[m] = cadd(em, cmul(tw[m], om));
+      }
+    }
+  }
+  __syncthreads();
+  V* dst = spec + r0 * H;
+  staged_copy<RB * H, kZBlock>([&](int i) { return pl[(i / H) * LP + (i % H)]; },
+                               [&](int i, V x) { dst[i] = x; });
 }
 
 // --------------------------------------------------- C: moment coupling ---
@@ -286,6 +363,92 @@ k_couple(typename cplx_of<T>::type* __restrict__ spec, const typename cplx_of<T>
 
 // ------------------------------------------- P: inverse + epilogue -------
 
+// Complex-to-real merge of RB packed spectral rows in LDS (pitch LP):
+// Z_k = (X_k + conj X_{H-k}) + i conj(w_k) (X_k - conj X_{H-k}); column 0
+// carries the real pair (X_0, X_{n/2}).
+template <typename V, typename T, int NN, int RB, int LP, int BLOCK>
+__device__ __forceinline__ void c2r_merge(V* pl, const V* tw) {
+  constexpr int H = NN / 2, half = H / 2;
+  for (int i = threadIdx.x; i < RB * (half + 1); i += BLOCK) {
+    const int y = i / (half + 1), k = i - y * (half + 1);
+    V* row = pl + y * LP;
+    if (k == 0) {
+      const V p0 = row[0];
+      row[0] = cmk<V>(p0.x + p0.y, p0.x - p0.y);
+    } else {
+      const int m = H - k;
+      const V xk = row[k], xm = row[m];
+      const V xmc = cconj(xm), xkc = cconj(xk);
+      row[k] = cadd(cadd(xk, xmc), cmul_i<V, +1>(cmul(cconj(tw[k]), csub(xk, xmc))));
+      if (m != k) row[m] = cadd(cadd(xm, xkc), cmul_i<V, +1>(cmul(cconj(tw[m]), csub(xm, xkc))));
+    }
+  }
+}
+
+// Pointwise epilogue of RB rows starting at row y0 of plane (b, z):
+// o = u + w + h (-Sigma_l v + q) on (x_{2j}, x_{2j+1}) pairs; after the last
+// stage also phi_int += dt o (FP64) for the fluence moment and the partial
+// sums of (o - u)^2 and o^2.
+template <typename V, typename T, int NN, int RB, int LP, int BLOCK, bool FIRST, bool LAST>
+__device__ __forceinline__ void epilogue(const V* pl, int y0, int b, int z, const T* vin, T* u,
+                                         T* dst, const T* __restrict__ sig, const T* __restrict__ q,
+                                         bool hasq, double* __restrict__ phi_int, T h, double dt,
+                                         double& acc_d, double& acc_o) {
+  constexpr int n = NN, H = NN / 2;
+  const int l = isqrt_c(b);
+  const size_t poff = (size_t(b) * n + z) * n * n + size_t(y0) * n;
+  const size_t voff = size_t(z) * n * n + size_t(y0) * n;
+  const T* sg = sig + size_t(l) * n * n * n + voff;
+#pragma unroll 4
+  for (int i = threadIdx.x; i < RB * H; i += BLOCK) {
+    const int y = i / H, j = i - y * H;
+    const int e = y * n + 2 * j;
+    const V w = pl[y * LP + j];
+    const V uu = *reinterpret_cast<const V*>(u + poff + e);
+    const V vv = FIRST ? uu : *reinterpret_cast<const V*>(vin + poff + e);
+    const V ss = *reinterpret_cast<const V*>(sg + e);
+    T src0 = -ss.x * vv.x, src1 = -ss.y * vv.y;
+    if (hasq) {
+      const V qq = *reinterpret_cast<const V*>(q + poff + e);
+      src0 += qq.x;
+      src1 += qq.y;
+    }
+    const V o = cmk<V>(uu.x + w.x + h * src0, uu.y + w.y + h * src1);
+    *reinterpret_cast<V*>(dst + poff + e) = o;
+    if (LAST && b == 0) {
+      double2* pi = reinterpret_cast<double2*>(phi_int + voff + e);
+      double2 acc = *pi;
+      acc.x += dt * double(o.x);
+      acc.y += dt * double(o.y);
+      *pi = acc;
+      const double d0 = double(o.x) - double(uu.x), d1 = double(o.y) - double(uu.y);
+      acc_d += d0 * d0 + d1 * d1;
+      acc_o += double(o.x) * double(o.x) + double(o.y) * double(o.y);
+    }
+  }
+}
+
+// Deterministic block sum of two FP64 values (fixed tree), written to out[0..1].
+template <int BLOCK>
+__device__ __forceinline__ void block_sum2(unsigned char* smem, double a, double c, double* out) {
+  __syncthreads();
+  double* red = reinterpret_cast<double*>(smem);
+  red[threadIdx.x] = a;
+  red[BLOCK + threadIdx.x] = c;
+  __syncthreads();
+  for (int s = BLOCK / 2; s > 0; s >>= 1) {
+    if (int(threadIdx.x) < s) {
+      red[threadIdx.x] += red[threadIdx.x + s];
+      red[BLOCK + threadIdx.x] += red[BLOCK + threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = red[0];
+    out[1] = red[BLOCK];
+  }
+}
+
 template <typename T, int NN, bool FIRST, bool LAST>
 __global__ void __launch_bounds__(kPBlock)
 k_inv_plane(const typename cplx_of<T>::type* __restrict__ spec, const T* vin, T* u, T* dst,
@@ -312,78 +475,52 @@ k_inv_plane(const typename cplx_of<T>::type* __restrict__ spec, const T* vin, T*
   __syncthreads();
   fft_batch<V, n, LP, n, +1, H, kPBlock>(tw, [&](int f) { return pl + f; });
   __syncthreads();
-  // complex-to-real merge: Z_k = (X_k + conj X_{H-k}) + i conj(w_k) (X_k - conj X_{H-k});
-  // column 0 carries the real pair (X_0, X_{n/2}).
-  constexpr int half = H / 2;
-  for (int i = threadIdx.x; i < n * (half + 1); i += kPBlock) {
-    const int y = i / (half + 1), k = i - y * (half + 1);
-    V* row = pl + y * LP;
-    if (k == 0) {
-      const V p0 = row[0];
-      row[0] = cmk<V>(p0.x + p0.y, p0.x - p0.y);
-    } else {
-      const int m = H - k;
-      const V xk = row[k], xm = row[m];
-      const V xmc = cconj(xm), xkc = cconj(xk);
-      row[k] = cadd(cadd(xk, xmc), cmul_i<V, +1>(cmul(cconj(tw[k]), csub(xk, xmc))));
-      if (m != k) row[m] = cadd(cadd(xm, xkc), cmul_i<V, +1>(cmul(cconj(tw[m]), csub(xm, xkc))));
-    }
-  }
+  c2r_merge<V, T, NN, n, LP, kPBlock>(pl, tw);
   __syncthreads();
   fft_batch<V, H, 1, 2 * H, +1, n, kPBlock>(tw, [&](int f) { return pl + f * LP; });
   __syncthreads();
-  // epilogue on (x_{2j}, x_{2j+1}) pairs
-  const int l = isqrt_c(b);
-  const size_t poff = size_t(plane) * n * n;
-  const size_t voff = size_t(z) * n * n;
-  const T* sg = sig + size_t(l) * n * n * n + voff;
-  const bool hasq = (q != nullptr) && qflag[z];
   double acc_d = 0.0, acc_o = 0.0;
-#pragma unroll 4
-  for (int i = threadIdx.x; i < n * H; i += kPBlock) {
-    const int y = i / H, j = i - y * H;
-    const int e = y * n + 2 * j;
-    const V w = pl[y * LP + j];
-    const V uu = *reinterpret_cast<const V*>(u + poff + e);
-    const V vv = FIRST ? uu : *reinterpret_cast<const V*>(vin + poff + e);
-    const V ss = *reinterpret_cast<const V*>(sg + e);
-    T src0 = -ss.x * vv.x, src1 = -ss.y * vv.y;
-    if (hasq) {
-      const V qq = *reinterpret_cast<const V*>(q + poff + e);
-      src0 += qq.x;
-      src1 += qq.y;
-    }
-    const V o = cmk<V>(uu.x + w.x + h * src0, uu.y + w.y + h * src1);
-    *reinterpret_cast<V*>(dst + poff + e) = o;
-    if (LAST && b == 0) {
-      double2* pi = reinterpret_cast<double2*>(phi_int + voff + e);
-      double2 acc = *pi;
-      acc.x += dt * double(o.x);
-      acc.y += dt * double(o.y);
-      *pi = acc;
-      const double d0 = double(o.x) - double(uu.x), d1 = double(o.y) - double(uu.y);
-      acc_d += d0 * d0 + d1 * d1;
-      acc_o += double(o.x) * double(o.x) + double(o.y) * double(o.y);
-    }
-  }
-  if (LAST && b == 0) {
-    __syncthreads();
-    double* red = reinterpret_cast<double*>(smem);
-    red[threadIdx.x] = acc_d;
-    red[kPBlock + threadIdx.x] = acc_o;
-    __syncthreads();
-    for (int s = kPBlock / 2; s > 0; s >>= 1) {
-      if (threadIdx.x < s) {
-        red[threadIdx.x] += red[threadIdx.x + s];
-        red[kPBlock + threadIdx.x] += red[kPBlock + threadIdx.x + s];
-      }
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-      partial[2 * z] = red[0];
-      partial[2 * z + 1] = red[kPBlock];
-    }
-  }
+  const bool hasq = (q != nullptr) && qflag[z];
+  epilogue<V, T, NN, n, LP, kPBlock, FIRST, LAST>(pl, 0, b, z, vin, u, dst, sig, q, hasq, phi_int, h, dt,
+                                                  acc_d, acc_o);
+  if (LAST && b == 0) block_sum2<kPBlock>(smem, acc_d, acc_o, partial + 2 * z);
+}
+
+// Inverse x transform + epilogue of RB rows per workgroup (grids whose
+// plane does not fit in LDS; the y transform ran before as a pencil pass).
+// Logical order (z, row block, moment) so moments sharing loss rows are
+// neighbours on one XCD.
+template <typename T, int NN, bool FIRST, bool LAST>
+__global__ void __launch_bounds__(kZBlock)
+k_rows_inv(const typename cplx_of<T>::type* __restrict__ spec, const T* vin, T* u, T* dst,
+           const T* __restrict__ sig, const T* __restrict__ q, const int* __restrict__ qflag,
+           double* __restrict__ phi_int, double* __restrict__ partial,
+           const typename cplx_of<T>::type* __restrict__ twg, int M, T h, double dt,
+           const Ctl* __restrict__ ctl) {
+  using V = typename cplx_of<T>::type;
+  constexpr int n = NN, H = NN / 2, LP = H + 1, RB = RowShape<NN>::RB, NB = NN / RB;
+  if (ctl->stop) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  V* tw = reinterpret_cast<V*>(smem);
+  V* pl = tw + n;
+  const int lt = xcd_tile(blockIdx.x, gridDim.x);
+  const int b = lt % M, zy = lt / M;
+  const int z = zy / NB, yb = zy - z * NB;
+  const int y0 = yb * RB;
+  for (int i = threadIdx.x; i < n; i += kZBlock) tw[i] = twg[i];
+  const V* srcp = spec + ((size_t(b) * n + z) * n + y0) * H;
+  staged_copy<RB * H, kZBlock>([&](int i) { return srcp[i]; },
+                               [&](int i, V x) { pl[(i / H) * LP + (i % H)] = x; });
+  __syncthreads();
+  c2r_merge<V, T, NN, RB, LP, kZBlock>(pl, tw);
+  __syncthreads();
+  fft_batch<V, H, 1, 2 * H, +1, RB, kZBlock>(tw, [&](int f) { return pl + f * LP; });
+  __syncthreads();
+  double acc_d = 0.0, acc_o = 0.0;
+  const bool hasq = (q != nullptr) && qflag[z];
+  epilogue<V, T, NN, RB, LP, kZBlock, FIRST, LAST>(pl, y0, b, z, vin, u, dst, sig, q, hasq, phi_int, h, dt,
+                                                   acc_d, acc_o);
+  if (LAST && b == 0) block_sum2<kZBlock>(smem, acc_d, acc_o, partial + 2 * zy);
 }
 
 // ------------------------------------------------------- end of step ---
@@ -392,17 +529,30 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_end_step(const T* __restrict__ u, const long long* __restrict__ det, int ndet,
            double* __restrict__ readings, double* __restrict__ resid, long long cap,
-           const double* __restrict__ partial, int n, Ctl* ctl) {
+           const double* __restrict__ partial, int npart, Ctl* ctl) {
+  __shared__ double red[2 * kBlock];
   if (ctl->stop) return;
   const long long s = ctl->step;
   if (s < cap)
-    for (int p = threadIdx.x; p < ndet; p += blockDim.x) readings[s * ndet + p] = double(u[det[p]]);
-  if (threadIdx.x == 0) {
-    double d2 = 0.0, o2 = 0.0;
-    for (int z = 0; z < n; ++z) {
-      d2 += partial[2 * z];
-      o2 += partial[2 * z + 1];
+    for (int p = threadIdx.x; p < ndet; p += kBlock) readings[s * ndet + p] = double(u[det[p]]);
+  // deterministic: fixed per-thread strides, then a fixed tree
+  double pd = 0.0, po = 0.0;
+  for (int i = threadIdx.x; i < npart; i += kBlock) {
+    pd += partial[2 * i];
+    po += partial[2 * i + 1];
+  }
+  red[threadIdx.x] = pd;
+  red[kBlock + threadIdx.x] = po;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w) {
+      red[threadIdx.x] += red[threadIdx.x + w];
+      red[kBlock + threadIdx.x] += red[kBlock + threadIdx.x + w];
     }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double d2 = red[0], o2 = red[kBlock];
     const double r = o2 > 0.0 ? sqrt(d2 / o2) : 0.0;
     if (s < cap) resid[s] = r;
     ctl->last_resid = r;
@@ -415,22 +565,41 @@ k_end_step(const T* __restrict__ u, const long long* __restrict__ det, int ndet,
 
 // ------------------------------------------------------------ launch ---
 
+// Grids up to 128 points per axis keep a whole plane in LDS (plane passes);
+// larger grids split each plane pass into a row pass and a y-pencil pass.
+template <int NN> constexpr bool split_planes() { return NN > 128; }
+
 template <typename T, int NN, int N>
 hipError_t prepare_t(const StepArgs& a) {
   hipError_t e = hipSuccess;
   auto set = [&](const void* f, size_t bytes) {
     if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
   };
-  set(reinterpret_cast<const void*>(&k_fwd_plane<T, NN>), plane_lds<T, NN>());
-  set(reinterpret_cast<const void*>(&k_inv_plane<T, NN, true, false>), plane_lds<T, NN>());
-  set(reinterpret_cast<const void*>(&k_inv_plane<T, NN, false, false>), plane_lds<T, NN>());
-  set(reinterpret_cast<const void*>(&k_inv_plane<T, NN, false, true>), plane_lds<T, NN>());
-  set(reinterpret_cast<const void*>(&k_zderiv<T, NN>), zd_lds<T, NN>());
+  if constexpr (split_planes<NN>()) {
+    set(reinterpret_cast<const void*>(&k_rows_fwd<T, NN>), rows_lds<T, NN>());
+    set(reinterpret_cast<const void*>(&k_rows_inv<T, NN, true, false>), rows_lds<T, NN>());
+    set(reinterpret_cast<const void*>(&k_rows_inv<T, NN, false, false>), rows_lds<T, NN>());
+    set(reinterpret_cast<const void*>(&k_rows_inv<T, NN, false, true>), rows_lds<T, NN>());
+    set(reinterpret_cast<const void*>(&k_pencil<T, NN, PENCIL_YFWD>), zd_lds<T, NN>());
+    set(reinterpret_cast<const void*>(&k_pencil<T, NN, PENCIL_YINV>), zd_lds<T, NN>());
+  } else {
+    set(reinterpret_cast<const void*>(&k_fwd_plane<T, NN>), plane_lds<T, NN>());
+    set(reinterpret_cast<const void*>(&k_inv_plane<T, NN, true, false>), plane_lds<T, NN>());
+    set(reinterpret_cast<const void*>(&k_inv_plane<T, NN, false, false>), plane_lds<T, NN>());
+    set(reinterpret_cast<const void*>(&k_inv_plane<T, NN, false, true>), plane_lds<T, NN>());
+  }
+  set(reinterpret_cast<const void*>(&k_pencil<T, NN, PENCIL_ZDERIV>), zd_lds<T, NN>());
   return e;
 }
 
+// Number of per-block fluence-change partial sums written by the last
+// stage (one per z-plane, or one per row block on split grids).
+template <int NN> constexpr int partial_count() {
+  return split_planes<NN>() ? NN * (NN / RowShape<NN>::RB) : NN;
+}
+
 template <typename T, int NN, int N>
-hipError_t enqueue_t(const StepArgs& a, hipEvent_t* ev) {
+hipError_t enqueue_t(const StepArgs& a, ProfRec* pr) {
   using V = typename cplx_of<T>::type;
   using Z = ZdShape<T, NN>;
   constexpr int M = (N + 1) * (N + 1);
@@ -449,38 +618,68 @@ hipError_t enqueue_t(const StepArgs& a, hipEvent_t* ev) {
   const double alphas[4] = {0.25, 1.0 / 3.0, 0.5, 1.0};
   const dim3 blk(kBlock), pblk(kPBlock), zblk(kZBlock), cblk(kCBlock);
   const int planes = M * NN;
-  const int zblocks = M * NN * Z::NTILE;
+  const int pencils = M * NN * Z::NTILE;
   const int cblocks = (NN * NN * (NN / 2) + kCBlock - 1) / kCBlock;
-  const size_t lp = plane_lds<T, NN>(), lz = zd_lds<T, NN>();
-  int mark = 0;
-  auto rec = [&]() {
-    if (ev) (void)hipEventRecord(ev[mark++], st);
+  const int rblocks = M * NN * (NN / RowShape<NN>::RB);
+  const size_t lp = plane_lds<T, NN>(), lz = zd_lds<T, NN>(), lr = rows_lds<T, NN>();
+  auto rec = [&](int cls) {
+    if (pr && pr->count < kMaxProfLaunches) {
+      (void)hipEventRecord(static_cast<hipEvent_t>(pr->ev[pr->count]), st);
+      pr->cls[pr->count++] = cls;
+    }
   };
-  rec();
+  if (pr) {
+    (void)hipEventRecord(static_cast<hipEvent_t>(pr->ev0), st);
+    pr->count = 0;
+  }
   for (int s = 0; s < 4; ++s) {
     const double hs = alphas[s] * a.dt * a.c;
     const T* src = s == 0 ? u : v;
-    hipLaunchKernelGGL((k_fwd_plane<T, NN>), dim3(planes), pblk, lp, st, src, spec, tw, cctl);
-    rec();
-    hipLaunchKernelGGL((k_zderiv<T, NN>), dim3(zblocks), zblk, lz, st, spec, dspec, tw, kv, cctl);
-    rec();
+    T* out = s == 3 ? u : v;
+    if constexpr (split_planes<NN>()) {
+      hipLaunchKernelGGL((k_rows_fwd<T, NN>), dim3(rblocks), zblk, lr, st, src, spec, tw, cctl);
+      rec(PROF_FWD_ROWS);
+      hipLaunchKernelGGL((k_pencil<T, NN, PENCIL_YFWD>), dim3(pencils), zblk, lz, st, spec, spec, tw, kv, cctl);
+      rec(PROF_Y_FWD);
+    } else {
+      hipLaunchKernelGGL((k_fwd_plane<T, NN>), dim3(planes), pblk, lp, st, src, spec, tw, cctl);
+      rec(PROF_FWD_PLANE);
+    }
+    hipLaunchKernelGGL((k_pencil<T, NN, PENCIL_ZDERIV>), dim3(pencils), zblk, lz, st, spec, dspec, tw, kv,
+                       cctl);
+    rec(PROF_ZDERIV);
     hipLaunchKernelGGL((k_couple<T, NN, N>), dim3(cblocks), cblk, 0, st, spec, dspec, kv, coef, T(hs / n2),
                        cctl);
-    rec();
-    if (s == 0)
-      hipLaunchKernelGGL((k_inv_plane<T, NN, true, false>), dim3(planes), pblk, lp, st, spec, src, u, v, sig,
-                         q, a.qflag, a.phi_int, a.partial, tw, M, T(hs), a.dt, cctl);
-    else if (s < 3)
-      hipLaunchKernelGGL((k_inv_plane<T, NN, false, false>), dim3(planes), pblk, lp, st, spec, src, u, v,
-                         sig, q, a.qflag, a.phi_int, a.partial, tw, M, T(hs), a.dt, cctl);
-    else
-      hipLaunchKernelGGL((k_inv_plane<T, NN, false, true>), dim3(planes), pblk, lp, st, spec, src, u, u, sig,
-                         q, a.qflag, a.phi_int, a.partial, tw, M, T(hs), a.dt, cctl);
-    rec();
+    rec(PROF_COUPLE);
+    if constexpr (split_planes<NN>()) {
+      hipLaunchKernelGGL((k_pencil<T, NN, PENCIL_YINV>), dim3(pencils), zblk, lz, st, spec, spec, tw, kv, cctl);
+      rec(PROF_Y_INV);
+      if (s == 0)
+        hipLaunchKernelGGL((k_rows_inv<T, NN, true, false>), dim3(rblocks), zblk, lr, st, spec, src, u, out,
+                           sig, q, a.qflag, a.phi_int, a.partial, tw, M, T(hs), a.dt, cctl);
+      else if (s < 3)
+        hipLaunchKernelGGL((k_rows_inv<T, NN, false, false>), dim3(rblocks), zblk, lr, st, spec, src, u, out,
+                           sig, q, a.qflag, a.phi_int, a.partial, tw, M, T(hs), a.dt, cctl);
+      else
+        hipLaunchKernelGGL((k_rows_inv<T, NN, false, true>), dim3(rblocks), zblk, lr, st, spec, src, u, out,
+                           sig, q, a.qflag, a.phi_int, a.partial, tw, M, T(hs), a.dt, cctl);
+      rec(PROF_INV_ROWS);
+    } else {
+      if (s == 0)
+        hipLaunchKernelGGL((k_inv_plane<T, NN, true, false>), dim3(planes), pblk, lp, st, spec, src, u, out,
+                           sig, q, a.qflag, a.phi_int, a.partial, tw, M, T(hs), a.dt, cctl);
+      else if (s < 3)
+        hipLaunchKernelGGL((k_inv_plane<T, NN, false, false>), dim3(planes), pblk, lp, st, spec, src, u, out,
+                           sig, q, a.qflag, a.phi_int, a.partial, tw, M, T(hs), a.dt, cctl);
+      else
+        hipLaunchKernelGGL((k_inv_plane<T, NN, false, true>), dim3(planes), pblk, lp, st, spec, src, u, out,
+                           sig, q, a.qflag, a.phi_int, a.partial, tw, M, T(hs), a.dt, cctl);
+      rec(PROF_INV_PLANE);
+    }
   }
   hipLaunchKernelGGL((k_end_step<T>), dim3(1), blk, 0, st, u, a.det, a.ndet, a.readings, a.resid, a.cap,
-                     a.partial, NN, static_cast<Ctl*>(a.ctl));
-  rec();
+                     a.partial, partial_count<NN>(), static_cast<Ctl*>(a.ctl));
+  rec(PROF_END);
   return hipGetLastError();
 }
 
@@ -507,7 +706,7 @@ hipError_t dispatch_tn(const StepArgs& a, Args... args) {
 }
 
 template <typename T, int NN, int N> struct EnqueueFn {
-  static hipError_t call(const StepArgs& a, hipEvent_t* ev) { return enqueue_t<T, NN, N>(a, ev); }
+  static hipError_t call(const StepArgs& a, ProfRec* pr) { return enqueue_t<T, NN, N>(a, pr); }
 };
 template <typename T, int NN, int N> struct PrepareFn {
   static hipError_t call(const StepArgs& a) { return prepare_t<T, NN, N>(a); }
@@ -515,8 +714,8 @@ template <typename T, int NN, int N> struct PrepareFn {
 
 // Defines the per-size entry points used by the runtime.
 #define RTE_DEFINE_SIZE(NN)                                                              \
-  int enqueue_step_n##NN(const StepArgs& a, void* ev) {                                  \
-    return int(dispatch_tn<EnqueueFn, NN>(a, static_cast<hipEvent_t*>(ev)));             \
+  int enqueue_step_n##NN(const StepArgs& a, void* pr) {                                  \
+    return int(dispatch_tn<EnqueueFn, NN>(a, static_cast<ProfRec*>(pr)));                \
   }                                                                                      \
   int prepare_n##NN(const StepArgs& a) { return int(dispatch_tn<PrepareFn, NN>(a)); }
 

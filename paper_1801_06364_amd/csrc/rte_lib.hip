@@ -37,9 +37,10 @@ inline bool config_ok(const rte_config* c) {
   if (c->pml_width > 0 && (!(c->pml_mu0 >= 0) || !(c->pml_mu1 >= 0))) return false;
   if (c->n_det < 0 || (c->n_det > 0 && !c->det_index)) return false;
   if (c->record_steps < 0) return false;
-  // plane passes keep one n x (n/2+1) complex plane in LDS (160 KB per CU)
+  // grids up to 128 keep one n x (n/2+1) complex plane in LDS (160 KB per
+  // CU); larger grids use row + pencil passes
   const size_t s = c->precision == RTE_FP64 ? 16 : 8;
-  if ((size_t(c->n) * (c->n / 2 + 1) + c->n) * s > 160 * 1024) return false;
+  if (c->n <= 128 && (size_t(c->n) * (c->n / 2 + 1) + c->n) * s > 160 * 1024) return false;
   return true;
 }
 
@@ -62,7 +63,7 @@ inline Layout layout_of(const rte_config* c, bool has_q) {
   L.det = o; o = up(o + size_t(c->n_det) * 8);
   L.readings = o; o = up(o + size_t(c->record_steps) * c->n_det * 8);
   L.resid = o; o = up(o + size_t(c->record_steps) * 8);
-  L.partial = o; o = up(o + n * 2 * 8);
+  L.partial = o; o = up(o + n * n * 2 * 8);
   L.phi_int = o; o = up(o + V * 8);
   L.ctl = o; o = up(o + sizeof(Ctl));
   L.total = o;
@@ -75,12 +76,14 @@ int enqueue_step_n48(const StepArgs& a, void* ev);
 int enqueue_step_n64(const StepArgs& a, void* ev);
 int enqueue_step_n96(const StepArgs& a, void* ev);
 int enqueue_step_n128(const StepArgs& a, void* ev);
+int enqueue_step_n256(const StepArgs& a, void* ev);
 int prepare_n16(const StepArgs& a);
 int prepare_n32(const StepArgs& a);
 int prepare_n48(const StepArgs& a);
 int prepare_n64(const StepArgs& a);
 int prepare_n96(const StepArgs& a);
 int prepare_n128(const StepArgs& a);
+int prepare_n256(const StepArgs& a);
 
 int launch_enqueue_step(int n, const StepArgs& a, void* ev) {
   switch (n) {
@@ -90,6 +93,7 @@ int launch_enqueue_step(int n, const StepArgs& a, void* ev) {
     case 64: return enqueue_step_n64(a, ev);
     case 96: return enqueue_step_n96(a, ev);
     case 128: return enqueue_step_n128(a, ev);
+    case 256: return enqueue_step_n256(a, ev);
     default: return int(hipErrorInvalidValue);
   }
 }
@@ -102,6 +106,7 @@ int launch_prepare(int n, const StepArgs& a) {
     case 64: return prepare_n64(a);
     case 96: return prepare_n96(a);
     case 128: return prepare_n128(a);
+    case 256: return prepare_n256(a);
     default: return int(hipErrorInvalidValue);
   }
 }
@@ -466,35 +471,38 @@ int rte_coupling_dense(int32_t order_N, double* bx, double* by, double* bz) {
 int rte_profile_kernels(rte_handle* h, int64_t nsteps, double* ms, int64_t* counts) {
   using namespace rte;
   if (!h || !ms || !counts || nsteps < 0) return RTE_EINVAL;
-  constexpr int kLaunches = 17;
-  constexpr int kClasses = 5;
-  hipEvent_t ev[kLaunches + 1];
-  for (int i = 0; i <= kLaunches; ++i)
+  ProfRec pr{};
+  hipEvent_t e0;
+  hipEvent_t ev[kMaxProfLaunches];
+  if (hipEventCreate(&e0) != hipSuccess) return RTE_EDEVICE;
+  for (int i = 0; i < kMaxProfLaunches; ++i)
     if (hipEventCreate(&ev[i]) != hipSuccess) return RTE_EDEVICE;
-  for (int c = 0; c < kClasses; ++c) {
+  pr.ev0 = e0;
+  for (int i = 0; i < kMaxProfLaunches; ++i) pr.ev[i] = ev[i];
+  for (int c = 0; c < PROF_CLASSES; ++c) {
     ms[c] = 0.0;
     counts[c] = 0;
   }
   int rc = RTE_OK;
   for (int64_t s = 0; s < nsteps && rc == RTE_OK; ++s) {
-    hipError_t e = hipError_t(launch_enqueue_step(h->n, h->args, ev));
-    if (e == hipSuccess) e = hipEventSynchronize(ev[kLaunches]);
+    hipError_t e = hipError_t(launch_enqueue_step(h->n, h->args, &pr));
+    if (e == hipSuccess && pr.count > 0) e = hipEventSynchronize(ev[pr.count - 1]);
     if (e != hipSuccess) {
       rc = RTE_EDEVICE;
       break;
     }
-    for (int i = 0; i < kLaunches; ++i) {
+    for (int i = 0; i < pr.count; ++i) {
       float t = 0.f;
-      if (hipEventElapsedTime(&t, ev[i], ev[i + 1]) != hipSuccess) {
+      if (hipEventElapsedTime(&t, i == 0 ? e0 : ev[i - 1], ev[i]) != hipSuccess) {
         rc = RTE_EDEVICE;
         break;
       }
-      const int cls = i == kLaunches - 1 ? kClasses - 1 : i % 4;
-      ms[cls] += t;
-      counts[cls] += 1;
+      ms[pr.cls[i]] += t;
+      counts[pr.cls[i]] += 1;
     }
   }
-  for (int i = 0; i <= kLaunches; ++i) (void)hipEventDestroy(ev[i]);
+  (void)hipEventDestroy(e0);
+  for (int i = 0; i < kMaxProfLaunches; ++i) (void)hipEventDestroy(ev[i]);
   return rc;
 }
 

@@ -218,7 +218,7 @@ void potentials(int n, int N, int W, double mu0, double mu1,
 
 bool grid_supported(int n) {
   switch (n) {
-    case 16: case 32: case 48: case 64: case 96: case 128: return true;
+    case 16: case 32: case 48: case 64: case 96: case 128: case 256: return true;
     default: return false;
   }
 }

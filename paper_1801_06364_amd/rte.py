@@ -26,7 +26,8 @@ EXPORTS = (
     "rte_set_state", "rte_coupling_dense", "rte_profile_kernels", "rte_destroy",
     "rte_strerror",
 )
-KERNEL_CLASSES = ("fwd_plane", "zderiv", "couple", "inv_plane", "end_step")
+KERNEL_CLASSES = ("fwd_plane", "zderiv", "couple", "inv_plane", "end_step",
+                  "fwd_rows", "y_fwd", "y_inv", "inv_rows")
 
 
 class RteError(RuntimeError):
@@ -234,7 +235,7 @@ class Solver:
         _check(lib().rte_profile_kernels(self.h, int(nsteps), _dptr(ms),
                                          cnt.ctypes.data_as(C.POINTER(C.c_int64))),
                "rte_profile_kernels")
-        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNEL_CLASSES)}
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNEL_CLASSES) if cnt[i]}
 
     def close(self):
         if getattr(self, "h", None):

@@ -44,7 +44,7 @@ def test_workspace_bytes_cover_state_and_spectrum(n, N, prec):
     assert floor <= b <= floor * 2
 
 
-@pytest.mark.parametrize("bad", [dict(n=100), dict(n=256, precision=rte.RTE_FP64), dict(N=8),
+@pytest.mark.parametrize("bad", [dict(n=100), dict(n=512), dict(N=8),
                                  dict(N=-1), dict(W=16, n=32), dict(dx=0.0), dict(c=-1.0),
                                  dict(precision=7)])
 def test_invalid_configs_rejected(bad):

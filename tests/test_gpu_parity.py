@@ -128,6 +128,63 @@ def test_single_fourier_mode_full_size(torch_cuda, prec):
     s.close()
 
 
+def test_split_grid_256_against_oracle(torch_cuda):
+    """The 256^3 grid runs the row + pencil pass variant (a plane does not
+    fit in LDS): one RK4 step of a P_1 heterogeneous phantom with absorbing
+    layer, FP32, element by element against the FP64 oracle."""
+    n, N = 256, 1
+    print("\n[parity] split grid 256^3 P_1 f32, 1 step", flush=True)
+    mu_a, mu_s, g = ri.sphere_maps(n, 32, 3, seed=7, radius=(8, 32))
+    psi0 = ri.gaussian_ic(n, N, sigma=3.0)
+    psi0[1:] = 0.3 * psi0[0]
+    wl = ri.Workload("split", n, N, "f32", 0.25, 0.3, 0.2 * 0.25 / 0.3, 32, 0.01, 1.0, 1,
+                     mu_a, mu_s, g, psi0, None)
+    s = _solver(wl)
+    s.step(1)
+    st = s.get_state()
+    s.close()
+    ref = pn.solve(n, N, wl.dx, wl.c, wl.dt, mu_a, mu_s, g, psi0, None, wl.W, wl.mu0, wl.mu1, 1)
+    assert rel(st, ref["state"]) <= TOL["f32"]
+
+
+def test_single_fourier_mode_256_p5(torch_cuda):
+    """Full 256^3 / P_5 / FP32 size: single Fourier mode against the closed
+    form R(dt M(k))^n, element by element."""
+    n, N, dx, c = 256, 5, 0.25, 0.3
+    M = (N + 1) ** 2
+    steps = 3
+    dt = 0.2 * dx / c
+    rng = np.random.default_rng(5)
+    v = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+    f = (-7, 30, 101)
+    mua, mus, g = 0.01, 10.0, 0.85
+    ma, ms, gg = ri.homogeneous_maps(n, mua, mus, g)
+    psi0 = ri.fourier_mode_ic(n, N, f, v)
+    sig = [mua + mus * (1 - g ** l) for l in range(N + 1)]
+    k = pn.wavenumbers(n, dx)
+    kv = (k[f[0]], k[f[1]], k[f[2]])
+    U = pn.real_basis_transform(N)
+    Rk = np.linalg.matrix_power(pn.rk4_poly(dt * pn.mode_matrix(N, kv, sig, c)), steps)
+    Rmk = np.linalg.matrix_power(pn.rk4_poly(dt * pn.mode_matrix(N, tuple(-t for t in kv), sig, c)), steps)
+    aR = U.conj() @ (Rk @ (U.T @ v))
+    aRm = U.conj() @ (Rmk @ (U.T @ v.conj()))
+    s = _solver(ri.Workload("mode256", n, N, "f32", dx, c, dt, 0, 0.01, 1.0, steps, ma, ms, gg,
+                            psi0, None))
+    del psi0
+    s.step(steps)
+    st = s.get_state()
+    s.close()
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    ph = np.exp(2j * np.pi * (f[0] * x + f[1] * y + f[2] * z) / n)
+    del z, y, x
+    err2 = ref2 = 0.0
+    for a in range(M):
+        ref = (0.5 * (aR[a] * ph + aRm[a] * ph.conj())).real
+        err2 += float(((st[a] - ref) ** 2).sum())
+        ref2 += float((ref ** 2).sum())
+    assert np.sqrt(err2 / ref2) <= TOL["f32"]
+
+
 def test_photon_number_conserved_on_gpu(torch_cuda):
     """mu_a = 0, no absorbing layer: sum of psi_0^0 is invariant (FP64)."""
     n, N = 64, 3
