@@ -142,6 +142,31 @@ int rte_set_state(rte_handle* h, const double* in, size_t len);
  * device needed. */
 int rte_coupling_dense(int32_t order_N, double* bx, double* by, double* bz);
 
+/* ---- Discrete adjoint (gradients of detector readings) ----------------
+ * The derivative of a scalar loss J(readings) with respect to mu_a(r) and
+ * mu_s(r) through the exact transpose of the nested RK4 step (reverse mode
+ * of the discrete scheme), with the stage states recomputed from
+ * checkpoints of u kept every `every` steps (sqrt(steps) balances memory
+ * and recomputation). Inside the absorbing layer the loss does not depend
+ * on mu_a, mu_s (eq. 12) and the gradient is zero there.
+ *
+ * rte_adjoint_workspace_bytes: device bytes of the second workspace the two
+ * calls below share (ceil(steps/every) + every + 7 states plus FP64 maps).
+ *
+ * rte_forward_checkpointed: like rte_step(h, steps) from the current state,
+ * additionally saving u every `every` steps into adj_ws (caller-owned,
+ * 256-byte aligned). Readings are recorded as by rte_step.
+ *
+ * rte_adjoint: with dj_dr = dJ/d(reading) as a host FP64 array
+ * [steps][n_det] for the readings of that forward run, writes dJ/dmu_a and
+ * dJ/dmu_s (host FP64, n^3 each). Uses the checkpoints in adj_ws; leaves the
+ * handle's state, step count and record unchanged. Synchronises. */
+size_t rte_adjoint_workspace_bytes(const rte_config* cfg, int64_t steps, int64_t every);
+int rte_forward_checkpointed(rte_handle* h, int64_t steps, int64_t every, void* adj_ws,
+                             size_t adj_bytes);
+int rte_adjoint(rte_handle* h, int64_t steps, int64_t every, void* adj_ws, size_t adj_bytes,
+                const double* dj_dr, double* grad_mu_a, double* grad_mu_s);
+
 /* Run nsteps steps with plain launches, timing every kernel with HIP
  * events on the handle's stream, and store the summed milliseconds of each
  * kernel class in ms[0..8] and the launch counts in counts[0..8]. Classes:

@@ -18,5 +18,6 @@ from .pn import (  # noqa: F401
     alpha, beta, sh_index, sh_lm, coupling_matrices, real_basis_transform,
     wavenumbers, pml_depth, pml_profile, potentials, operator, rk4_step,
     solve, to_complex_basis, to_real_basis, mode_matrix, rk4_poly,
-    hg_phase, hg_legendre_moments,
+    hg_phase, hg_legendre_moments, real_coupling, operator_transpose,
+    adjoint_gradient,
 )

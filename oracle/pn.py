@@ -375,3 +375,121 @@ def hg_legendre_moments(g: float, L: int, nodes: int = 400) -> np.ndarray:
         Pl = np.polynomial.legendre.Legendre.basis(l)(x)
         out[l] = 2 * np.pi * np.sum(w * p * Pl)
     return out
+
+
+# ------------------------------------------- discrete adjoint (reverse) ---
+
+def real_coupling(N: int):
+    """Real-basis streaming matrices ``conj(U) B_j U^T`` (real up to
+    rounding), from the eq. (6) matrices and the quadrature-built U."""
+    U = real_basis_transform(N)
+    return tuple((U.conj() @ B @ U.T).real for B in coupling_matrices(N))
+
+
+def _spectral_derivative(f, k, axis):
+    """d f / d x_axis of a real periodic field (axis 0 = z, 1 = y, 2 = x),
+    via the FFT with the Nyquist wavenumber zero."""
+    shape = [1, 1, 1]
+    shape[axis] = k.size
+    fh = sfft.fftn(f, axes=(axis,), workers=WORKERS)
+    return sfft.ifftn(1j * k.reshape(shape) * fh, axes=(axis,), workers=WORKERS).real
+
+
+def operator_transpose(y, Sig, BR, k, c):
+    """Transpose (Euclidean, real basis) of the linear part of the operator:
+    ``L = -c (sum_j B_j d_j + Sigma)``; with ``d_j^T = -d_j`` (periodic,
+    skew spectral derivative) ``L^T y = -c (-sum_j B_j^T d_j y + Sigma y)``."""
+    M = y.shape[0]
+    N = int(math.isqrt(M)) - 1
+    out = np.zeros_like(y)
+    for j, axis in ((0, 2), (1, 1), (2, 0)):      # B_x acts along x (axis 2)
+        BT = BR[j].T
+        d = np.stack([_spectral_derivative(y[b], k, axis) for b in range(M)])
+        out -= np.tensordot(BT, d, axes=(1, 0))
+    for l in range(N + 1):
+        for m in range(-l, l + 1):
+            a = sh_index(l, m)
+            out[a] += Sig[l] * y[a]
+    return -c * out
+
+
+def adjoint_gradient(n, N, dx, c, dt, mu_a, mu_s, g, psi0_real, q_real, W, mu0,
+                     mu1, steps, det_index, dj_dr):
+    """Gradient of a loss J(readings) with respect to mu_a(r), mu_s(r) by the
+    reverse mode of the classic RK4 scheme that :func:`solve` integrates.
+
+    ``dj_dr[s, d]`` is dJ/d(reading of detector d after step s + 1). Forward
+    states are produced by the complex-basis solver; the reverse sweep runs
+    in the real basis with :func:`operator_transpose`. Returns
+    ``(grad_mu_a, grad_mu_s)``, each ``(n, n, n)``, zero in the layer
+    (there the loss is ``mu_b`` for every degree, eq. 12)."""
+    M = (N + 1) ** 2
+    B = coupling_matrices(N)
+    BR = real_coupling(N)
+    U = real_basis_transform(N)
+    k = wavenumbers(n, dx)
+    Sig, omega = potentials(mu_a, mu_s, g, N, W, mu0, mu1)
+    q = None
+    if q_real is not None:
+        q = to_complex_basis(np.asarray(q_real, float), U) * omega[None]
+
+    def f(y):
+        return operator(y, Sig, q, B, k, c)
+
+    psi = (to_complex_basis(np.asarray(psi0_real, float), U).astype(complex)
+           if psi0_real is not None else np.zeros((M, n, n, n), complex))
+    states = [psi]
+    for _ in range(steps):
+        psi = rk4_step(psi, f, dt)
+        states.append(psi)
+    det = np.asarray(det_index, np.int64)
+    lofa = np.array([sh_lm(a)[0] for a in range(M)])
+    gsig = np.zeros((N + 1, n, n, n))
+
+    def add_grad(kbar, y):
+        # d f / d Sigma_l = -c y_a for the moments a of degree l
+        prod = -c * kbar * y
+        for l in range(N + 1):
+            gsig[l] += prod[lofa == l].sum(axis=0)
+
+    lam = np.zeros((M, n, n, n))
+
+    def inject(s):
+        flat = lam[0].reshape(-1)
+        np.add.at(flat, det, dj_dr[s])
+
+    inject(steps - 1)
+    for s in range(steps - 1, -1, -1):
+        u = states[s]
+        k1 = f(u)
+        k2 = f(u + 0.5 * dt * k1)
+        k3 = f(u + 0.5 * dt * k2)
+        ys = [to_real_basis(u, U), to_real_basis(u + 0.5 * dt * k1, U),
+              to_real_basis(u + 0.5 * dt * k2, U), to_real_basis(u + dt * k3, U)]
+        kb = [dt / 6 * lam, dt / 3 * lam, dt / 3 * lam, dt / 6 * lam]
+        ub = lam.copy()
+        # stage 4: y4 = u + dt k3
+        yb = operator_transpose(kb[3], Sig, BR, k, c)
+        add_grad(kb[3], ys[3])
+        ub += yb
+        kb[2] = kb[2] + dt * yb
+        # stage 3: y3 = u + dt/2 k2
+        yb = operator_transpose(kb[2], Sig, BR, k, c)
+        add_grad(kb[2], ys[2])
+        ub += yb
+        kb[1] = kb[1] + 0.5 * dt * yb
+        # stage 2: y2 = u + dt/2 k1
+        yb = operator_transpose(kb[1], Sig, BR, k, c)
+        add_grad(kb[1], ys[1])
+        ub += yb
+        kb[0] = kb[0] + 0.5 * dt * yb
+        # stage 1: y1 = u
+        yb = operator_transpose(kb[0], Sig, BR, k, c)
+        add_grad(kb[0], ys[0])
+        ub += yb
+        lam = ub
+        if s >= 1:
+            inject(s - 1)
+    gmua = gsig.sum(axis=0) * omega
+    gmus = sum((1.0 - g ** l) * gsig[l] for l in range(N + 1)) * omega
+    return gmua, gmus

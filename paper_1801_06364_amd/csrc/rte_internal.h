@@ -131,10 +131,31 @@ struct ProfRec {
   int count;
 };
 
-// Per-grid-size entry points (one translation unit per n). enqueue_step
-// queues the kernels of one RK4 step; pr (a ProfRec*) is null except when
-// profiling.
-int launch_enqueue_step(int n, const StepArgs& a, void* pr);
+// Device operations queued by the per-grid-size entry points.
+enum {
+  OP_STEP = 0,       // one RK4 step with readings / integrated fluence / flags
+  OP_STAGE = 1,      // one forward stage into a given buffer (no bookkeeping)
+  OP_ADJ_STAGE = 2,  // one transposed stage: y = coef h F~(x), u += y
+  OP_ADJ_GRAD = 3,   // gradient accumulation from (x, y)
+  OP_ADJ_INJECT = 4  // detector adjoint sources into u
+};
+struct OpArgs {
+  int kind;
+  int stage;         // OP_STAGE: 0..2
+  double coef;       // OP_ADJ_STAGE / OP_ADJ_GRAD: RK stage coefficient
+  void* u;           // base state / accumulator
+  const void* x;     // stage input
+  void* y;           // stage output
+  const double* gin; // g inside the real domain, > 1 in the layer
+  double* gmua;      // gradient accumulators (FP64, n^3)
+  double* gmus;
+  const double* djdr;// adjoint sources of one step's readings (ndet)
+};
+
+// Per-grid-size entry points (one translation unit per n). enqueue_op
+// queues one operation; pr (a ProfRec*) is null except when profiling a
+// step.
+int launch_enqueue_op(int n, const StepArgs& a, const OpArgs& op, void* pr);
 int launch_prepare(int n, const StepArgs& a);
 
 }  // namespace rte

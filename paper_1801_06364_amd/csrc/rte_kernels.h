@@ -385,11 +385,17 @@ __device__ __forceinline__ void c2r_merge(V* pl, const V* tw) {
   }
 }
 
-// Pointwise epilogue of RB rows starting at row y0 of plane (b, z):
-// o = u + w + h (-Sigma_l v + q) on (x_{2j}, x_{2j+1}) pairs; after the last
-// stage also phi_int += dt o (FP64) for the fluence moment and the partial
-// sums of (o - u)^2 and o^2.
-template <typename V, typename T, int NN, int RB, int LP, int BLOCK, bool FIRST, bool LAST>
+// Epilogue modes of the inverse pass.
+enum { EPI_MID = 0, EPI_FIRST = 1, EPI_LAST = 2, EPI_ADJ = 3 };
+
+// Pointwise epilogue of RB rows starting at row y0 of plane (b, z), on
+// (x_{2j}, x_{2j+1}) pairs:
+//   forward stages  o = u + w + h (-Sigma_l v + q)   -> dst
+//     (EPI_FIRST: v = u; EPI_LAST: also phi_int += dt o (FP64) for the
+//     fluence moment and the partial sums of (o - u)^2 and o^2);
+//   EPI_ADJ         o = w - h Sigma_l v  -> dst, and u += o (u is the
+//     adjoint accumulator; no source term in the transposed operator).
+template <typename V, typename T, int NN, int RB, int LP, int BLOCK, int MODE>
 __device__ __forceinline__ void epilogue(const V* pl, int y0, int b, int z, const T* vin, T* u,
                                          T* dst, const T* __restrict__ sig, const T* __restrict__ q,
                                          bool hasq, double* __restrict__ phi_int, T h, double dt,
@@ -405,17 +411,23 @@ __device__ __forceinline__ void epilogue(const V* pl, int y0, int b, int z, cons
     const int e = y * n + 2 * j;
     const V w = pl[y * LP + j];
     const V uu = *reinterpret_cast<const V*>(u + poff + e);
-    const V vv = FIRST ? uu : *reinterpret_cast<const V*>(vin + poff + e);
+    const V vv = MODE == EPI_FIRST ? uu : *reinterpret_cast<const V*>(vin + poff + e);
     const V ss = *reinterpret_cast<const V*>(sg + e);
     T src0 = -ss.x * vv.x, src1 = -ss.y * vv.y;
-    if (hasq) {
+    if (MODE != EPI_ADJ && hasq) {
       const V qq = *reinterpret_cast<const V*>(q + poff + e);
       src0 += qq.x;
       src1 += qq.y;
     }
+    if constexpr (MODE == EPI_ADJ) {
+      const V o = cmk<V>(w.x + h * src0, w.y + h * src1);
+      *reinterpret_cast<V*>(dst + poff + e) = o;
+      *reinterpret_cast<V*>(u + poff + e) = cmk<V>(uu.x + o.x, uu.y + o.y);
+      continue;
+    }
     const V o = cmk<V>(uu.x + w.x + h * src0, uu.y + w.y + h * src1);
     *reinterpret_cast<V*>(dst + poff + e) = o;
-    if (LAST && b == 0) {
+    if (MODE == EPI_LAST && b == 0) {
       double2* pi = reinterpret_cast<double2*>(phi_int + voff + e);
       double2 acc = *pi;
       acc.x += dt * double(o.x);
@@ -449,7 +461,7 @@ __device__ __forceinline__ void block_sum2(unsigned char* smem, double a, double
   }
 }
 
-template <typename T, int NN, bool FIRST, bool LAST>
+template <typename T, int NN, int MODE>
 __global__ void __launch_bounds__(kPBlock)
 k_inv_plane(const typename cplx_of<T>::type* __restrict__ spec, const T* vin, T* u, T* dst,
             const T* __restrict__ sig, const T* __restrict__ q, const int* __restrict__ qflag,
@@ -481,16 +493,16 @@ k_inv_plane(const typename cplx_of<T>::type* __restrict__ spec, const T* vin, T*
   __syncthreads();
   double acc_d = 0.0, acc_o = 0.0;
   const bool hasq = (q != nullptr) && qflag[z];
-  epilogue<V, T, NN, n, LP, kPBlock, FIRST, LAST>(pl, 0, b, z, vin, u, dst, sig, q, hasq, phi_int, h, dt,
-                                                  acc_d, acc_o);
-  if (LAST && b == 0) block_sum2<kPBlock>(smem, acc_d, acc_o, partial + 2 * z);
+  epilogue<V, T, NN, n, LP, kPBlock, MODE>(pl, 0, b, z, vin, u, dst, sig, q, hasq, phi_int, h, dt, acc_d,
+                                           acc_o);
+  if (MODE == EPI_LAST && b == 0) block_sum2<kPBlock>(smem, acc_d, acc_o, partial + 2 * z);
 }
 
 // Inverse x transform + epilogue of RB rows per workgroup (grids whose
 // plane does not fit in LDS; the y transform ran before as a pencil pass).
 // Logical order (z, row block, moment) so moments sharing loss rows are
 // neighbours on one XCD.
-template <typename T, int NN, bool FIRST, bool LAST>
+template <typename T, int NN, int MODE>
 __global__ void __launch_bounds__(kZBlock)
 k_rows_inv(const typename cplx_of<T>::type* __restrict__ spec, const T* vin, T* u, T* dst,
            const T* __restrict__ sig, const T* __restrict__ q, const int* __restrict__ qflag,
@@ -518,9 +530,9 @@ k_rows_inv(const typename cplx_of<T>::type* __restrict__ spec, const T* vin, T* 
   __syncthreads();
   double acc_d = 0.0, acc_o = 0.0;
   const bool hasq = (q != nullptr) && qflag[z];
-  epilogue<V, T, NN, RB, LP, kZBlock, FIRST, LAST>(pl, y0, b, z, vin, u, dst, sig, q, hasq, phi_int, h, dt,
-                                                   acc_d, acc_o);
-  if (LAST && b == 0) block_sum2<kZBlock>(smem, acc_d, acc_o, partial + 2 * zy);
+  epilogue<V, T, NN, RB, LP, kZBlock, MODE>(pl, y0, b, z, vin, u, dst, sig, q, hasq, phi_int, h, dt, acc_d,
+                                            acc_o);
+  if (MODE == EPI_LAST && b == 0) block_sum2<kZBlock>(smem, acc_d, acc_o, partial + 2 * zy);
 }
 
 // ------------------------------------------------------- end of step ---
@@ -565,6 +577,48 @@ k_end_step(const T* __restrict__ u, const long long* __restrict__ det, int ndet,
 
 // ------------------------------------------------------------ launch ---
 
+// ------------------------------------------------------ adjoint helpers ---
+
+// Gradient accumulation of one adjoint stage, one thread per voxel:
+//   g_mu_a(r) += wgt * sum_a (2l+1) xs_a(r) y_a(r)
+//   g_mu_s(r) += wgt * sum_a (1 - g(r)^l) (2l+1) xs_a(r) y_a(r)
+// inside the real domain (gin(r) = g(r) there, > 1 in the layer, where the
+// loss does not depend on mu_a, mu_s). xs is the (2l+1)-scaled adjoint of the
+// stage output, y the forward stage input, wgt = -c a h (stage coefficient).
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_adj_grad(const T* __restrict__ xs, const T* __restrict__ y, const double* __restrict__ gin,
+           double* __restrict__ gmua, double* __restrict__ gmus, int N, long long nvox, double wgt) {
+  const long long r = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (r >= nvox) return;
+  const double g = gin[r];
+  if (g > 1.0) return;
+  double sa = 0.0, ss = 0.0, gl = 1.0;
+  for (int l = 0; l <= N; ++l) {
+    double acc = 0.0;
+    for (int m = -l; m <= l; ++m) {
+      const long long a = l * l + l + m;
+      acc += double(xs[a * nvox + r]) * double(y[a * nvox + r]);
+    }
+    acc *= double(2 * l + 1);
+    sa += acc;
+    ss += (1.0 - gl) * acc;
+    gl *= g;
+  }
+  gmua[r] += wgt * sa;
+  gmus[r] += wgt * ss;
+}
+
+// Adjoint source of the detector readings: lam_0(det_p) += dJ/dr[p].
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_adj_inject(T* __restrict__ lam, const long long* __restrict__ det, const double* __restrict__ djdr,
+             int ndet) {
+  for (int p = threadIdx.x; p < ndet; p += kBlock) lam[det[p]] += T(djdr[p]);
+}
+
+// ---------------------------------------------------------------- launch ---
+
 // Grids up to 128 points per axis keep a whole plane in LDS (plane passes);
 // larger grids split each plane pass into a row pass and a y-pencil pass.
 template <int NN> constexpr bool split_planes() { return NN > 128; }
@@ -577,16 +631,18 @@ hipError_t prepare_t(const StepArgs& a) {
   };
   if constexpr (split_planes<NN>()) {
     set(reinterpret_cast<const void*>(&k_rows_fwd<T, NN>), rows_lds<T, NN>());
-    set(reinterpret_cast<const void*>(&k_rows_inv<T, NN, true, false>), rows_lds<T, NN>());
-    set(reinterpret_cast<const void*>(&k_rows_inv<T, NN, false, false>), rows_lds<T, NN>());
-    set(reinterpret_cast<const void*>(&k_rows_inv<T, NN, false, true>), rows_lds<T, NN>());
+    set(reinterpret_cast<const void*>(&k_rows_inv<T, NN, EPI_FIRST>), rows_lds<T, NN>());
+    set(reinterpret_cast<const void*>(&k_rows_inv<T, NN, EPI_MID>), rows_lds<T, NN>());
+    set(reinterpret_cast<const void*>(&k_rows_inv<T, NN, EPI_LAST>), rows_lds<T, NN>());
+    set(reinterpret_cast<const void*>(&k_rows_inv<T, NN, EPI_ADJ>), rows_lds<T, NN>());
     set(reinterpret_cast<const void*>(&k_pencil<T, NN, PENCIL_YFWD>), zd_lds<T, NN>());
     set(reinterpret_cast<const void*>(&k_pencil<T, NN, PENCIL_YINV>), zd_lds<T, NN>());
   } else {
     set(reinterpret_cast<const void*>(&k_fwd_plane<T, NN>), plane_lds<T, NN>());
-    set(reinterpret_cast<const void*>(&k_inv_plane<T, NN, true, false>), plane_lds<T, NN>());
-    set(reinterpret_cast<const void*>(&k_inv_plane<T, NN, false, false>), plane_lds<T, NN>());
-    set(reinterpret_cast<const void*>(&k_inv_plane<T, NN, false, true>), plane_lds<T, NN>());
+    set(reinterpret_cast<const void*>(&k_inv_plane<T, NN, EPI_FIRST>), plane_lds<T, NN>());
+    set(reinterpret_cast<const void*>(&k_inv_plane<T, NN, EPI_MID>), plane_lds<T, NN>());
+    set(reinterpret_cast<const void*>(&k_inv_plane<T, NN, EPI_LAST>), plane_lds<T, NN>());
+    set(reinterpret_cast<const void*>(&k_inv_plane<T, NN, EPI_ADJ>), plane_lds<T, NN>());
   }
   set(reinterpret_cast<const void*>(&k_pencil<T, NN, PENCIL_ZDERIV>), zd_lds<T, NN>());
   return e;
@@ -598,14 +654,14 @@ template <int NN> constexpr int partial_count() {
   return split_planes<NN>() ? NN * (NN / RowShape<NN>::RB) : NN;
 }
 
-template <typename T, int NN, int N>
-hipError_t enqueue_t(const StepArgs& a, ProfRec* pr) {
+// One stage: out = MODE-epilogue of (u, src) with the streaming term
+// sgn * a h c (-B.grad src) (sgn = -1 gives the transposed streaming).
+template <typename T, int NN, int N, int MODE>
+hipError_t enqueue_stage(const StepArgs& a, ProfRec* pr, double hs, double sgn, const T* src, T* u, T* out) {
   using V = typename cplx_of<T>::type;
   using Z = ZdShape<T, NN>;
   constexpr int M = (N + 1) * (N + 1);
   hipStream_t st = reinterpret_cast<hipStream_t>(a.stream);
-  T* u = static_cast<T*>(a.u);
-  T* v = static_cast<T*>(a.v);
   V* spec = static_cast<V*>(a.spec);
   V* dspec = static_cast<V*>(a.dspec);
   const V* tw = static_cast<const V*>(a.tw);
@@ -615,8 +671,7 @@ hipError_t enqueue_t(const StepArgs& a, ProfRec* pr) {
   const T* q = static_cast<const T*>(a.q);
   const Ctl* cctl = static_cast<const Ctl*>(a.ctl);
   const double n2 = double(NN) * NN;
-  const double alphas[4] = {0.25, 1.0 / 3.0, 0.5, 1.0};
-  const dim3 blk(kBlock), pblk(kPBlock), zblk(kZBlock), cblk(kCBlock);
+  const dim3 pblk(kPBlock), zblk(kZBlock), cblk(kCBlock);
   const int planes = M * NN;
   const int pencils = M * NN * Z::NTILE;
   const int cblocks = (NN * NN * (NN / 2) + kCBlock - 1) / kCBlock;
@@ -628,58 +683,93 @@ hipError_t enqueue_t(const StepArgs& a, ProfRec* pr) {
       pr->cls[pr->count++] = cls;
     }
   };
-  if (pr) {
-    (void)hipEventRecord(static_cast<hipEvent_t>(pr->ev0), st);
-    pr->count = 0;
+  if constexpr (split_planes<NN>()) {
+    hipLaunchKernelGGL((k_rows_fwd<T, NN>), dim3(rblocks), zblk, lr, st, src, spec, tw, cctl);
+    rec(PROF_FWD_ROWS);
+    hipLaunchKernelGGL((k_pencil<T, NN, PENCIL_YFWD>), dim3(pencils), zblk, lz, st, spec, spec, tw, kv, cctl);
+    rec(PROF_Y_FWD);
+  } else {
+    hipLaunchKernelGGL((k_fwd_plane<T, NN>), dim3(planes), pblk, lp, st, src, spec, tw, cctl);
+    rec(PROF_FWD_PLANE);
   }
-  for (int s = 0; s < 4; ++s) {
-    const double hs = alphas[s] * a.dt * a.c;
-    const T* src = s == 0 ? u : v;
-    T* out = s == 3 ? u : v;
-    if constexpr (split_planes<NN>()) {
-      hipLaunchKernelGGL((k_rows_fwd<T, NN>), dim3(rblocks), zblk, lr, st, src, spec, tw, cctl);
-      rec(PROF_FWD_ROWS);
-      hipLaunchKernelGGL((k_pencil<T, NN, PENCIL_YFWD>), dim3(pencils), zblk, lz, st, spec, spec, tw, kv, cctl);
-      rec(PROF_Y_FWD);
-    } else {
-      hipLaunchKernelGGL((k_fwd_plane<T, NN>), dim3(planes), pblk, lp, st, src, spec, tw, cctl);
-      rec(PROF_FWD_PLANE);
-    }
-    hipLaunchKernelGGL((k_pencil<T, NN, PENCIL_ZDERIV>), dim3(pencils), zblk, lz, st, spec, dspec, tw, kv,
-                       cctl);
-    rec(PROF_ZDERIV);
-    hipLaunchKernelGGL((k_couple<T, NN, N>), dim3(cblocks), cblk, 0, st, spec, dspec, kv, coef, T(hs / n2),
-                       cctl);
-    rec(PROF_COUPLE);
-    if constexpr (split_planes<NN>()) {
-      hipLaunchKernelGGL((k_pencil<T, NN, PENCIL_YINV>), dim3(pencils), zblk, lz, st, spec, spec, tw, kv, cctl);
-      rec(PROF_Y_INV);
-      if (s == 0)
-        hipLaunchKernelGGL((k_rows_inv<T, NN, true, false>), dim3(rblocks), zblk, lr, st, spec, src, u, out,
-                           sig, q, a.qflag, a.phi_int, a.partial, tw, M, T(hs), a.dt, cctl);
-      else if (s < 3)
-        hipLaunchKernelGGL((k_rows_inv<T, NN, false, false>), dim3(rblocks), zblk, lr, st, spec, src, u, out,
-                           sig, q, a.qflag, a.phi_int, a.partial, tw, M, T(hs), a.dt, cctl);
-      else
-        hipLaunchKernelGGL((k_rows_inv<T, NN, false, true>), dim3(rblocks), zblk, lr, st, spec, src, u, out,
-                           sig, q, a.qflag, a.phi_int, a.partial, tw, M, T(hs), a.dt, cctl);
-      rec(PROF_INV_ROWS);
-    } else {
-      if (s == 0)
-        hipLaunchKernelGGL((k_inv_plane<T, NN, true, false>), dim3(planes), pblk, lp, st, spec, src, u, out,
-                           sig, q, a.qflag, a.phi_int, a.partial, tw, M, T(hs), a.dt, cctl);
-      else if (s < 3)
-        hipLaunchKernelGGL((k_inv_plane<T, NN, false, false>), dim3(planes), pblk, lp, st, spec, src, u, out,
-                           sig, q, a.qflag, a.phi_int, a.partial, tw, M, T(hs), a.dt, cctl);
-      else
-        hipLaunchKernelGGL((k_inv_plane<T, NN, false, true>), dim3(planes), pblk, lp, st, spec, src, u, out,
-                           sig, q, a.qflag, a.phi_int, a.partial, tw, M, T(hs), a.dt, cctl);
-      rec(PROF_INV_PLANE);
-    }
+  hipLaunchKernelGGL((k_pencil<T, NN, PENCIL_ZDERIV>), dim3(pencils), zblk, lz, st, spec, dspec, tw, kv, cctl);
+  rec(PROF_ZDERIV);
+  hipLaunchKernelGGL((k_couple<T, NN, N>), dim3(cblocks), cblk, 0, st, spec, dspec, kv, coef, T(sgn * hs / n2),
+                     cctl);
+  rec(PROF_COUPLE);
+  if constexpr (split_planes<NN>()) {
+    hipLaunchKernelGGL((k_pencil<T, NN, PENCIL_YINV>), dim3(pencils), zblk, lz, st, spec, spec, tw, kv, cctl);
+    rec(PROF_Y_INV);
+    hipLaunchKernelGGL((k_rows_inv<T, NN, MODE>), dim3(rblocks), zblk, lr, st, spec, src, u, out, sig, q, a.qflag,
+                       a.phi_int, a.partial, tw, M, T(hs), a.dt, cctl);
+    rec(PROF_INV_ROWS);
+  } else {
+    hipLaunchKernelGGL((k_inv_plane<T, NN, MODE>), dim3(planes), pblk, lp, st, spec, src, u, out, sig, q, a.qflag,
+                       a.phi_int, a.partial, tw, M, T(hs), a.dt, cctl);
+    rec(PROF_INV_PLANE);
   }
-  hipLaunchKernelGGL((k_end_step<T>), dim3(1), blk, 0, st, u, a.det, a.ndet, a.readings, a.resid, a.cap,
-                     a.partial, partial_count<NN>(), static_cast<Ctl*>(a.ctl));
-  rec(PROF_END);
+  return hipSuccess;
+}
+
+constexpr double kRkAlpha[4] = {0.25, 1.0 / 3.0, 0.5, 1.0};
+
+template <typename T, int NN, int N>
+hipError_t enqueue_t(const StepArgs& a, const OpArgs& op, ProfRec* pr) {
+  hipStream_t st = reinterpret_cast<hipStream_t>(a.stream);
+  const double hc = a.dt * a.c;
+  const long long nvox = (long long)NN * NN * NN;
+  switch (op.kind) {
+    case OP_STEP: {
+      T* u = static_cast<T*>(a.u);
+      T* v = static_cast<T*>(a.v);
+      if (pr) {
+        (void)hipEventRecord(static_cast<hipEvent_t>(pr->ev0), st);
+        pr->count = 0;
+      }
+      enqueue_stage<T, NN, N, EPI_FIRST>(a, pr, kRkAlpha[0] * hc, 1.0, u, u, v);
+      enqueue_stage<T, NN, N, EPI_MID>(a, pr, kRkAlpha[1] * hc, 1.0, v, u, v);
+      enqueue_stage<T, NN, N, EPI_MID>(a, pr, kRkAlpha[2] * hc, 1.0, v, u, v);
+      enqueue_stage<T, NN, N, EPI_LAST>(a, pr, kRkAlpha[3] * hc, 1.0, v, u, u);
+      hipLaunchKernelGGL((k_end_step<T>), dim3(1), dim3(kBlock), 0, st, u, a.det, a.ndet, a.readings, a.resid,
+                         a.cap, a.partial, partial_count<NN>(), static_cast<Ctl*>(a.ctl));
+      if (pr && pr->count < kMaxProfLaunches) {
+        (void)hipEventRecord(static_cast<hipEvent_t>(pr->ev[pr->count]), st);
+        pr->cls[pr->count++] = PROF_END;
+      }
+      break;
+    }
+    case OP_STAGE: {
+      // forward stage op.stage (0..2) of the nested RK4 form from base state
+      // op.u with stage input op.x, writing op.y (no bookkeeping)
+      const int s = op.stage;
+      const T* xin = static_cast<const T*>(op.x);
+      T* u = static_cast<T*>(op.u);
+      T* out = static_cast<T*>(op.y);
+      if (s == 0) enqueue_stage<T, NN, N, EPI_FIRST>(a, nullptr, kRkAlpha[0] * hc, 1.0, u, u, out);
+      else enqueue_stage<T, NN, N, EPI_MID>(a, nullptr, kRkAlpha[s] * hc, 1.0, xin, u, out);
+      break;
+    }
+    case OP_ADJ_STAGE: {
+      // xs_out = coef h F~(xs_in) with the streaming sign flipped, acc += xs_out
+      enqueue_stage<T, NN, N, EPI_ADJ>(a, nullptr, op.coef * hc, -1.0, static_cast<const T*>(op.x),
+                                       static_cast<T*>(op.u), static_cast<T*>(op.y));
+      break;
+    }
+    case OP_ADJ_GRAD: {
+      const int blocks = int((nvox + kBlock - 1) / kBlock);
+      hipLaunchKernelGGL((k_adj_grad<T>), dim3(blocks), dim3(kBlock), 0, st, static_cast<const T*>(op.x),
+                         static_cast<const T*>(op.y), op.gin, op.gmua, op.gmus, N, nvox,
+                         -a.c * op.coef * a.dt);
+      break;
+    }
+    case OP_ADJ_INJECT: {
+      hipLaunchKernelGGL((k_adj_inject<T>), dim3(1), dim3(kBlock), 0, st, static_cast<T*>(op.u), a.det,
+                         op.djdr, a.ndet);
+      break;
+    }
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -706,7 +796,7 @@ hipError_t dispatch_tn(const StepArgs& a, Args... args) {
 }
 
 template <typename T, int NN, int N> struct EnqueueFn {
-  static hipError_t call(const StepArgs& a, ProfRec* pr) { return enqueue_t<T, NN, N>(a, pr); }
+  static hipError_t call(const StepArgs& a, const OpArgs* op, ProfRec* pr) { return enqueue_t<T, NN, N>(a, *op, pr); }
 };
 template <typename T, int NN, int N> struct PrepareFn {
   static hipError_t call(const StepArgs& a) { return prepare_t<T, NN, N>(a); }
@@ -714,8 +804,8 @@ template <typename T, int NN, int N> struct PrepareFn {
 
 // Defines the per-size entry points used by the runtime.
 #define RTE_DEFINE_SIZE(NN)                                                              \
-  int enqueue_step_n##NN(const StepArgs& a, void* pr) {                                  \
-    return int(dispatch_tn<EnqueueFn, NN>(a, static_cast<ProfRec*>(pr)));                \
+  int enqueue_op_n##NN(const StepArgs& a, const OpArgs& op, void* pr) {                 \
+    return int(dispatch_tn<EnqueueFn, NN>(a, &op, static_cast<ProfRec*>(pr)));           \
   }                                                                                      \
   int prepare_n##NN(const StepArgs& a) { return int(dispatch_tn<PrepareFn, NN>(a)); }
 

@@ -22,7 +22,8 @@ constexpr size_t kAlign = 256;
 inline size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t u, v, spec, dspec, sig, q, qflag, tw, kv, coef, det, readings, resid, partial, phi_int, ctl, total;
+  size_t u, v, spec, dspec, sig, q, qflag, tw, kv, coef, det, readings, resid, partial, phi_int, gin, ctl,
+      total;
 };
 
 inline bool config_ok(const rte_config* c) {
@@ -65,18 +66,19 @@ inline Layout layout_of(const rte_config* c, bool has_q) {
   L.resid = o; o = up(o + size_t(c->record_steps) * 8);
   L.partial = o; o = up(o + n * n * 2 * 8);
   L.phi_int = o; o = up(o + V * 8);
+  L.gin = o; o = up(o + V * 8);
   L.ctl = o; o = up(o + sizeof(Ctl));
   L.total = o;
   return L;
 }
 
-int enqueue_step_n16(const StepArgs& a, void* ev);
-int enqueue_step_n32(const StepArgs& a, void* ev);
-int enqueue_step_n48(const StepArgs& a, void* ev);
-int enqueue_step_n64(const StepArgs& a, void* ev);
-int enqueue_step_n96(const StepArgs& a, void* ev);
-int enqueue_step_n128(const StepArgs& a, void* ev);
-int enqueue_step_n256(const StepArgs& a, void* ev);
+int enqueue_op_n16(const StepArgs& a, const OpArgs& op, void* pr);
+int enqueue_op_n32(const StepArgs& a, const OpArgs& op, void* pr);
+int enqueue_op_n48(const StepArgs& a, const OpArgs& op, void* pr);
+int enqueue_op_n64(const StepArgs& a, const OpArgs& op, void* pr);
+int enqueue_op_n96(const StepArgs& a, const OpArgs& op, void* pr);
+int enqueue_op_n128(const StepArgs& a, const OpArgs& op, void* pr);
+int enqueue_op_n256(const StepArgs& a, const OpArgs& op, void* pr);
 int prepare_n16(const StepArgs& a);
 int prepare_n32(const StepArgs& a);
 int prepare_n48(const StepArgs& a);
@@ -85,15 +87,15 @@ int prepare_n96(const StepArgs& a);
 int prepare_n128(const StepArgs& a);
 int prepare_n256(const StepArgs& a);
 
-int launch_enqueue_step(int n, const StepArgs& a, void* ev) {
+int launch_enqueue_op(int n, const StepArgs& a, const OpArgs& op, void* ev) {
   switch (n) {
-    case 16: return enqueue_step_n16(a, ev);
-    case 32: return enqueue_step_n32(a, ev);
-    case 48: return enqueue_step_n48(a, ev);
-    case 64: return enqueue_step_n64(a, ev);
-    case 96: return enqueue_step_n96(a, ev);
-    case 128: return enqueue_step_n128(a, ev);
-    case 256: return enqueue_step_n256(a, ev);
+    case 16: return enqueue_op_n16(a, op, ev);
+    case 32: return enqueue_op_n32(a, op, ev);
+    case 48: return enqueue_op_n48(a, op, ev);
+    case 64: return enqueue_op_n64(a, op, ev);
+    case 96: return enqueue_op_n96(a, op, ev);
+    case 128: return enqueue_op_n128(a, op, ev);
+    case 256: return enqueue_op_n256(a, op, ev);
     default: return int(hipErrorInvalidValue);
   }
 }
@@ -132,6 +134,12 @@ struct rte_handle {
 namespace rte {
 
 int to_code(hipError_t e) { return e == hipSuccess ? RTE_OK : RTE_EDEVICE; }
+
+OpArgs step_op() {
+  OpArgs op{};
+  op.kind = OP_STEP;
+  return op;
+}
 
 template <typename T>
 void convert_upload(std::vector<T>& tmp, const double* src, size_t count) {
@@ -236,6 +244,13 @@ int upload_tables_t(rte_handle* h, const rte_medium* med, const std::vector<doub
     put(L.q, tmp.data(), tmp.size() * sizeof(T));
   }
   put(L.qflag, qflag.data(), qflag.size() * sizeof(int));
+  {
+    // g inside the real domain, 2 (> 1) in the layer: the adjoint gradient
+    // of the loss with respect to mu_a, mu_s vanishes there (eq. 12)
+    std::vector<double> gin(V);
+    for (size_t i = 0; i < V; ++i) gin[i] = inside[i] ? med->g[i] : 2.0;
+    put(L.gin, gin.data(), V * 8);
+  }
   if (h->cfg.n_det > 0) put(L.det, h->cfg.det_index, size_t(h->cfg.n_det) * 8);
   return to_code(e);
 }
@@ -245,7 +260,7 @@ int enqueue_steps(rte_handle* h, int64_t k) {
   if (h->use_graph && !h->graph_ready) {
     hipError_t e = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-      hipError_t e2 = hipError_t(launch_enqueue_step(h->n, h->args, nullptr));
+      hipError_t e2 = hipError_t(launch_enqueue_op(h->n, h->args, step_op(), nullptr));
       e = hipStreamEndCapture(h->stream, &h->graph);
       if (e2 != hipSuccess) e = e2;
     }
@@ -259,10 +274,48 @@ int enqueue_steps(rte_handle* h, int64_t k) {
   }
   for (int64_t i = 0; i < k; ++i) {
     hipError_t e = h->graph_ready ? hipGraphLaunch(h->exec, h->stream)
-                                  : hipError_t(launch_enqueue_step(h->n, h->args, nullptr));
+                                  : hipError_t(launch_enqueue_op(h->n, h->args, step_op(), nullptr));
     if (e != hipSuccess) return RTE_EDEVICE;
   }
   return RTE_OK;
+}
+
+// ------------------------------------------------------------- adjoint ---
+
+struct AdjLayout {
+  size_t ckpt, seg, v1, v2, v3, lam, xa, xb, scratch, gmua, gmus, djdr, phi, partial, ctl, total;
+  int64_t nckpt, every;
+};
+
+inline AdjLayout adj_layout(const rte_config* c, int64_t steps, int64_t every) {
+  AdjLayout A{};
+  const size_t n = c->n, M = size_t(c->order_N + 1) * (c->order_N + 1);
+  const size_t s = c->precision == RTE_FP64 ? 8 : 4;
+  const size_t V = n * n * n, F = M * V * s;
+  A.every = every;
+  A.nckpt = (steps + every - 1) / every;
+  size_t o = 0;
+  A.ckpt = o; o = up(o + size_t(A.nckpt) * F);
+  A.seg = o; o = up(o + size_t(every) * F);
+  A.v1 = o; o = up(o + F);
+  A.v2 = o; o = up(o + F);
+  A.v3 = o; o = up(o + F);
+  A.lam = o; o = up(o + F);
+  A.xa = o; o = up(o + F);
+  A.xb = o; o = up(o + F);
+  A.scratch = o; o = up(o + F);
+  A.gmua = o; o = up(o + V * 8);
+  A.gmus = o; o = up(o + V * 8);
+  A.djdr = o; o = up(o + size_t(steps) * size_t(c->n_det) * 8);
+  A.phi = o; o = up(o + V * 8);
+  A.partial = o; o = up(o + n * n * 2 * 8);
+  A.ctl = o; o = up(o + sizeof(Ctl));
+  A.total = o;
+  return A;
+}
+
+inline size_t state_bytes(const rte_handle* h) {
+  return size_t(h->M) * h->n * h->n * h->n * (h->prec == RTE_FP64 ? 8 : 4);
 }
 
 }  // namespace rte
@@ -468,6 +521,151 @@ int rte_coupling_dense(int32_t order_N, double* bx, double* by, double* bz) {
   return RTE_OK;
 }
 
+size_t rte_adjoint_workspace_bytes(const rte_config* cfg, int64_t steps, int64_t every) {
+  if (!rte::config_ok(cfg) || steps <= 0 || every <= 0) return 0;
+  return rte::adj_layout(cfg, steps, every).total;
+}
+
+int rte_forward_checkpointed(rte_handle* h, int64_t steps, int64_t every, void* adj_ws, size_t adj_bytes) {
+  using namespace rte;
+  if (!h || steps <= 0 || every <= 0) return RTE_EINVAL;
+  const AdjLayout A = adj_layout(&h->cfg, steps, every);
+  if (!adj_ws || (reinterpret_cast<uintptr_t>(adj_ws) % kAlign) != 0 || adj_bytes < A.total) return RTE_ENOMEM;
+  unsigned char* w = static_cast<unsigned char*>(adj_ws);
+  const size_t F = state_bytes(h);
+  for (int64_t i = 0; i < steps; ++i) {
+    if (i % every == 0) {
+      if (hipMemcpyAsync(w + A.ckpt + size_t(i / every) * F, h->ws + h->lay.u, F, hipMemcpyDeviceToDevice,
+                         h->stream) != hipSuccess)
+        return RTE_EDEVICE;
+    }
+    const int rc = enqueue_steps(h, 1);
+    if (rc) return rc;
+  }
+  Ctl c;
+  const int rc = read_ctl(h, &c);
+  if (rc) return rc;
+  return c.stop == 2 ? RTE_EUNSTABLE : RTE_OK;
+}
+
+int rte_adjoint(rte_handle* h, int64_t steps, int64_t every, void* adj_ws, size_t adj_bytes,
+                const double* dj_dr, double* grad_mu_a, double* grad_mu_s) {
+  using namespace rte;
+  if (!h || steps <= 0 || every <= 0 || !grad_mu_a || !grad_mu_s) return RTE_EINVAL;
+  if (h->cfg.n_det > 0 && !dj_dr) return RTE_EINVAL;
+  const AdjLayout A = adj_layout(&h->cfg, steps, every);
+  if (!adj_ws || (reinterpret_cast<uintptr_t>(adj_ws) % kAlign) != 0 || adj_bytes < A.total) return RTE_ENOMEM;
+  unsigned char* w = static_cast<unsigned char*>(adj_ws);
+  const size_t F = state_bytes(h);
+  const size_t V = size_t(h->n) * h->n * h->n;
+  const int nd = h->cfg.n_det;
+  hipStream_t st = h->stream;
+  hipError_t e = hipSuccess;
+  auto ok = [&](hipError_t x) {
+    if (e == hipSuccess) e = x;
+  };
+  if (nd > 0) ok(hipMemcpyAsync(w + A.djdr, dj_dr, size_t(steps) * nd * 8, hipMemcpyHostToDevice, st));
+  ok(hipMemsetAsync(w + A.gmua, 0, V * 8, st));
+  ok(hipMemsetAsync(w + A.gmus, 0, V * 8, st));
+  ok(hipMemsetAsync(w + A.lam, 0, F, st));
+  Ctl c0{};
+  c0.growth_limit = 1e300;
+  ok(hipMemcpyAsync(w + A.ctl, &c0, sizeof(Ctl), hipMemcpyHostToDevice, st));
+  ok(hipStreamSynchronize(st));
+  if (e != hipSuccess) return RTE_EDEVICE;
+
+  // recompute arguments: private bookkeeping buffers, no readings
+  StepArgs R = h->args;
+  R.readings = nullptr;
+  R.resid = nullptr;
+  R.cap = 0;
+  R.ndet = 0;
+  R.phi_int = reinterpret_cast<double*>(w + A.phi);
+  R.partial = reinterpret_cast<double*>(w + A.partial);
+  R.ctl = w + A.ctl;
+  R.v = w + A.scratch;
+  const StepArgs& H = h->args;
+  auto op = [&](const StepArgs& sa, const OpArgs& o) {
+    if (e == hipSuccess) e = hipError_t(launch_enqueue_op(h->n, sa, o, nullptr));
+  };
+  auto inject = [&](int64_t reading) {
+    if (nd == 0) return;
+    OpArgs o{};
+    o.kind = OP_ADJ_INJECT;
+    o.u = w + A.lam;
+    o.djdr = reinterpret_cast<const double*>(w + A.djdr) + size_t(reading) * nd;
+    op(H, o);
+  };
+  auto grad = [&](const void* x, const void* y, double coef) {
+    OpArgs o{};
+    o.kind = OP_ADJ_GRAD;
+    o.x = x;
+    o.y = const_cast<void*>(y);
+    o.coef = coef;
+    o.gin = h->at<double>(h->lay.gin);
+    o.gmua = reinterpret_cast<double*>(w + A.gmua);
+    o.gmus = reinterpret_cast<double*>(w + A.gmus);
+    op(R, o);
+  };
+  auto adj_stage = [&](const void* x, void* y, double coef) {
+    OpArgs o{};
+    o.kind = OP_ADJ_STAGE;
+    o.x = x;
+    o.y = y;
+    o.u = w + A.lam;
+    o.coef = coef;
+    op(R, o);
+  };
+  auto fwd_stage = [&](int s, const void* un, const void* x, void* y) {
+    OpArgs o{};
+    o.kind = OP_STAGE;
+    o.stage = s;
+    o.u = const_cast<void*>(un);
+    o.x = x;
+    o.y = y;
+    op(R, o);
+  };
+
+  // readings r_s (s = 0..steps-1) are psi_00 of u_{s+1}
+  inject(steps - 1);
+  for (int64_t j = A.nckpt - 1; j >= 0 && e == hipSuccess; --j) {
+    const int64_t n0 = j * every, n1 = std::min(steps, n0 + every);
+    unsigned char* seg = w + A.seg;
+    ok(hipMemcpyAsync(seg, w + A.ckpt + size_t(j) * F, F, hipMemcpyDeviceToDevice, st));
+    for (int64_t nn = n0; nn + 1 < n1; ++nn) {
+      unsigned char* next = seg + size_t(nn - n0 + 1) * F;
+      ok(hipMemcpyAsync(next, seg + size_t(nn - n0) * F, F, hipMemcpyDeviceToDevice, st));
+      StepArgs S = R;
+      S.u = next;
+      OpArgs o{};
+      o.kind = OP_STEP;
+      op(S, o);
+    }
+    for (int64_t nn = n1 - 1; nn >= n0 && e == hipSuccess; --nn) {
+      const void* un = seg + size_t(nn - n0) * F;
+      fwd_stage(0, un, un, w + A.v1);
+      fwd_stage(1, un, w + A.v1, w + A.v2);
+      fwd_stage(2, un, w + A.v2, w + A.v3);
+      // transposed nested stages (coefficients 1, 1/2, 1/3, 1/4), each
+      // preceded by the gradient term of its forward counterpart
+      grad(w + A.lam, w + A.v3, 1.0);
+      adj_stage(w + A.lam, w + A.xa, 1.0);
+      grad(w + A.xa, w + A.v2, 0.5);
+      adj_stage(w + A.xa, w + A.xb, 0.5);
+      grad(w + A.xb, w + A.v1, 1.0 / 3.0);
+      adj_stage(w + A.xb, w + A.xa, 1.0 / 3.0);
+      grad(w + A.xa, un, 0.25);
+      adj_stage(w + A.xa, w + A.xb, 0.25);
+      if (nn >= 1) inject(nn - 1);
+    }
+  }
+  if (e != hipSuccess) return RTE_EDEVICE;
+  ok(hipMemcpyAsync(grad_mu_a, w + A.gmua, V * 8, hipMemcpyDeviceToHost, st));
+  ok(hipMemcpyAsync(grad_mu_s, w + A.gmus, V * 8, hipMemcpyDeviceToHost, st));
+  ok(hipStreamSynchronize(st));
+  return to_code(e);
+}
+
 int rte_profile_kernels(rte_handle* h, int64_t nsteps, double* ms, int64_t* counts) {
   using namespace rte;
   if (!h || !ms || !counts || nsteps < 0) return RTE_EINVAL;
@@ -485,7 +683,7 @@ int rte_profile_kernels(rte_handle* h, int64_t nsteps, double* ms, int64_t* coun
   }
   int rc = RTE_OK;
   for (int64_t s = 0; s < nsteps && rc == RTE_OK; ++s) {
-    hipError_t e = hipError_t(launch_enqueue_step(h->n, h->args, &pr));
+    hipError_t e = hipError_t(launch_enqueue_op(h->n, h->args, step_op(), &pr));
     if (e == hipSuccess && pr.count > 0) e = hipEventSynchronize(ev[pr.count - 1]);
     if (e != hipSuccess) {
       rc = RTE_EDEVICE;

@@ -24,7 +24,8 @@ EXPORTS = (
     "rte_workspace_bytes", "rte_create", "rte_step", "rte_run", "rte_fluence",
     "rte_readings", "rte_residuals", "rte_steps_done", "rte_get_state",
     "rte_set_state", "rte_coupling_dense", "rte_profile_kernels", "rte_destroy",
-    "rte_strerror",
+    "rte_strerror", "rte_adjoint_workspace_bytes", "rte_forward_checkpointed",
+    "rte_adjoint",
 )
 KERNEL_CLASSES = ("fwd_plane", "zderiv", "couple", "inv_plane", "end_step",
                   "fwd_rows", "y_fwd", "y_inv", "inv_rows")
@@ -92,6 +93,12 @@ def lib():
         L.rte_coupling_dense.restype = C.c_int
         L.rte_profile_kernels.argtypes = [vp, C.c_int64, dp, i64p]
         L.rte_profile_kernels.restype = C.c_int
+        L.rte_adjoint_workspace_bytes.argtypes = [C.POINTER(rte_config), C.c_int64, C.c_int64]
+        L.rte_adjoint_workspace_bytes.restype = C.c_size_t
+        L.rte_forward_checkpointed.argtypes = [vp, C.c_int64, C.c_int64, vp, C.c_size_t]
+        L.rte_forward_checkpointed.restype = C.c_int
+        L.rte_adjoint.argtypes = [vp, C.c_int64, C.c_int64, vp, C.c_size_t, dp, dp, dp]
+        L.rte_adjoint.restype = C.c_int
         L.rte_destroy.argtypes = [vp]
         L.rte_destroy.restype = None
         L.rte_strerror.argtypes = [C.c_int]
@@ -226,6 +233,34 @@ class Solver:
     def set_state(self, psi: np.ndarray):
         a = _f64(psi).ravel()
         _check(lib().rte_set_state(self.h, _dptr(a), a.size), "rte_set_state")
+
+    # -- discrete adjoint ---------------------------------------------------
+    def forward_checkpointed(self, steps: int, every: int = 0):
+        """Run ``steps`` steps keeping checkpoints every ``every`` steps
+        (default ceil(sqrt(steps))) in a torch-owned device workspace."""
+        import math
+        import torch
+        every = int(every) or max(1, math.ceil(math.sqrt(steps)))
+        nbytes = int(lib().rte_adjoint_workspace_bytes(C.byref(self.cfg), int(steps), every))
+        if nbytes == 0:
+            raise RteError(RTE_EINVAL, "rte_adjoint_workspace_bytes")
+        self.adj_ws = torch.empty(nbytes, dtype=torch.uint8, device=self.workspace.device)
+        self.adj_steps, self.adj_every = int(steps), every
+        _check(lib().rte_forward_checkpointed(self.h, int(steps), every,
+                                              C.c_void_p(self.adj_ws.data_ptr()), nbytes),
+               "rte_forward_checkpointed")
+
+    def adjoint(self, dj_dr):
+        """dJ/dmu_a, dJ/dmu_s (each (n, n, n), FP64) for adjoint sources
+        ``dj_dr[step][det]`` of the last checkpointed forward run."""
+        n = self.n
+        ga = np.zeros(n ** 3)
+        gs = np.zeros(n ** 3)
+        d = np.ascontiguousarray(dj_dr, np.float64).reshape(self.adj_steps, self.n_det)
+        _check(lib().rte_adjoint(self.h, self.adj_steps, self.adj_every,
+                                 C.c_void_p(self.adj_ws.data_ptr()), self.adj_ws.numel(),
+                                 _dptr(d), _dptr(ga), _dptr(gs)), "rte_adjoint")
+        return ga.reshape(n, n, n), gs.reshape(n, n, n)
 
     def profile_kernels(self, nsteps: int):
         """Per-kernel-class milliseconds (summed) and launch counts over
