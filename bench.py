@@ -84,7 +84,7 @@ def cpu_baseline(wl, workers: int):
     U = pn.real_basis_transform(wl.N)
     k = pn.wavenumbers(wl.n, wl.dx)
     Sig, _ = pn.potentials(wl.mu_a, wl.mu_s, wl.g, wl.N, wl.W, wl.mu0, wl.mu1)
-    psi = pn.to_complex_basis(wl.psi0, U).astype(complex)
+    psi = pn.to_complex_basis(pn.full_moments(wl.psi0, wl.M), U).astype(complex)
     t0 = time.perf_counter()
     f = pn.operator(psi, Sig, None, B, k, wl.c, workers)
     psi = psi + (0.5 * wl.dt) * f
@@ -109,6 +109,82 @@ def traffic_for(kind: str, workload: str):
     return rec["bytes_per_launch"]
 
 
+def serving_bench(a):
+    """Continuous batching vs one-at-a-time on the seeded request trace:
+    Poisson arrivals at 1.5 / (mean one-at-a-time service time)."""
+    import numpy as np
+    import torch
+
+    import rte_inputs as ri
+    from paper_1801_06364_amd import serving
+
+    torch.cuda.set_device(0)
+    specs = ri.serving_requests(count=a.requests, seed=4)
+    srv = serving.Server(budget_bytes=int(a.budget_gib * 2 ** 30), max_slots=a.slots)
+    # warm-up: one small request (library load, first launches), not reported
+    srv.service_times([ri.RequestSpec(-1, 32, 1, 5, 0, 0, 1.0)])
+    print(f"[serving] {len(specs)} requests; measuring one-at-a-time service times",
+          file=sys.stderr, flush=True)
+    alone = srv.service_times(specs)
+    svc = np.array([r.finished - r.admitted for r in alone.values()])
+    rate = 1.5 / svc.mean()
+    arr = serving.poisson_arrivals(specs, rate)
+    fifo = serving.fifo_replay(specs, arr, alone)
+    print(f"[serving] mean service {svc.mean():.3f} s, rate {rate:.3f}/s; serving batched",
+          file=sys.stderr, flush=True)
+    bat = srv.serve(specs, arr)
+    same = sum(1 for s in specs if bat.results[s.rid].ok and
+               bat.results[s.rid].checksum == alone[s.rid].checksum)
+    fs, bs = fifo.summary(), bat.summary()
+    out = {"metric": "p50/p99 solve latency and aggregate updates/s (serving)",
+           "value": bs["updates_per_s"], "unit": "updates/s", "n_gpus": 1,
+           "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{len(specs)} seeded requests (seed 4): grids {{32,48,64,96,128}}^3, "
+                                  "P_N in {1,3,5,7}, 200-1000 RK4 steps, half homogeneous / half 1-5 "
+                                  "inclusions, Gaussian pulse; Poisson arrivals at 1.5 / mean "
+                                  "one-at-a-time service time",
+                      "budget_GiB": a.budget_gib, "slots": a.slots, "rate_per_s": rate,
+                      "mean_service_s": float(svc.mean())},
+           "batched": bs, "one_at_a_time": fs,
+           "speedup_p50": fs["p50_latency_s"] / bs["p50_latency_s"],
+           "speedup_p99": fs["p99_latency_s"] / bs["p99_latency_s"],
+           "speedup_throughput": bs["updates_per_s"] / fs["updates_per_s"],
+           "results_identical_alone_vs_mix": f"{same}/{len(specs)}"}
+    print(json.dumps(out), flush=True)
+
+
+def accuracy_report():
+    """FP32 and FP64 GPU results against the FP64 oracle on the bench recipe
+    at a reduced size (p7_spheres, 32^3, 12 steps): relative L2 per result
+    (readings relative to the fluence peak of each step)."""
+    import numpy as np
+
+    import rte_inputs as ri
+    from oracle import pn
+    from paper_1801_06364_amd.rte import Solver
+
+    n, steps = 32, 12
+    wl = ri.workload("p7_spheres", n=n, steps=steps)
+    ref = pn.solve(wl.n, wl.N, wl.dx, wl.c, wl.dt, wl.mu_a, wl.mu_s, wl.g, wl.psi0, None, wl.W,
+                   wl.mu0, wl.mu1, steps, det_index=wl.det_index)
+
+    def rel(x, y):
+        return float(np.linalg.norm(np.ravel(x) - np.ravel(y)) / np.linalg.norm(np.ravel(y)))
+
+    out = {"workload": f"p7_spheres recipe at {n}^3, {steps} RK4 steps"}
+    for prec in ("f32", "f64"):
+        s = Solver.from_workload(ri.workload("p7_spheres", n=n, steps=steps, precision=prec))
+        s.step(steps)
+        r = s.readings()
+        out[prec] = {"fluence": rel(s.fluence(), ref["fluence"]),
+                     "state": rel(s.get_state(), ref["state"]),
+                     "integrated_fluence": rel(s.fluence(1), ref["phi_int"]),
+                     "readings_max_err_over_peak": float(np.max(np.abs(r - ref["readings"]) /
+                                                                ref["peak"][:, None]))}
+        s.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,6 +195,12 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--profile-steps", type=int, default=5)
+    ap.add_argument("--serving", action="store_true",
+                    help="serve the seeded Poisson request trace instead (separate JSON line)")
+    ap.add_argument("--requests", type=int, default=256)
+    ap.add_argument("--budget-gib", type=float, default=12.0)
+    ap.add_argument("--slots", type=int, default=12)
+    ap.add_argument("--no-accuracy", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the hot path is a single-GPU solve; "
@@ -130,6 +212,9 @@ def main():
 
     import rte_inputs as ri
     from paper_1801_06364_amd.rte import Solver
+
+    if a.serving:
+        return serving_bench(a)
 
     wl = ri.workload(a.workload, steps=a.steps + a.warmup)
     torch.cuda.set_device(0)
@@ -203,6 +288,8 @@ def main():
         "kernel_ms_per_launch": per,
         "roofline": roofline,
     }
+    if not a.no_accuracy:
+        out["accuracy"] = accuracy_report()
     if not a.no_cpu_baseline:
         workers = int(os.environ.get("OMP_NUM_THREADS", "0")) or min(16, os.cpu_count() or 1)
         wlc = ri.workload(a.workload, steps=1)

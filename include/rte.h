@@ -21,7 +21,8 @@
  *    to d psi/dt = c (-[s.grad psi] - Sigma_l psi + q) (the sign form that
  *    eqs. 1 and 6 give), evaluated in the equivalent nested form
  *    v <- u + dt/4 f(u); v <- u + dt/3 f(v); v <- u + dt/2 f(v);
- *    u <- u + dt f(v), exact for this autonomous affine right-hand side.
+ *    u <- u + dt f(v), exact for this autonomous affine right-hand side;
+ *    or, on request, the paper's first-order explicit step (eq. 11).
  *
  * Grid: n^3 voxels, voxel (z, y, x) at r = (x, y, z) * dx; every field is
  * stored [z][y][x] with x fastest; moment fields are [a][z][y][x]. The real
@@ -56,6 +57,7 @@ enum {
 };
 
 enum { RTE_FP32 = 0, RTE_FP64 = 1 };
+enum { RTE_RK4 = 0, RTE_EULER = 1 };
 enum { RTE_FLUENCE_NOW = 0, RTE_FLUENCE_INTEGRATED = 1 };
 
 typedef struct rte_handle rte_handle;
@@ -74,7 +76,9 @@ typedef struct {
   double pml_mu0;          /* layer attenuation at the real-domain edge       */
   double pml_mu1;          /* layer attenuation at the grid edge (mm^-1)      */
   int32_t n_det;           /* number of detector voxels (>= 0)                */
-  int32_t reserved0;
+  int32_t scheme;          /* RTE_RK4 (classic four-stage, default) or
+                              RTE_EULER (the first-order explicit step of
+                              eq. 11: u <- u + dt f(u), one stage per step)  */
   const int64_t* det_index;/* n_det linear voxel indices (z*n+y)*n+x, host    */
   int64_t record_steps;    /* capacity of the per-step record (readings,
                               residuals); later steps run unrecorded         */
@@ -84,9 +88,13 @@ typedef struct {           /* host arrays, FP64, read during rte_create only   *
   const double* mu_a;      /* n^3 absorption (mm^-1), >= 0                     */
   const double* mu_s;      /* n^3 scattering (mm^-1), >= 0                     */
   const double* g;         /* n^3 HG anisotropy, -1 < g < 1                    */
-  const double* psi0;      /* M*n^3 initial real-basis moments, or NULL (0)    */
-  const double* q;         /* M*n^3 time-constant source moments, or NULL;
-                              zeroed inside the absorbing layer (eq. 12)      */
+  const double* psi0;      /* psi0_moments*n^3 initial real-basis moments
+                              (moments a < psi0_moments; the rest are 0), or
+                              NULL for an all-zero initial state             */
+  const double* q;         /* q_moments*n^3 time-constant source moments, or
+                              NULL; zeroed inside the absorbing layer (eq. 12) */
+  int32_t psi0_moments;    /* leading moments given in psi0; 0 means all M    */
+  int32_t q_moments;       /* leading moments given in q; 0 means all M       */
 } rte_medium;
 
 /* Bytes of device workspace a configuration needs (0 if it is invalid). */

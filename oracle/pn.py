@@ -289,8 +289,26 @@ def rk4_step(psi, f, dt):
     return psi + (dt / 6.0) * acc
 
 
+def full_moments(a, M):
+    """Inputs may give only the K <= M leading moments; pad with zeros."""
+    if a is None:
+        return None
+    a = np.asarray(a, float)
+    if a.shape[0] == M:
+        return a
+    out = np.zeros((M,) + a.shape[1:])
+    out[:a.shape[0]] = a
+    return out
+
+
+def euler_step(psi, f, dt):
+    """First-order explicit step of eq. (11) (with the sign reading of the
+    right-hand side): ``psi + dt f(psi)``."""
+    return psi + dt * f(psi)
+
+
 def solve(n, N, dx, c, dt, mu_a, mu_s, g, psi0_real, q_real, W, mu0, mu1,
-          steps, det_index=(), workers=None, return_state=True):
+          steps, det_index=(), workers=None, return_state=True, scheme="rk4"):
     """March ``steps`` RK4 steps from ``psi0_real`` (real-basis moments).
 
     Returns a dict with ``fluence`` (psi_0^0 after the last step),
@@ -304,13 +322,15 @@ def solve(n, N, dx, c, dt, mu_a, mu_s, g, psi0_real, q_real, W, mu0, mu1,
     U = real_basis_transform(N)
     k = wavenumbers(n, dx)
     Sig, omega = potentials(mu_a, mu_s, g, N, W, mu0, mu1)
+    psi0_real = full_moments(psi0_real, M)
+    q_real = full_moments(q_real, M)
     if psi0_real is None:
         psi = np.zeros((M, n, n, n), complex)
     else:
-        psi = to_complex_basis(np.asarray(psi0_real, float), U).astype(complex)
+        psi = to_complex_basis(psi0_real, U).astype(complex)
     q = None
     if q_real is not None:
-        q = to_complex_basis(np.asarray(q_real, float), U) * omega[None]
+        q = to_complex_basis(q_real, U) * omega[None]
     det = np.asarray(det_index, dtype=np.int64)
     readings = np.zeros((steps, det.size))
     residual = np.zeros(steps)
@@ -321,8 +341,9 @@ def solve(n, N, dx, c, dt, mu_a, mu_s, g, psi0_real, q_real, W, mu0, mu1,
     def f(y):
         return operator(y, Sig, q, B, k, c, workers)
 
+    stepper = euler_step if scheme == "euler" else rk4_step
     for s in range(steps):
-        psi = rk4_step(psi, f, dt)
+        psi = stepper(psi, f, dt)
         phi = psi[0].real
         readings[s] = phi.ravel()[det]
         peak[s] = np.abs(phi).max()
@@ -414,7 +435,7 @@ def operator_transpose(y, Sig, BR, k, c):
 
 
 def adjoint_gradient(n, N, dx, c, dt, mu_a, mu_s, g, psi0_real, q_real, W, mu0,
-                     mu1, steps, det_index, dj_dr):
+                     mu1, steps, det_index, dj_dr, scheme="rk4"):
     """Gradient of a loss J(readings) with respect to mu_a(r), mu_s(r) by the
     reverse mode of the classic RK4 scheme that :func:`solve` integrates.
 
@@ -429,18 +450,21 @@ def adjoint_gradient(n, N, dx, c, dt, mu_a, mu_s, g, psi0_real, q_real, W, mu0,
     U = real_basis_transform(N)
     k = wavenumbers(n, dx)
     Sig, omega = potentials(mu_a, mu_s, g, N, W, mu0, mu1)
+    psi0_real = full_moments(psi0_real, M)
+    q_real = full_moments(q_real, M)
     q = None
     if q_real is not None:
-        q = to_complex_basis(np.asarray(q_real, float), U) * omega[None]
+        q = to_complex_basis(q_real, U) * omega[None]
 
     def f(y):
         return operator(y, Sig, q, B, k, c)
 
-    psi = (to_complex_basis(np.asarray(psi0_real, float), U).astype(complex)
+    psi = (to_complex_basis(psi0_real, U).astype(complex)
            if psi0_real is not None else np.zeros((M, n, n, n), complex))
     states = [psi]
+    stepper = euler_step if scheme == "euler" else rk4_step
     for _ in range(steps):
-        psi = rk4_step(psi, f, dt)
+        psi = stepper(psi, f, dt)
         states.append(psi)
     det = np.asarray(det_index, np.int64)
     lofa = np.array([sh_lm(a)[0] for a in range(M)])
@@ -461,6 +485,14 @@ def adjoint_gradient(n, N, dx, c, dt, mu_a, mu_s, g, psi0_real, q_real, W, mu0,
     inject(steps - 1)
     for s in range(steps - 1, -1, -1):
         u = states[s]
+        if scheme == "euler":
+            # u' = u + dt f(u): adjoint lam + dt L^T lam, gradient (dt lam, u)
+            kb0 = dt * lam
+            add_grad(kb0, to_real_basis(u, U))
+            lam = lam + operator_transpose(kb0, Sig, BR, k, c)
+            if s >= 1:
+                inject(s - 1)
+            continue
         k1 = f(u)
         k2 = f(u + 0.5 * dt * k1)
         k3 = f(u + 0.5 * dt * k2)

@@ -91,6 +91,7 @@ struct Ctl {
 // precision (float or double) and complex spectra interleave (re, im).
 struct StepArgs {
   int prec;                 // 0 = FP32, 1 = FP64
+  int scheme;               // 0 = nested RK4, 1 = forward Euler
   int N, M;                 // order and moment count
   void* stream;             // hipStream_t
   void* u;                  // state [M][n^3]

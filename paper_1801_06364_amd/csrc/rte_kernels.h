@@ -386,7 +386,7 @@ __device__ __forceinline__ void c2r_merge(V* pl, const V* tw) {
 }
 
 // Epilogue modes of the inverse pass.
-enum { EPI_MID = 0, EPI_FIRST = 1, EPI_LAST = 2, EPI_ADJ = 3 };
+enum { EPI_MID = 0, EPI_FIRST = 1, EPI_LAST = 2, EPI_ADJ = 3, EPI_EULER = 4 };
 
 // Pointwise epilogue of RB rows starting at row y0 of plane (b, z), on
 // (x_{2j}, x_{2j+1}) pairs:
@@ -394,7 +394,8 @@ enum { EPI_MID = 0, EPI_FIRST = 1, EPI_LAST = 2, EPI_ADJ = 3 };
 //     (EPI_FIRST: v = u; EPI_LAST: also phi_int += dt o (FP64) for the
 //     fluence moment and the partial sums of (o - u)^2 and o^2);
 //   EPI_ADJ         o = w - h Sigma_l v  -> dst, and u += o (u is the
-//     adjoint accumulator; no source term in the transposed operator).
+//     adjoint accumulator; no source term in the transposed operator);
+//   EPI_EULER       first and last stage at once (v = u, o -> u, bookkeeping).
 template <typename V, typename T, int NN, int RB, int LP, int BLOCK, int MODE>
 __device__ __forceinline__ void epilogue(const V* pl, int y0, int b, int z, const T* vin, T* u,
                                          T* dst, const T* __restrict__ sig, const T* __restrict__ q,
@@ -411,7 +412,7 @@ __device__ __forceinline__ void epilogue(const V* pl, int y0, int b, int z, cons
     const int e = y * n + 2 * j;
     const V w = pl[y * LP + j];
     const V uu = *reinterpret_cast<const V*>(u + poff + e);
-    const V vv = MODE == EPI_FIRST ? uu : *reinterpret_cast<const V*>(vin + poff + e);
+    const V vv = (MODE == EPI_FIRST || MODE == EPI_EULER) ? uu : *reinterpret_cast<const V*>(vin + poff + e);
     const V ss = *reinterpret_cast<const V*>(sg + e);
     T src0 = -ss.x * vv.x, src1 = -ss.y * vv.y;
     if (MODE != EPI_ADJ && hasq) {
@@ -427,7 +428,7 @@ __device__ __forceinline__ void epilogue(const V* pl, int y0, int b, int z, cons
     }
     const V o = cmk<V>(uu.x + w.x + h * src0, uu.y + w.y + h * src1);
     *reinterpret_cast<V*>(dst + poff + e) = o;
-    if (MODE == EPI_LAST && b == 0) {
+    if ((MODE == EPI_LAST || MODE == EPI_EULER) && b == 0) {
       double2* pi = reinterpret_cast<double2*>(phi_int + voff + e);
       double2 acc = *pi;
       acc.x += dt * double(o.x);
@@ -495,7 +496,7 @@ k_inv_plane(const typename cplx_of<T>::type* __restrict__ spec, const T* vin, T*
   const bool hasq = (q != nullptr) && qflag[z];
   epilogue<V, T, NN, n, LP, kPBlock, MODE>(pl, 0, b, z, vin, u, dst, sig, q, hasq, phi_int, h, dt, acc_d,
                                            acc_o);
-  if (MODE == EPI_LAST && b == 0) block_sum2<kPBlock>(smem, acc_d, acc_o, partial + 2 * z);
+  if ((MODE == EPI_LAST || MODE == EPI_EULER) && b == 0) block_sum2<kPBlock>(smem, acc_d, acc_o, partial + 2 * z);
 }
 
 // Inverse x transform + epilogue of RB rows per workgroup (grids whose
@@ -532,7 +533,7 @@ k_rows_inv(const typename cplx_of<T>::type* __restrict__ spec, const T* vin, T* 
   const bool hasq = (q != nullptr) && qflag[z];
   epilogue<V, T, NN, RB, LP, kZBlock, MODE>(pl, y0, b, z, vin, u, dst, sig, q, hasq, phi_int, h, dt, acc_d,
                                             acc_o);
-  if (MODE == EPI_LAST && b == 0) block_sum2<kZBlock>(smem, acc_d, acc_o, partial + 2 * zy);
+  if ((MODE == EPI_LAST || MODE == EPI_EULER) && b == 0) block_sum2<kZBlock>(smem, acc_d, acc_o, partial + 2 * zy);
 }
 
 // ------------------------------------------------------- end of step ---
@@ -635,6 +636,7 @@ hipError_t prepare_t(const StepArgs& a) {
     set(reinterpret_cast<const void*>(&k_rows_inv<T, NN, EPI_MID>), rows_lds<T, NN>());
     set(reinterpret_cast<const void*>(&k_rows_inv<T, NN, EPI_LAST>), rows_lds<T, NN>());
     set(reinterpret_cast<const void*>(&k_rows_inv<T, NN, EPI_ADJ>), rows_lds<T, NN>());
+    set(reinterpret_cast<const void*>(&k_rows_inv<T, NN, EPI_EULER>), rows_lds<T, NN>());
     set(reinterpret_cast<const void*>(&k_pencil<T, NN, PENCIL_YFWD>), zd_lds<T, NN>());
     set(reinterpret_cast<const void*>(&k_pencil<T, NN, PENCIL_YINV>), zd_lds<T, NN>());
   } else {
@@ -643,6 +645,7 @@ hipError_t prepare_t(const StepArgs& a) {
     set(reinterpret_cast<const void*>(&k_inv_plane<T, NN, EPI_MID>), plane_lds<T, NN>());
     set(reinterpret_cast<const void*>(&k_inv_plane<T, NN, EPI_LAST>), plane_lds<T, NN>());
     set(reinterpret_cast<const void*>(&k_inv_plane<T, NN, EPI_ADJ>), plane_lds<T, NN>());
+    set(reinterpret_cast<const void*>(&k_inv_plane<T, NN, EPI_EULER>), plane_lds<T, NN>());
   }
   set(reinterpret_cast<const void*>(&k_pencil<T, NN, PENCIL_ZDERIV>), zd_lds<T, NN>());
   return e;
@@ -726,10 +729,15 @@ hipError_t enqueue_t(const StepArgs& a, const OpArgs& op, ProfRec* pr) {
         (void)hipEventRecord(static_cast<hipEvent_t>(pr->ev0), st);
         pr->count = 0;
       }
-      enqueue_stage<T, NN, N, EPI_FIRST>(a, pr, kRkAlpha[0] * hc, 1.0, u, u, v);
-      enqueue_stage<T, NN, N, EPI_MID>(a, pr, kRkAlpha[1] * hc, 1.0, v, u, v);
-      enqueue_stage<T, NN, N, EPI_MID>(a, pr, kRkAlpha[2] * hc, 1.0, v, u, v);
-      enqueue_stage<T, NN, N, EPI_LAST>(a, pr, kRkAlpha[3] * hc, 1.0, v, u, u);
+      if (a.scheme == 1) {
+        // forward Euler (eq. 11 with the sign reading): u <- u + dt f(u)
+        enqueue_stage<T, NN, N, EPI_EULER>(a, pr, hc, 1.0, u, u, u);
+      } else {
+        enqueue_stage<T, NN, N, EPI_FIRST>(a, pr, kRkAlpha[0] * hc, 1.0, u, u, v);
+        enqueue_stage<T, NN, N, EPI_MID>(a, pr, kRkAlpha[1] * hc, 1.0, v, u, v);
+        enqueue_stage<T, NN, N, EPI_MID>(a, pr, kRkAlpha[2] * hc, 1.0, v, u, v);
+        enqueue_stage<T, NN, N, EPI_LAST>(a, pr, kRkAlpha[3] * hc, 1.0, v, u, u);
+      }
       hipLaunchKernelGGL((k_end_step<T>), dim3(1), dim3(kBlock), 0, st, u, a.det, a.ndet, a.readings, a.resid,
                          a.cap, a.partial, partial_count<NN>(), static_cast<Ctl*>(a.ctl));
       if (pr && pr->count < kMaxProfLaunches) {

@@ -38,6 +38,7 @@ inline bool config_ok(const rte_config* c) {
   if (c->pml_width > 0 && (!(c->pml_mu0 >= 0) || !(c->pml_mu1 >= 0))) return false;
   if (c->n_det < 0 || (c->n_det > 0 && !c->det_index)) return false;
   if (c->record_steps < 0) return false;
+  if (c->scheme != RTE_RK4 && c->scheme != RTE_EULER) return false;
   // grids up to 128 keep one n x (n/2+1) complex plane in LDS (160 KB per
   // CU); larger grids use row + pencil passes
   const size_t s = c->precision == RTE_FP64 ? 16 : 8;
@@ -120,6 +121,7 @@ struct rte_handle {
   rte::Layout lay;
   rte::StepArgs args;
   int n, N, M, prec;
+  int q_moments;
   double dt;
   bool has_q;
   hipStream_t stream;
@@ -148,11 +150,12 @@ void convert_upload(std::vector<T>& tmp, const double* src, size_t count) {
 }
 
 template <typename T>
-int upload_state_t(rte_handle* h, const double* psi) {
-  const size_t cnt = size_t(h->M) * h->n * h->n * h->n;
-  std::vector<T> tmp;
-  if (psi) convert_upload(tmp, psi, cnt);
-  else tmp.assign(cnt, T(0));
+int upload_state_t(rte_handle* h, const double* psi, int moments) {
+  const size_t V = size_t(h->n) * h->n * h->n;
+  const size_t cnt = size_t(h->M) * V;
+  std::vector<T> tmp(cnt, T(0));
+  if (psi)
+    for (size_t i = 0; i < size_t(moments) * V; ++i) tmp[i] = T(psi[i]);
   hipError_t e = hipMemcpyAsync(h->at<T>(h->lay.u), tmp.data(), cnt * sizeof(T), hipMemcpyHostToDevice,
                                 h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
@@ -236,7 +239,7 @@ int upload_tables_t(rte_handle* h, const rte_medium* med, const std::vector<doub
     std::vector<double> qm(size_t(h->M) * V);
     for (int a = 0; a < h->M; ++a)
       for (size_t i = 0; i < V; ++i) {
-        const double val = inside[i] ? med->q[size_t(a) * V + i] : 0.0;
+        const double val = (inside[i] && a < h->q_moments) ? med->q[size_t(a) * V + i] : 0.0;
         qm[size_t(a) * V + i] = val;
         if (val != 0.0) qflag[i / (size_t(n) * n)] = 1;
       }
@@ -335,6 +338,7 @@ int rte_create(const rte_config* cfg, const rte_medium* med, void* dev_ws, size_
   if (!out) return RTE_EINVAL;
   *out = nullptr;
   if (!config_ok(cfg) || !med || !med->mu_a || !med->mu_s || !med->g) return RTE_EINVAL;
+  if (med->psi0_moments < 0 || med->q_moments < 0) return RTE_EINVAL;
   const int n = cfg->n, N = cfg->order_N, M = (N + 1) * (N + 1);
   const size_t V = size_t(n) * n * n;
   for (size_t i = 0; i < V; ++i) {
@@ -363,6 +367,7 @@ int rte_create(const rte_config* cfg, const rte_medium* med, void* dev_ws, size_
   h->prec = cfg->precision;
   h->dt = cfg->dt_ps > 0 ? cfg->dt_ps : 0.2 * cfg->dx_mm / cfg->c_mm_ps;
   h->has_q = has_q;
+  h->q_moments = (med->q_moments > 0 && med->q_moments < M) ? med->q_moments : M;
   h->stream = reinterpret_cast<hipStream_t>(hip_stream);
   h->ws = reinterpret_cast<unsigned char*>(dev_ws);
   h->lay = L;
@@ -371,6 +376,7 @@ int rte_create(const rte_config* cfg, const rte_medium* med, void* dev_ws, size_
   h->use_graph = (h->stream != nullptr) && !(ng && ng[0] == '1');
   StepArgs& A = h->args;
   A.prec = h->prec;
+  A.scheme = cfg->scheme;
   A.N = N;
   A.M = M;
   A.stream = h->stream;
@@ -397,7 +403,9 @@ int rte_create(const rte_config* cfg, const rte_medium* med, void* dev_ws, size_
   int rc = to_code(hipError_t(launch_prepare(n, A)));
   if (!rc) rc = h->prec == RTE_FP64 ? upload_tables_t<double>(h, med, sig, inside, coef)
                                     : upload_tables_t<float>(h, med, sig, inside, coef);
-  if (!rc) rc = h->prec == RTE_FP64 ? upload_state_t<double>(h, med->psi0) : upload_state_t<float>(h, med->psi0);
+  const int pm = (med->psi0_moments > 0 && med->psi0_moments < M) ? med->psi0_moments : M;
+  if (!rc)
+    rc = h->prec == RTE_FP64 ? upload_state_t<double>(h, med->psi0, pm) : upload_state_t<float>(h, med->psi0, pm);
   if (!rc) {
     std::vector<double> sig0(sig.begin(), sig.begin() + V);
     rc = reset_run_state(h, growth_limit_of(h, med->psi0, med->q, sig0));
@@ -506,7 +514,7 @@ int rte_set_state(rte_handle* h, const double* in, size_t len) {
   rte::Ctl c;
   int rc = rte::read_ctl(h, &c);
   if (rc) return rc;
-  rc = h->prec == RTE_FP64 ? rte::upload_state_t<double>(h, in) : rte::upload_state_t<float>(h, in);
+  rc = h->prec == RTE_FP64 ? rte::upload_state_t<double>(h, in, h->M) : rte::upload_state_t<float>(h, in, h->M);
   if (rc) return rc;
   return rte::reset_run_state(h, c.growth_limit);
 }
@@ -643,6 +651,13 @@ int rte_adjoint(rte_handle* h, int64_t steps, int64_t every, void* adj_ws, size_
     }
     for (int64_t nn = n1 - 1; nn >= n0 && e == hipSuccess; --nn) {
       const void* un = seg + size_t(nn - n0) * F;
+      if (h->args.scheme == RTE_EULER) {
+        // u' = u + h F(u): lam <- lam + h F^T lam, gradient term (lam, u)
+        grad(w + A.lam, un, 1.0);
+        adj_stage(w + A.lam, w + A.xa, 1.0);
+        if (nn >= 1) inject(nn - 1);
+        continue;
+      }
       fwd_stage(0, un, un, w + A.v1);
       fwd_stage(1, un, w + A.v1, w + A.v2);
       fwd_stage(2, un, w + A.v2, w + A.v3);

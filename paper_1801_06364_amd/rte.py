@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "librte.so")
 
 RTE_OK, RTE_EINVAL, RTE_ENOMEM, RTE_EUNSTABLE, RTE_EDEVICE = 0, -1, -2, -3, -4
 RTE_FP32, RTE_FP64 = 0, 1
+RTE_RK4, RTE_EULER = 0, 1
 RTE_FLUENCE_NOW, RTE_FLUENCE_INTEGRATED = 0, 1
 
 EXPORTS = (
@@ -42,7 +43,7 @@ class rte_config(C.Structure):
         ("n", C.c_int32), ("order_N", C.c_int32), ("precision", C.c_int32),
         ("pml_width", C.c_int32), ("dx_mm", C.c_double), ("c_mm_ps", C.c_double),
         ("dt_ps", C.c_double), ("pml_mu0", C.c_double), ("pml_mu1", C.c_double),
-        ("n_det", C.c_int32), ("reserved0", C.c_int32),
+        ("n_det", C.c_int32), ("scheme", C.c_int32),
         ("det_index", C.POINTER(C.c_int64)), ("record_steps", C.c_int64),
     ]
 
@@ -51,7 +52,8 @@ class rte_medium(C.Structure):
     _fields_ = [
         ("mu_a", C.POINTER(C.c_double)), ("mu_s", C.POINTER(C.c_double)),
         ("g", C.POINTER(C.c_double)), ("psi0", C.POINTER(C.c_double)),
-        ("q", C.POINTER(C.c_double)),
+        ("q", C.POINTER(C.c_double)), ("psi0_moments", C.c_int32),
+        ("q_moments", C.c_int32),
     ]
 
 
@@ -127,11 +129,11 @@ def _f64(a):
 
 
 def make_config(n, N, precision, dx, c, dt, W, mu0, mu1, det_index=None,
-                record_steps=0):
+                record_steps=0, scheme=RTE_RK4):
     det = np.ascontiguousarray(det_index if det_index is not None else [], np.int64)
     cfg = rte_config(n=n, order_N=N, precision=precision, pml_width=W, dx_mm=dx,
                      c_mm_ps=c, dt_ps=dt, pml_mu0=mu0, pml_mu1=mu1,
-                     n_det=int(det.size), reserved0=0,
+                     n_det=int(det.size), scheme=int(scheme),
                      det_index=det.ctypes.data_as(C.POINTER(C.c_int64)) if det.size else None,
                      record_steps=int(record_steps))
     return cfg, det
@@ -159,13 +161,16 @@ class Solver:
 
     def __init__(self, n, N, dx, c, dt, mu_a, mu_s, g, psi0=None, q=None, W=0,
                  mu0=0.01, mu1=1.0, precision="f32", det_index=None,
-                 record_steps=0, stream=None, device="cuda"):
+                 record_steps=0, stream=None, device="cuda", scheme="rk4"):
+        """psi0 / q: arrays of shape (K, n, n, n) holding the K leading
+        real-basis moments (K <= M; the rest are zero), or None."""
         import torch
         self.n, self.N, self.M = n, N, (N + 1) ** 2
         prec = RTE_FP64 if precision in ("f64", RTE_FP64) else RTE_FP32
         self.precision = prec
+        sch = RTE_EULER if scheme in ("euler", RTE_EULER) else RTE_RK4
         self.cfg, self._det = make_config(n, N, prec, dx, c, dt, W, mu0, mu1,
-                                          det_index, record_steps)
+                                          det_index, record_steps, sch)
         self.n_det = int(self._det.size)
         nbytes = rte_workspace_bytes(self.cfg)
         if nbytes == 0:
@@ -173,7 +178,12 @@ class Solver:
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(device)
         arrs = [_f64(mu_a), _f64(mu_s), _f64(g), _f64(psi0), _f64(q)]
-        med = rte_medium(*[_dptr(a) for a in arrs])
+        pm = 0 if psi0 is None else arrs[3].size // n ** 3
+        qm = 0 if q is None else arrs[4].size // n ** 3
+        if (psi0 is not None and (pm * n ** 3 != arrs[3].size or pm > self.M)) or \
+                (q is not None and (qm * n ** 3 != arrs[4].size or qm > self.M)):
+            raise RteError(RTE_EINVAL, "psi0 / q must hold whole leading moments")
+        med = rte_medium(*[_dptr(a) for a in arrs], pm, qm)
         self._keep = arrs
         h = C.c_void_p()
         rc = lib().rte_create(C.byref(self.cfg), C.byref(med),
@@ -188,7 +198,8 @@ class Solver:
         args = dict(n=wl.n, N=wl.N, dx=wl.dx, c=wl.c, dt=wl.dt, mu_a=wl.mu_a,
                     mu_s=wl.mu_s, g=wl.g, psi0=wl.psi0, q=wl.q, W=wl.W,
                     mu0=wl.mu0, mu1=wl.mu1, precision=wl.precision,
-                    det_index=wl.det_index, record_steps=wl.steps)
+                    det_index=wl.det_index, record_steps=wl.steps,
+                    scheme=getattr(wl, "scheme", "rk4"))
         args.update(kw)
         return cls(**args)
 

@@ -25,4 +25,6 @@ from .phantoms import (  # noqa: F401
     sphere_maps,
     workload,
     WORKLOADS,
+    RequestSpec,
+    serving_requests,
 )

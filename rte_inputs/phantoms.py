@@ -168,7 +168,10 @@ def outer_layer_detectors(n: int, W: int, count: int, seed: int):
 
 @dataclass
 class Workload:
-    """One solve: grid, order, medium, initial state, source, detectors."""
+    """One solve: grid, order, medium, initial state, source, detectors.
+
+    ``psi0`` / ``q`` hold the leading K <= (N+1)^2 real-basis moments
+    (shape (K, n, n, n)); the remaining moments are zero."""
     name: str
     n: int
     N: int
@@ -187,6 +190,7 @@ class Workload:
     q: Optional[np.ndarray]
     det_index: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int64))
     steady_tol: float = 0.0
+    scheme: str = "rk4"       # "rk4" | "euler"
 
     @property
     def M(self) -> int:
@@ -210,7 +214,7 @@ def workload(name: str, n: Optional[int] = None, steps: Optional[int] = None,
         mu_a, mu_s, g = homogeneous_maps(n, 0.01, 10.0, 0.9)
         return Workload(name, n, 1, precision or "f64", dx, c, _dt(dx, c), W,
                         0.01, 1.0, steps if steps is not None else 100,
-                        mu_a, mu_s, g, gaussian_ic(n, 1), None)
+                        mu_a, mu_s, g, gaussian_ic(n, 0), None)
     if name == "p7_spheres":        # P_7, 128^3, FP32, 5 inclusions, 2000 steps
         n = n or 128
         dx = 0.25
@@ -221,7 +225,7 @@ def workload(name: str, n: Optional[int] = None, steps: Optional[int] = None,
         det = outer_layer_detectors(n, W, 32, seed=2)
         return Workload(name, n, 7, precision or "f32", dx, c, _dt(dx, c), W,
                         0.01, 1.0, steps if steps is not None else 2000,
-                        mu_a, mu_s, g, delta_ic(n, 7), None, det)
+                        mu_a, mu_s, g, delta_ic(n, 0), None, det)
     if name == "p5_steady":         # P_5, 256^3, FP32, log-normal, steady state
         n = n or 256
         dx = 0.25
@@ -242,8 +246,69 @@ def workload(name: str, n: Optional[int] = None, steps: Optional[int] = None,
         det = outer_layer_detectors(n, W, 16, seed=5)
         return Workload(name, n, 3, precision or "f32", dx, c, _dt(dx, c), W,
                         0.01, 1.0, steps if steps is not None else 1000,
-                        mu_a, mu_s, g, gaussian_ic(n, 3), None, det)
+                        mu_a, mu_s, g, gaussian_ic(n, 0), None, det)
+    if name == "paper_pml_steady":  # P_7, 64^3, 50 mm cube, half-cosine layer, Euler
+        # steady state with an absorbing layer as in the paper's second
+        # experiment: a 35.5 mm real domain inside a 50 mm grid, mu_a 0.01,
+        # mu_s 10, g 0.95, constant isotropic Gaussian source (1/e diameter
+        # 1.5 mm) offset 8 mm along x, forward Euler with dt 0.04 ps
+        n = n or 64
+        L = 50.0
+        dx = L / n
+        W = int(round((L - 35.5) / 2 / dx))
+        mu_a, mu_s, g = homogeneous_maps(n, 0.01, 10.0, 0.95)
+        sigma = 0.75 / np.sqrt(2.0) / dx            # exp(-r^2/(2 s^2)) = 1/e at r = 0.75 mm
+        centre = (n // 2, n // 2, n // 2 + int(round(8.0 / dx)))
+        q = gaussian_ic(n, 0, center=centre, sigma=sigma)
+        return Workload(name, n, 7, precision or "f32", dx, c, 0.04, W, 0.01, 1.0,
+                        steps if steps is not None else 25000, mu_a, mu_s, g, None, q,
+                        np.zeros(0, np.int64), scheme="euler")
     raise KeyError(name)
 
 
-WORKLOADS = ("p1_gauss", "p7_spheres", "p5_steady", "p3_adjoint")
+WORKLOADS = ("p1_gauss", "p7_spheres", "p5_steady", "p3_adjoint", "paper_pml_steady")
+
+
+# ------------------------------------------------------------- serving ---
+
+@dataclass
+class RequestSpec:
+    """One solve request of the serving trace (inputs built on demand)."""
+    rid: int
+    n: int
+    N: int
+    steps: int
+    nspheres: int             # 0: homogeneous background
+    seed: int
+    gap: float                # unit-mean exponential inter-arrival gap
+
+    def workload(self, precision: str = "f32") -> Workload:
+        n = self.n
+        W = n // 8
+        dx, c = 0.25, 0.3
+        if self.nspheres == 0:
+            mu_a, mu_s, g = homogeneous_maps(n, 0.01, 10.0, 0.9)
+        else:
+            r = (max(1, n // 32), max(1, n // 8))
+            mu_a, mu_s, g = sphere_maps(n, W, self.nspheres, self.seed, radius=r)
+        psi0 = gaussian_ic(n, 0)        # only the isotropic moment is non-zero
+        return Workload(f"req{self.rid}", n, self.N, precision, dx, c, _dt(dx, c), W, 0.01,
+                        1.0, self.steps, mu_a, mu_s, g, psi0, None)
+
+
+def serving_requests(count: int = 256, seed: int = 4, sizes=(32, 48, 64, 96, 128),
+                     orders=(1, 3, 5, 7), steps=(200, 1000)):
+    """Seeded request trace: grid uniform in ``sizes``, P_N order uniform in
+    ``orders``, step count uniform in ``steps`` (inclusive), half
+    homogeneous and half with 1-5 spherical inclusions, Poisson arrivals
+    (unit-mean exponential gaps, scaled by the server to the wanted rate)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = int(rng.choice(sizes))
+        N = int(rng.choice(orders))
+        st = int(rng.integers(steps[0], steps[1] + 1))
+        ns = 0 if rng.random() < 0.5 else int(rng.integers(1, 6))
+        out.append(RequestSpec(i, n, N, st, ns, int(rng.integers(1 << 30)),
+                               float(rng.exponential(1.0))))
+    return out

@@ -42,7 +42,8 @@ def _solver(wl, **kw):
 def _oracle(name, n, steps):
     wl = ri.workload(name, n=n, steps=steps)
     return pn.solve(wl.n, wl.N, wl.dx, wl.c, wl.dt, wl.mu_a, wl.mu_s, wl.g, wl.psi0,
-                    wl.q, wl.W, wl.mu0, wl.mu1, wl.steps, det_index=wl.det_index)
+                    wl.q, wl.W, wl.mu0, wl.mu1, wl.steps, det_index=wl.det_index,
+                    scheme=wl.scheme)
 
 
 CASES = [
@@ -53,6 +54,7 @@ CASES = [
     ("p5_steady", 32, 20),      # P_5 with the collimated slab source
     ("p7_spheres", 16, 8),      # smallest grid
     ("p3_adjoint", 96, 3),      # radix-3, larger
+    ("paper_pml_steady", 32, 15),   # forward Euler (eq. 11), source, layer
 ]
 
 

@@ -38,17 +38,19 @@ def test_operator_transpose_dot_product():
     assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1.0)
 
 
-def _loss(wl_args, det, target, mu_a, mu_s):
+def _loss(wl_args, det, target, mu_a, mu_s, scheme="rk4"):
     n, N, dx, c, dt, g, psi0, W, steps = wl_args
     out = pn.solve(n, N, dx, c, dt, mu_a, mu_s, g, psi0, None, W, 0.01, 1.0, steps,
-                   det_index=det, return_state=False)
+                   det_index=det, return_state=False, scheme=scheme)
     r = out["readings"]
     return float(((r - target) ** 2).sum()), r
 
 
-def test_adjoint_matches_central_differences():
+@pytest.mark.parametrize("scheme", ["rk4", "euler"])
+def test_adjoint_matches_central_differences(scheme):
     """dJ/dmu_a and dJ/dmu_s from the reverse sweep equal central finite
-    differences of the forward solver at interior voxels (FP64)."""
+    differences of the forward solver at interior voxels (FP64), for the
+    RK4 scheme and the first-order step of eq. (11)."""
     rng, n, N, W, mu_a, mu_s, g = _tiny(2)
     dx, c = 0.5, 0.3
     dt = 0.2 * dx / c
@@ -57,10 +59,10 @@ def test_adjoint_matches_central_differences():
     det = np.array([(3 * n + 4) * n + 2, (5 * n + 2) * n + 5], np.int64)
     target = rng.uniform(0.0, 0.01, (steps, det.size))
     args = (n, N, dx, c, dt, g, psi0, W, steps)
-    J0, r = _loss(args, det, target, mu_a, mu_s)
+    J0, r = _loss(args, det, target, mu_a, mu_s, scheme)
     djdr = 2.0 * (r - target)
     ga, gs = pn.adjoint_gradient(n, N, dx, c, dt, mu_a, mu_s, g, psi0, None, W, 0.01, 1.0,
-                                 steps, det, djdr)
+                                 steps, det, djdr, scheme=scheme)
     for (z, y, x) in [(3, 3, 3), (4, 2, 5), (5, 5, 2)]:
         for grad, which in ((ga, "a"), (gs, "s")):
             eps = 1e-5
@@ -68,9 +70,9 @@ def test_adjoint_matches_central_differences():
             base = ma if which == "a" else ms
             h = eps * base[z, y, x]
             base[z, y, x] += h
-            Jp, _ = _loss(args, det, target, ma, ms)
+            Jp, _ = _loss(args, det, target, ma, ms, scheme)
             base[z, y, x] -= 2 * h
-            Jm, _ = _loss(args, det, target, ma, ms)
+            Jm, _ = _loss(args, det, target, ma, ms, scheme)
             fd = (Jp - Jm) / (2 * h)
             assert abs(fd - grad[z, y, x]) <= 1e-6 * max(abs(fd), 1e-12) + 1e-14, (which, fd, grad[z, y, x])
     # zero inside the absorbing layer

@@ -265,6 +265,30 @@ def test_single_mode_equals_rk4_polynomial_and_expm(N):
     assert 12.0 < ratio < 20.0, errs
 
 
+def test_single_mode_forward_euler():
+    """Eq. (11) (first-order explicit step, sign reading R1): a single
+    Fourier mode evolves as (I + dt M(k))^n exactly."""
+    n, N, dx, c = 8, 2, 0.5, 0.3
+    M = (N + 1) ** 2
+    rng = np.random.default_rng(9)
+    v = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+    f = (2, 1, -3)
+    mua, mus, g = 0.05, 3.0, 0.8
+    ma, ms, gg = ri.homogeneous_maps(n, mua, mus, g)
+    sig = [mua + mus * (1 - g ** l) for l in range(N + 1)]
+    k = pn.wavenumbers(n, dx)
+    kv = (k[f[0]], k[f[1]], k[f[2]])
+    U = pn.real_basis_transform(N)
+    dt, steps = 0.05, 7
+    out = pn.solve(n, N, dx, c, dt, ma, ms, gg, ri.fourier_mode_ic(n, N, f, v), None, 0,
+                   0.01, 1.0, steps, scheme="euler")
+    I = np.eye(M)
+    Rk = np.linalg.matrix_power(I + dt * pn.mode_matrix(N, kv, sig, c), steps)
+    Rmk = np.linalg.matrix_power(I + dt * pn.mode_matrix(N, tuple(-t for t in kv), sig, c), steps)
+    ref = _mode_state(n, N, f, v, U, Rk, Rmk)
+    assert np.abs(out["state"] - ref).max() < 1e-13 * np.abs(ref).max()
+
+
 def test_k0_decay_and_integrated_fluence():
     """C-P9: a uniform field in a homogeneous medium has only the k=0 mode;
     each degree decays by the scalar RK4 factor R(-c dt Sigma_l) per step
