@@ -112,6 +112,9 @@ def traffic_for(kind: str, workload: str):
 def serving_bench(a):
     """Continuous batching vs one-at-a-time on the seeded request trace:
     Poisson arrivals at 1.5 / (mean one-at-a-time service time)."""
+    # one hardware queue per request stream (HIP's default is 4 per process),
+    # set before the runtime initialises
+    os.environ.setdefault("GPU_MAX_HW_QUEUES", str(max(4, min(16, a.slots))))
     import numpy as np
     import torch
 
@@ -120,7 +123,8 @@ def serving_bench(a):
 
     torch.cuda.set_device(0)
     specs = ri.serving_requests(count=a.requests, seed=4)
-    srv = serving.Server(budget_bytes=int(a.budget_gib * 2 ** 30), max_slots=a.slots)
+    srv = serving.Server(budget_bytes=int(a.budget_gib * 2 ** 30), max_slots=a.slots,
+                         large_slots=a.large_slots)
     # warm-up: one small request (library load, first launches), not reported
     srv.service_times([ri.RequestSpec(-1, 32, 1, 5, 0, 0, 1.0)])
     print(f"[serving] {len(specs)} requests; measuring one-at-a-time service times",
@@ -143,7 +147,8 @@ def serving_bench(a):
                                   "P_N in {1,3,5,7}, 200-1000 RK4 steps, half homogeneous / half 1-5 "
                                   "inclusions, Gaussian pulse; Poisson arrivals at 1.5 / mean "
                                   "one-at-a-time service time",
-                      "budget_GiB": a.budget_gib, "slots": a.slots, "rate_per_s": rate,
+                      "budget_GiB": a.budget_gib, "slots": a.slots, "large_slots": a.large_slots,
+                      "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES"), "rate_per_s": rate,
                       "mean_service_s": float(svc.mean())},
            "batched": bs, "one_at_a_time": fs,
            "speedup_p50": fs["p50_latency_s"] / bs["p50_latency_s"],
@@ -199,7 +204,8 @@ def main():
                     help="serve the seeded Poisson request trace instead (separate JSON line)")
     ap.add_argument("--requests", type=int, default=256)
     ap.add_argument("--budget-gib", type=float, default=12.0)
-    ap.add_argument("--slots", type=int, default=12)
+    ap.add_argument("--slots", type=int, default=16)
+    ap.add_argument("--large-slots", type=int, default=2)
     ap.add_argument("--no-accuracy", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:

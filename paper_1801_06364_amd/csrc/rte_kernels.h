@@ -144,13 +144,16 @@ k_fwd_plane(const T* __restrict__ src, typename cplx_of<T>::type* __restrict__ s
 //                  not fit in LDS).
 enum { PENCIL_ZDERIV = 0, PENCIL_YFWD = 1, PENCIL_YINV = 2 };
 
+#ifndef RTE_ZDW
+#define RTE_ZDW 16
+#endif
 constexpr int zd_width(int H) {
-  int t = 16;
+  int t = RTE_ZDW;
   while (t > 1 && H % t != 0) t /= 2;
   return t;
 }
 template <typename T, int NN> struct ZdShape {
-  static constexpr int TZ = zd_width(NN / 2);   // largest power of two <= 16 dividing n/2
+  static constexpr int TZ = zd_width(NN / 2);   // largest power of two <= RTE_ZDW dividing n/2
   static constexpr int PITCH = NN + 1;
   static constexpr int NTILE = (NN / 2) / TZ;
   static_assert(NTILE * TZ == NN / 2, "tiles must cover the half spectrum");

@@ -13,6 +13,13 @@ admitted requests start while earlier ones are still running. A request
 retires when the event recorded after its last step completes; its
 workspace is released and the next request can be admitted.
 
+Admission has two lanes, each first-come first-served: requests whose
+workspace exceeds ``large_bytes`` (large grids / high orders, which on their
+own already keep HBM busy) share ``large_slots`` slots, the others the
+remaining slots, so a short request never queues behind a long one and no
+request is overtaken within its lane (no starvation). The total resident
+workspace never exceeds the budget.
+
 The one-at-a-time baseline serves the same trace first-come first-served on
 one stream: each request's service time is measured alone, and the FIFO
 single-server queue is replayed from those times.
@@ -88,14 +95,19 @@ def updates_of(spec) -> int:
 
 class Server:
     """Continuous batching over ``max_slots`` concurrent solves within an
-    HBM budget of ``budget_bytes``."""
+    HBM budget of ``budget_bytes``; at most ``large_slots`` of them may be
+    requests larger than ``large_bytes``."""
 
     def __init__(self, budget_bytes: int = 12 << 30, max_slots: int = 12,
-                 precision: str = "f32", keep_fluence: bool = False):
+                 precision: str = "f32", keep_fluence: bool = False,
+                 large_bytes: int = 512 << 20, large_slots: int = 2):
         import torch
         self.torch = torch
         self.budget = int(budget_bytes)
         self.max_slots = int(max_slots)
+        self.large_bytes = int(large_bytes)
+        self.large_slots = max(1, min(int(large_slots), self.max_slots - 1)) \
+            if self.max_slots > 1 else 1
         self.precision = precision
         self.keep = keep_fluence
         self.streams = [torch.cuda.Stream() for _ in range(self.max_slots)]
@@ -117,55 +129,62 @@ class Server:
     def serve(self, specs: List, arrivals: List[float]) -> Report:
         """Serve requests whose arrival times (seconds from start) are given."""
         order = sorted(range(len(specs)), key=lambda i: arrivals[i])
-        queue = collections.deque(order)
+        incoming = collections.deque(order)
+        sizes = [footprint(sp, self.precision) for sp in specs]
+        lanes = {False: collections.deque(), True: collections.deque()}   # large?
+        slots = {True: list(range(self.large_slots)),
+                 False: list(range(self.large_slots, self.max_slots))}
+        if not slots[False]:
+            slots[False] = slots[True]
         rep = Report("batched")
-        free = list(range(self.max_slots))
-        active = {}            # slot -> (index, solver, event, bytes)
+        active = {}            # slot -> (index, solver, event, bytes, large)
         resident = 0
         t0 = time.perf_counter()
-        while queue or active:
+        while incoming or active or lanes[False] or lanes[True]:
             now = time.perf_counter() - t0
             progressed = False
             for slot in list(active):
-                i, solver, ev, nb = active[slot]
+                i, solver, ev, nb, big = active[slot]
                 if ev.query():
                     res = rep.results[specs[i].rid]
                     self._finish(res, solver, t0)
                     solver.close()
                     del active[slot]
-                    free.append(slot)
+                    slots[big].append(slot)
                     resident -= nb
                     progressed = True
-            while queue and free:
-                i = queue[0]
-                if arrivals[i] > now:
-                    break
-                nb = footprint(specs[i], self.precision)
-                if resident + nb > self.budget and active:
-                    break                   # wait for memory; keep FIFO order
-                queue.popleft()
-                slot = free.pop()
-                spec = specs[i]
-                res = Result(spec.rid, arrivals[i], admitted=time.perf_counter() - t0,
-                             updates=updates_of(spec))
-                rep.results[spec.rid] = res
-                try:
-                    solver = rte.Solver.from_workload(spec.workload(self.precision),
-                                                      stream=self.streams[slot], record_steps=0)
-                    solver.step(spec.steps)
-                except rte.RteError as e:
-                    res.ok, res.error = False, str(e)
-                    res.finished = time.perf_counter() - t0
-                    free.append(slot)
-                    continue
-                ev = self.torch.cuda.Event()
-                ev.record(self.streams[slot])
-                active[slot] = (i, solver, ev, nb)
-                resident += nb
-                rep.peak_resident_bytes = max(rep.peak_resident_bytes, resident)
-                rep.peak_slots = max(rep.peak_slots, len(active))
-                progressed = True
-                now = time.perf_counter() - t0
+            while incoming and arrivals[incoming[0]] <= now:
+                i = incoming.popleft()
+                lanes[sizes[i] > self.large_bytes].append(i)
+            for big in (False, True):
+                q = lanes[big]
+                while q and slots[big]:
+                    i = q[0]
+                    nb = sizes[i]
+                    if resident + nb > self.budget and active:
+                        break               # wait for memory; keep FIFO order
+                    q.popleft()
+                    slot = slots[big].pop()
+                    spec = specs[i]
+                    res = Result(spec.rid, arrivals[i], admitted=time.perf_counter() - t0,
+                                 updates=updates_of(spec))
+                    rep.results[spec.rid] = res
+                    try:
+                        solver = rte.Solver.from_workload(spec.workload(self.precision),
+                                                          stream=self.streams[slot], record_steps=0)
+                        solver.step(spec.steps)
+                    except rte.RteError as e:
+                        res.ok, res.error = False, str(e)
+                        res.finished = time.perf_counter() - t0
+                        slots[big].append(slot)
+                        continue
+                    ev = self.torch.cuda.Event()
+                    ev.record(self.streams[slot])
+                    active[slot] = (i, solver, ev, nb, big)
+                    resident += nb
+                    rep.peak_resident_bytes = max(rep.peak_resident_bytes, resident)
+                    rep.peak_slots = max(rep.peak_slots, len(active))
+                    progressed = True
             if not progressed:
                 time.sleep(2e-4)
         rep.makespan = time.perf_counter() - t0 - (min(arrivals) if arrivals else 0.0)
