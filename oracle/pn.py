@@ -525,3 +525,35 @@ def adjoint_gradient(n, N, dx, c, dt, mu_a, mu_s, g, psi0_real, q_real, W, mu0,
     gmua = gsig.sum(axis=0) * omega
     gmus = sum((1.0 - g ** l) * gsig[l] for l in range(N + 1)) * omega
     return gmua, gmus
+
+
+# --------------------------------------------------------- steady state ---
+
+def steady_state(n, N, dx, c, mu_a, mu_s, g, q_real, W, mu0, mu1, tol=1e-12,
+                 workers=None):
+    """Steady state of the semi-discrete system: the u with ``f(u) = 0``,
+    i.e. ``(S + Sigma) u = q`` in the real basis (the time-marched solution
+    approaches it; Sec. II.A). Solved with SciPy's GMRES on the oracle's
+    operator (a library Krylov routine as the solver step); returns the
+    real-basis state."""
+    import scipy.sparse.linalg as spla
+    M = (N + 1) ** 2
+    B = coupling_matrices(N)
+    U = real_basis_transform(N)
+    k = wavenumbers(n, dx)
+    Sig, omega = potentials(mu_a, mu_s, g, N, W, mu0, mu1)
+    qR = full_moments(q_real, M) * omega[None]
+    size = M * n ** 3
+
+    def A(xflat):
+        x = to_complex_basis(xflat.reshape(M, n, n, n), U).astype(complex)
+        # f(x) = c (-(S + Sigma) x) for q = 0, so (S + Sigma) x = -f(x) / c
+        fx = operator(x, Sig, None, B, k, c, workers)
+        return (-to_real_basis(fx, U) / c).ravel()
+
+    op = spla.LinearOperator((size, size), matvec=A, dtype=float)
+    b = qR.ravel()
+    x, info = spla.gmres(op, b, rtol=tol, atol=0.0, restart=60, maxiter=400)
+    if info != 0:
+        raise RuntimeError(f"oracle steady-state GMRES did not converge (info={info})")
+    return x.reshape(M, n, n, n)

@@ -400,6 +400,10 @@ def test_steady_state_matches_direct_solve():
     out = pn.solve(n, N, dx, c, dt, mua, mus, g, None, qR, W, 0.01, 1.0, 3000)
     assert np.abs(out["state"] - ref).max() < 1e-10 * np.abs(ref).max()
     assert out["residual"][-1] < 1e-12
+    # the Krylov steady state (library GMRES on the oracle operator) equals
+    # the direct dense solve
+    ss = pn.steady_state(n, N, dx, c, mua, mus, g, qR, W, 0.01, 1.0, tol=1e-13)
+    assert np.abs(ss - ref).max() < 1e-10 * np.abs(ref).max()
 
 
 # ------------------------------------------------------ boundary layer ---
