@@ -586,16 +586,19 @@ def expo_advance(n, N, dx, c, mu_a, mu_s, g, psi0_real, q_real, T):
          else sfft.fftn(to_complex_basis(p0, U).astype(complex), axes=(1, 2, 3)))
     qh = (np.zeros((M, n, n, n), complex) if q0 is None
           else sfft.fftn(to_complex_basis(q0, U).astype(complex), axes=(1, 2, 3)))
+    from threadpoolctl import threadpool_limits
     Bx, By, Bz = B
     D = np.diag([sig[sh_lm(i)[0]] for i in range(M)]).astype(complex)
     out = np.empty_like(a)
     G = np.zeros((M + 1, M + 1), complex)
-    for z in range(n):
-        for y in range(n):
-            for x in range(n):
-                # T M(k), M(k) = -c (i k.B + Sigma): the mode generator
-                G[:M, :M] = (-c * T) * (1j * (k[x] * Bx + k[y] * By + k[z] * Bz) + D)
-                G[:M, M] = (T * c) * qh[:, z, y, x]
-                E = expm(G)
-                out[:, z, y, x] = E[:M, :M] @ a[:, z, y, x] + E[:M, M]
+    # small dense products: one BLAS thread is far faster than many
+    with threadpool_limits(limits=1):
+        for z in range(n):
+            for y in range(n):
+                for x in range(n):
+                    # T M(k), M(k) = -c (i k.B + Sigma): the mode generator
+                    G[:M, :M] = (-c * T) * (1j * (k[x] * Bx + k[y] * By + k[z] * Bz) + D)
+                    G[:M, M] = (T * c) * qh[:, z, y, x]
+                    E = expm(G)
+                    out[:, z, y, x] = E[:M, :M] @ a[:, z, y, x] + E[:M, M]
     return to_real_basis(sfft.ifftn(out, axes=(1, 2, 3)), U)
