@@ -175,6 +175,47 @@ int rte_forward_checkpointed(rte_handle* h, int64_t steps, int64_t every, void* 
 int rte_adjoint(rte_handle* h, int64_t steps, int64_t every, void* adj_ws, size_t adj_bytes,
                 const double* dj_dr, double* grad_mu_a, double* grad_mu_s);
 
+/* ---- Steady state by a Krylov solve ---------------------------------
+ * Instead of marching to steady state (Sec. II.A notes the steady state can
+ * be found from the time-integrated operator with a Krylov method), solve
+ * A u = q with A = S + Sigma (streaming plus per-degree loss, so that
+ * c (-A u + q) = 0) by restarted GMRES. Vectors stay on the device; only the
+ * small Hessenberg system crosses to the host. Inner product: sum over
+ * moments of (2l+1) x_a y_a (orthonormal-basis coefficients), in which A is
+ * positive real. The current state u is the initial guess and receives the
+ * solution (read it back with rte_fluence / rte_get_state).
+ *
+ * rte_krylov_workspace_bytes: device bytes of the GMRES workspace
+ * (restart + 1 basis vectors), 1 <= restart <= 31.
+ * rte_steady_gmres: iterate until ||q - A u|| / ||q|| <= tol (weighted
+ * norms) or max_iters Arnoldi steps; *iters and *rel_residual receive the
+ * Arnoldi steps taken and the final true relative residual. */
+size_t rte_krylov_workspace_bytes(const rte_config* cfg, int32_t restart);
+int rte_steady_gmres(rte_handle* h, int32_t restart, int64_t max_iters, double tol, void* kws,
+                     size_t kbytes, int64_t* iters, double* rel_residual);
+
+/* ---- Exact propagation in homogeneous media --------------------------
+ * The paper integrates the time-domain form analytically to obtain an
+ * implicit operator (Sec. II.A) and reports exponential integrators that
+ * take arbitrary time steps in homogeneous media (Sec. IV). In a
+ * homogeneous medium on the periodic grid (no boundary layer) every Fourier
+ * mode of the moment vector evolves independently,
+ *   da/dt = M(k) a + c q(k),   M(k) = -c (i k.B + Sigma),
+ * so the state after a time T is exp(T M) a + int_0^T exp(s M) ds c q per
+ * mode, with no time-step error and no stability limit on T.
+ *
+ * rte_expo_advance: advance the handle's state by t_ps picoseconds this way
+ * (t_ps >= 0; 0 is a no-op). Per spectral point the exponential is a
+ * truncated Taylor series in substeps whose remainder is bounded below the
+ * working precision's unit roundoff (2^-24 FP32, 2^-53 FP64). Requires a
+ * handle created with constant mu_a, mu_s, g and pml_width 0 (else
+ * RTE_EINVAL); refuses a t_ps so large that a spectral point would need more
+ * than 10^6 substeps (RTE_EINVAL: split it into shorter advances) and a
+ * handle whose run was flagged unstable (RTE_EUNSTABLE). Leaves the step
+ * count, readings and integrated fluence unchanged; clears a converged
+ * run's stop flag. Uses the handle's spectrum buffers; synchronises. */
+int rte_expo_advance(rte_handle* h, double t_ps);
+
 /* Run nsteps steps with plain launches, timing every kernel with HIP
  * events on the handle's stream, and store the summed milliseconds of each
  * kernel class in ms[0..8] and the launch counts in counts[0..8]. Classes:

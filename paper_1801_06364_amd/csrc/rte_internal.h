@@ -10,6 +10,9 @@ namespace rte {
 
 constexpr int kMaxOrder = 7;                       // N <= 7
 constexpr int kMaxMoments = (kMaxOrder + 1) * (kMaxOrder + 1);
+// Largest Taylor degree of the exact propagation per working precision.
+constexpr int kTaylorMaxF32 = 14;
+constexpr int kTaylorMaxF64 = 24;
 constexpr int kMaxSlots = 12;                      // coupling slots per row
 
 constexpr int isqrt_c(int a) {
@@ -73,6 +76,11 @@ void potentials(int n, int N, int W, double mu0, double mu1,
 bool grid_supported(int n);
 
 // ------------------------------------------------------- step launcher --
+
+// Krylov solver limits: basis vectors (restart + 1) and dot-product
+// partial sums (blocks x basis vectors).
+constexpr int kMaxBasisVectors = 32;
+constexpr int kDotPartials = 1024 * kMaxBasisVectors;
 
 // Device control block: step counter and run/stop flags shared by every
 // kernel of a step (kernels return at once when stop != 0).
@@ -138,7 +146,13 @@ enum {
   OP_STAGE = 1,      // one forward stage into a given buffer (no bookkeeping)
   OP_ADJ_STAGE = 2,  // one transposed stage: y = coef h F~(x), u += y
   OP_ADJ_GRAD = 3,   // gradient accumulation from (x, y)
-  OP_ADJ_INJECT = 4  // detector adjoint sources into u
+  OP_ADJ_INJECT = 4, // detector adjoint sources into u
+  OP_APPLY = 5,      // y = (S + Sigma) x (steady-state operator)
+  OP_WDOTS = 6,      // gmus[i] = <x_i, y>_W, i < count (x: count vectors)
+  OP_COMBINE = 7,    // y = coef * y + scale * sum_i djdr[i] x_i
+  OP_SCALE = 8,      // y = x / djdr[0]
+  OP_RHS_MINUS = 9,  // y = x - y (x may be null)
+  OP_EXPO = 10       // u <- exact propagation over time coef (homogeneous medium)
 };
 struct OpArgs {
   int kind;
@@ -150,7 +164,12 @@ struct OpArgs {
   const double* gin; // g inside the real domain, > 1 in the layer
   double* gmua;      // gradient accumulators (FP64, n^3)
   double* gmus;
-  const double* djdr;// adjoint sources of one step's readings (ndet)
+  const double* djdr;// adjoint sources of one step's readings (ndet); device
+                     // coefficients of OP_COMBINE / OP_SCALE
+  int count;         // OP_WDOTS / OP_COMBINE: number of basis vectors
+  double scale;      // OP_COMBINE; OP_EXPO: per-substep norm limit theta
+  double eps;        // OP_EXPO: Taylor truncation target
+  double sigl[kMaxOrder + 1];  // OP_EXPO: per-degree loss of the medium
 };
 
 // Per-grid-size entry points (one translation unit per n). enqueue_op

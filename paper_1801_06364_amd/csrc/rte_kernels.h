@@ -48,6 +48,10 @@ constexpr int kBlock = 256;        // end-of-step kernel
 constexpr int kPBlock = RTE_PBLOCK;  // plane passes
 constexpr int kZBlock = RTE_ZBLOCK;  // z-derivative pass
 constexpr int kCBlock = RTE_CBLOCK;  // coupling pass
+#ifndef RTE_FPPW
+#define RTE_FPPW 1
+#endif
+constexpr int kFwdPlanes = RTE_FPPW;  // planes per forward-plane workgroup
 constexpr int kXcds = 8;
 
 // Physical block id -> logical tile: XCD x (= bid % 8) receives a contiguous
@@ -82,53 +86,76 @@ constexpr size_t plane_lds() {
 template <typename T, int NN>
 __global__ void __launch_bounds__(kPBlock)
 k_fwd_plane(const T* __restrict__ src, typename cplx_of<T>::type* __restrict__ spec,
-            const typename cplx_of<T>::type* __restrict__ twg, const Ctl* __restrict__ ctl) {
+            const typename cplx_of<T>::type* __restrict__ twg, const Ctl* __restrict__ ctl, int nplanes) {
   using V = typename cplx_of<T>::type;
   using G = GridC<NN>;
   constexpr int n = NN, H = G::H, LP = H + 1;   // LDS row pitch (odd: no bank aliasing)
+  constexpr int CNT = n * H;                     // complex values per packed plane
+  constexpr int ITER = (CNT + kPBlock - 1) / kPBlock;
   if (ctl->stop) return;
   extern __shared__ __align__(16) unsigned char smem[];
   V* tw = reinterpret_cast<V*>(smem);
   V* pl = tw + n;
-  const int plane = blockIdx.x;            // b * n + z
   for (int i = threadIdx.x; i < n; i += kPBlock) tw[i] = twg[i];
-  const V* s = reinterpret_cast<const V*>(src + size_t(plane) * n * n);
-  staged_copy<n * H, kPBlock>([&](int i) { return s[i]; },
-                              [&](int i, V x) { pl[(i / H) * LP + (i % H)] = x; });
-  __syncthreads();
-  // x: n packed rows of length H (twiddle table of length n, stride 2)
-  fft_batch<V, H, 1, 2 * H, -1, n, kPBlock>(tw, [&](int f) { return pl + f * LP; });
-  __syncthreads();
-  // real-to-complex split: X_k from Z_k and Z_{H-k}
-  constexpr int half = H / 2;
-  for (int i = threadIdx.x; i < n * (half + 1); i += kPBlock) {
-    const int y = i / (half + 1), k = i - y * (half + 1);
-    V* row = pl + y * LP;
-    if (k == 0) {
-      const V z0 = row[0];
-      row[0] = cmk<V>(z0.x + z0.y, z0.x - z0.y);   // packed (X_0, X_{n/2})
-    } else {
-      const int m = H - k;
-      const V zk = row[k], zm = row[m];
-      const V zmc = cconj(zm), zkc = cconj(zk);
-      // X_k = (Z_k + conj Z_m)/2 - i w_k (Z_k - conj Z_m)/2,  w_k = exp(-2 pi i k / n)
-      const V ek = cscale(cadd(zk, zmc), T(0.5));
-      const V ok = cmul_i<V, -1>(cscale(csub(zk, zmc), T(0.5)));
-      row[k] = cadd(ek, cmul(tw[k], ok));
-      if (m != k) {
-        const V em = cscale(cadd(zm, zkc), T(0.5));
-        const V om = cmul_i<V, -1>(cscale(csub(zm, zkc), T(0.5)));
-        row[m] = cadd(em, cmul(tw[m], om));
+  // kFwdPlanes consecutive planes per workgroup; the next plane's loads are
+  // issued into registers before the current plane's FFTs, so HBM traffic
+  // overlaps the LDS work
+  const int p0 = blockIdx.x * kFwdPlanes;
+  V pre[ITER];
+  auto gload = [&](int plane) {
+    const V* s = reinterpret_cast<const V*>(src + size_t(plane) * n * n);
+#pragma unroll
+    for (int it = 0; it < ITER; ++it) {
+      const int i = int(threadIdx.x) + it * kPBlock;
+      if (CNT % kPBlock == 0 || i < CNT) pre[it] = s[i];
+    }
+  };
+  gload(p0);
+  for (int k = 0; k < kFwdPlanes; ++k) {
+    const int plane = p0 + k;                    // b * n + z
+    if (plane >= nplanes) break;
+#pragma unroll
+    for (int it = 0; it < ITER; ++it) {
+      const int i = int(threadIdx.x) + it * kPBlock;
+      if (CNT % kPBlock == 0 || i < CNT) pl[(i / H) * LP + (i % H)] = pre[it];
+    }
+    __syncthreads();
+    if (k + 1 < kFwdPlanes && plane + 1 < nplanes) gload(plane + 1);
+    // x: n packed rows of length H (twiddle table of length n, stride 2)
+    fft_batch<V, H, 1, 2 * H, -1, n, kPBlock>(tw, [&](int f) { return pl + f * LP; });
+    __syncthreads();
+    // real-to-complex split: X_k from Z_k and Z_{H-k}
+    constexpr int half = H / 2;
+    for (int i = threadIdx.x; i < n * (half + 1); i += kPBlock) {
+      const int y = i / (half + 1), kk = i - y * (half + 1);
+      V* row = pl + y * LP;
+      if (kk == 0) {
+        const V z0 = row[0];
+        row[0] = cmk<V>(z0.x + z0.y, z0.x - z0.y);   // packed (X_0, X_{n/2})
+      } else {
+        const int m = H - kk;
+        const V zk = row[kk], zm = row[m];
+        const V zmc = cconj(zm), zkc = cconj(zk);
+        // X_k = (Z_k + conj Z_m)/2 - i w_k (Z_k - conj Z_m)/2,  w_k = exp(-2 pi i k / n)
+        const V ek = cscale(cadd(zk, zmc), T(0.5));
+        const V ok = cmul_i<V, -1>(cscale(csub(zk, zmc), T(0.5)));
+        row[kk] = cadd(ek, cmul(tw[kk], ok));
+        if (m != kk) {
+          const V em = cscale(cadd(zm, zkc), T(0.5));
+          const V om = cmul_i<V, -1>(cscale(csub(zm, zkc), T(0.5)));
+          row[m] = cadd(em, cmul(tw[m], om));
+        }
       }
     }
+    __syncthreads();
+    // y: H columns of length n, stride LP
+    fft_batch<V, n, LP, n, -1, H, kPBlock>(tw, [&](int f) { return pl + f; });
+    __syncthreads();
+    V* dst = spec + size_t(plane) * n * H;
+    staged_copy<n * H, kPBlock>([&](int i) { return pl[(i / H) * LP + (i % H)]; },
+                                [&](int i, V x) { dst[i] = x; });
+    __syncthreads();
   }
-  __syncthreads();
-  // y: H columns of length n, stride LP
-  fft_batch<V, n, LP, n, -1, H, kPBlock>(tw, [&](int f) { return pl + f; });
-  __syncthreads();
-  V* dst = spec + size_t(plane) * n * H;
-  staged_copy<n * H, kPBlock>([&](int i) { return pl[(i / H) * LP + (i % H)]; },
-                              [&](int i, V x) { dst[i] = x; });
 }
 
 // ------------------------------------------------ pencil passes (D, Y) ---
@@ -141,8 +168,12 @@ k_fwd_plane(const T* __restrict__ src, typename cplx_of<T>::type* __restrict__ s
 //                  (tile = (b, ky, kx-tile));
 //   PENCIL_YFWD / PENCIL_YINV: axis y, forward / inverse FFT in place
 //                  (tile = (b, z, kx-tile); used where a whole plane does
-//                  not fit in LDS).
-enum { PENCIL_ZDERIV = 0, PENCIL_YFWD = 1, PENCIL_YINV = 2 };
+//                  not fit in LDS);
+//   PENCIL_ZFWD / PENCIL_ZINV: axis z, forward / inverse FFT in place (the
+//                  full 3D spectrum of the exact propagation).
+enum { PENCIL_ZDERIV = 0, PENCIL_YFWD = 1, PENCIL_YINV = 2, PENCIL_ZFWD = 3, PENCIL_ZINV = 4 };
+constexpr bool pencil_z(int mode) { return mode == PENCIL_ZDERIV || mode == PENCIL_ZFWD || mode == PENCIL_ZINV; }
+constexpr bool pencil_inverse(int mode) { return mode == PENCIL_YINV || mode == PENCIL_ZINV; }
 
 #ifndef RTE_ZDW
 #define RTE_ZDW 16
@@ -174,7 +205,7 @@ k_pencil(const typename cplx_of<T>::type* src, typename cplx_of<T>::type* dst,  
   using Z = ZdShape<T, NN>;
   constexpr int n = NN, H = NN / 2, TZ = Z::TZ, PITCH = Z::PITCH;
   // element stride along the pencil axis in the [b][z][ky][kx] spectrum
-  constexpr size_t AX = MODE == PENCIL_ZDERIV ? size_t(n) * H : size_t(H);
+  constexpr size_t AX = pencil_z(MODE) ? size_t(n) * H : size_t(H);
   if (ctl->stop) return;
   extern __shared__ __align__(16) unsigned char smem[];
   V* tw = reinterpret_cast<V*>(smem);
@@ -185,14 +216,14 @@ k_pencil(const typename cplx_of<T>::type* src, typename cplx_of<T>::type* dst,  
   const int bw = tile / Z::NTILE;
   const int kx0 = (tile - bw * Z::NTILE) * TZ;
   const int b = bw / n, w = bw - b * n;
-  const size_t base = MODE == PENCIL_ZDERIV ? (size_t(b) * n * n + w) * H + kx0
+  const size_t base = pencil_z(MODE) ? (size_t(b) * n * n + w) * H + kx0
                                             : (size_t(b) * n + w) * size_t(n) * H + kx0;
   for (int i = threadIdx.x; i < n; i += kZBlock) tw[i] = twg[i];
   staged_copy<n * TZ, kZBlock>(
       [&](int i) { return src[base + size_t(i / TZ) * AX + (i % TZ)]; },
       [&](int i, V x) { col[(i % TZ) * PITCH + i / TZ] = x; });
   __syncthreads();
-  if constexpr (MODE == PENCIL_YINV) {
+  if constexpr (pencil_inverse(MODE)) {
     fft_batch<V, n, 1, n, +1, TZ, kZBlock>(tw, [&](int f) { return col + f * PITCH; });
   } else {
     fft_batch<V, n, 1, n, -1, TZ, kZBlock>(tw, [&](int f) { return col + f * PITCH; });
@@ -389,7 +420,7 @@ __device__ __forceinline__ void c2r_merge(V* pl, const V* tw) {
 }
 
 // Epilogue modes of the inverse pass.
-enum { EPI_MID = 0, EPI_FIRST = 1, EPI_LAST = 2, EPI_ADJ = 3, EPI_EULER = 4 };
+enum { EPI_MID = 0, EPI_FIRST = 1, EPI_LAST = 2, EPI_ADJ = 3, EPI_EULER = 4, EPI_APPLY = 5, EPI_SET = 6 };
 
 // Pointwise epilogue of RB rows starting at row y0 of plane (b, z), on
 // (x_{2j}, x_{2j+1}) pairs:
@@ -398,7 +429,11 @@ enum { EPI_MID = 0, EPI_FIRST = 1, EPI_LAST = 2, EPI_ADJ = 3, EPI_EULER = 4 };
 //     fluence moment and the partial sums of (o - u)^2 and o^2);
 //   EPI_ADJ         o = w - h Sigma_l v  -> dst, and u += o (u is the
 //     adjoint accumulator; no source term in the transposed operator);
-//   EPI_EULER       first and last stage at once (v = u, o -> u, bookkeeping).
+//   EPI_EULER       first and last stage at once (v = u, o -> u, bookkeeping);
+//   EPI_APPLY       o = -w + Sigma_l v -> dst with w = -S v (h = 1): the
+//     steady-state operator A v = (S + Sigma) v, for which the steady state
+//     solves A u = q;
+//   EPI_SET         o = w -> dst (the transformed field itself).
 template <typename V, typename T, int NN, int RB, int LP, int BLOCK, int MODE>
 __device__ __forceinline__ void epilogue(const V* pl, int y0, int b, int z, const T* vin, T* u,
                                          T* dst, const T* __restrict__ sig, const T* __restrict__ q,
@@ -414,7 +449,11 @@ __device__ __forceinline__ void epilogue(const V* pl, int y0, int b, int z, cons
     const int y = i / H, j = i - y * H;
     const int e = y * n + 2 * j;
     const V w = pl[y * LP + j];
-    const V uu = *reinterpret_cast<const V*>(u + poff + e);
+    if constexpr (MODE == EPI_SET) {
+      *reinterpret_cast<V*>(dst + poff + e) = w;
+      continue;
+    }
+    const V uu = MODE == EPI_APPLY ? cmk<V>(T(0), T(0)) : *reinterpret_cast<const V*>(u + poff + e);
     const V vv = (MODE == EPI_FIRST || MODE == EPI_EULER) ? uu : *reinterpret_cast<const V*>(vin + poff + e);
     const V ss = *reinterpret_cast<const V*>(sg + e);
     T src0 = -ss.x * vv.x, src1 = -ss.y * vv.y;
@@ -422,6 +461,10 @@ __device__ __forceinline__ void epilogue(const V* pl, int y0, int b, int z, cons
       const V qq = *reinterpret_cast<const V*>(q + poff + e);
       src0 += qq.x;
       src1 += qq.y;
+    }
+    if constexpr (MODE == EPI_APPLY) {
+      *reinterpret_cast<V*>(dst + poff + e) = cmk<V>(-w.x + ss.x * vv.x, -w.y + ss.y * vv.y);
+      continue;
     }
     if constexpr (MODE == EPI_ADJ) {
       const V o = cmk<V>(w.x + h * src0, w.y + h * src1);
@@ -621,6 +664,234 @@ k_adj_inject(T* __restrict__ lam, const long long* __restrict__ det, const doubl
   for (int p = threadIdx.x; p < ndet; p += kBlock) lam[det[p]] += T(djdr[p]);
 }
 
+// ------------------------------------------------- Krylov vector kernels ---
+
+// Weighted inner products <x, y>_W = sum_a (2l+1) sum_r x_a(r) y_a(r) (the
+// Euclidean product of orthonormal-basis coefficients, in which the
+// streaming operator is skew and the steady-state operator positive real).
+// k_wdots: per block partial sums of <basis_i, w>_W for i < count (fixed
+// element partition and tree: deterministic); k_cols_sum adds the block
+// partials in a fixed order.
+constexpr int kDotBlocks = 1024;
+constexpr int kMaxBasis = 32;
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_wdots(const T* __restrict__ basis, long long stride, int count, const T* __restrict__ w, int M,
+        long long n3, double* __restrict__ partial) {
+  __shared__ double red[kBlock];
+  double acc[kMaxBasis];
+#pragma unroll
+  for (int i = 0; i < kMaxBasis; ++i) acc[i] = 0.0;
+  const long long step = (long long)gridDim.x * kBlock;
+  for (int a = 0; a < M; ++a) {
+    const double wt = double(2 * isqrt_c(a) + 1);
+    const long long base = (long long)a * n3;
+    for (long long r = (long long)blockIdx.x * kBlock + threadIdx.x; r < n3; r += step) {
+      const double we = wt * double(w[base + r]);
+#pragma unroll
+      for (int i = 0; i < kMaxBasis; ++i)
+        if (i < count) acc[i] += we * double(basis[i * stride + base + r]);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kMaxBasis; ++i) {
+    if (i < count) {   // count is uniform over the grid
+      red[threadIdx.x] = acc[i];
+      __syncthreads();
+      for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if (int(threadIdx.x) < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) partial[(long long)blockIdx.x * kMaxBasis + i] = red[0];
+      __syncthreads();
+    }
+  }
+}
+
+template <typename T>   // instantiated per working precision (one copy per translation unit)
+__global__ void __launch_bounds__(kBlock)
+k_cols_sum(const double* __restrict__ partial, int nblocks, int count, double* __restrict__ out) {
+  const int i = threadIdx.x;
+  if (i >= count) return;
+  double s = 0.0;
+  for (int b = 0; b < nblocks; ++b) s += partial[(long long)b * kMaxBasis + i];
+  out[i] = s;
+}
+
+// w <- sgn * w + sum_i coef[i] * basis_i  (coef on the device)
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_combine(T* __restrict__ w, double sgn, const T* __restrict__ basis, long long stride, int count,
+          const double* __restrict__ coef, double cscale, long long len) {
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < len; e += (long long)gridDim.x * kBlock) {
+    double x = sgn * double(w[e]);
+    for (int i = 0; i < count; ++i) x += cscale * coef[i] * double(basis[i * stride + e]);
+    w[e] = T(x);
+  }
+}
+
+// dst = src / s[0]
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_scale_by(T* __restrict__ dst, const T* __restrict__ src, const double* __restrict__ s, long long len) {
+  const double inv = 1.0 / s[0];
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < len; e += (long long)gridDim.x * kBlock)
+    dst[e] = T(double(src[e]) * inv);
+}
+
+// dst = b - dst (b may be null: zero right-hand side)
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_rhs_minus(T* __restrict__ dst, const T* __restrict__ b, long long len) {
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < len; e += (long long)gridDim.x * kBlock)
+    dst[e] = (b ? b[e] : T(0)) - dst[e];
+}
+
+// ------------------------------------ E: exact propagation per mode ---
+
+// In a homogeneous medium without boundary layer every Fourier mode k of
+// the moment vector a obeys da/dt = M(k) a + c q(k) with
+//   M(k) = -c (i k.B + Sigma),
+// Sigma the per-degree loss. Over a time T the mode advances exactly by
+//   a <- exp(T M) a + int_0^T exp(s M) ds c q,
+// evaluated per spectral point, all moments in registers, as s substeps of
+// length h = T / s of the truncated Taylor series of the augmented
+// generator [[h M, h c q], [0, 0]]:
+//   t_1 = h (M a + c q),  t_j = h M t_{j-1} / j,  a <- a + sum_{j<=J} t_j.
+// With nu = c T (|k| + max Sigma) >= ||T M|| (k.B has spectral norm <= |k|
+// in the (2l+1)-weighted norm, in which Sigma is diagonal), the point takes
+// s = ceil(nu / theta) substeps and the fewest J terms whose remainder
+// bound (nu/s)^(J+1) / (J+1)! exp(nu/s) is below eps; theta is chosen on
+// the host so that J never exceeds kTaylorMax.
+template <typename T> struct TaylorMax;
+template <> struct TaylorMax<float> { static constexpr int value = kTaylorMaxF32; };
+template <> struct TaylorMax<double> { static constexpr int value = kTaylorMaxF64; };
+
+template <typename T> struct ExpoParams {
+  T sig[kMaxOrder + 1];   // per-degree loss Sigma_l
+  double ct;              // c T
+  double sigmax;          // max_l Sigma_l
+  double theta;           // largest per-substep norm bound
+  double eps;             // truncation target
+  T inv_n3;               // 1 / n^3 (unnormalised transforms)
+};
+
+// (k.B t)_A accumulated over the compile-time slots of row A: equal-order
+// slots carry Bz only, the others Bx and By only.
+template <typename V, typename T, int N, int A, int S>
+struct ExpoRowAcc {
+  static __device__ __forceinline__ void run(const V* t, const T* __restrict__ c, T kx, T ky, T kz, T& re,
+                                             T& im) {
+    constexpr int l = isqrt_c(A);
+    constexpr int m = A - l * l - l;
+    constexpr SlotList sl = slots_of(N, l, m);
+    if constexpr (S < sl.count) {
+      constexpr int b = sl.b[S];
+      constexpr int lb = isqrt_c(b);
+      constexpr int mb = b - lb * lb - lb;
+      const T* e = c + (A * kMaxSlots + S) * 3;
+      T cf;
+      if constexpr (mb == m) cf = e[2] * kz;
+      else cf = e[0] * kx + e[1] * ky;
+      re += cf * t[b].x;
+      im += cf * t[b].y;
+      ExpoRowAcc<V, T, N, A, S + 1>::run(t, c, kx, ky, kz, re, im);
+    }
+  }
+};
+
+// nt = h (M t / c + q) (q only for the first term: SRC), acc += nt, all
+// moments of one point; M t / c = -i (k.B) t - Sigma t.
+template <typename V, typename T, int N, int A, bool SRC>
+struct ExpoApply {
+  static __device__ __forceinline__ void run(const V* t, V* nt, V* acc, const T* __restrict__ c, T kx, T ky,
+                                             T kz, const ExpoParams<T>& p, T h, const V* __restrict__ qp,
+                                             size_t ms) {
+    if constexpr (A < (N + 1) * (N + 1)) {
+      constexpr int l = isqrt_c(A);
+      T re = 0, im = 0;
+      ExpoRowAcc<V, T, N, A, 0>::run(t, c, kx, ky, kz, re, im);
+      T ox = im - p.sig[l] * t[A].x;
+      T oy = -re - p.sig[l] * t[A].y;
+      if constexpr (SRC) {
+        const V qq = qp[A * ms];
+        ox += p.inv_n3 * qq.x;
+        oy += p.inv_n3 * qq.y;
+      }
+      nt[A] = cmk<V>(h * ox, h * oy);
+      acc[A] = cmk<V>(acc[A].x + nt[A].x, acc[A].y + nt[A].y);
+      ExpoApply<V, T, N, A + 1, SRC>::run(t, nt, acc, c, kx, ky, kz, p, h, qp, ms);
+    }
+  }
+};
+
+constexpr int kEBlock = 256;
+
+// One thread per point of the full spectrum [b][kz][ky][kx] (kx < n/2; the
+// kx = 0 slot carries the kx = n/2 column too, which has the same zero
+// wavenumber, and the propagation is complex-linear, so both advance
+// together). qs (the source spectrum, same layout) may be null.
+template <typename T, int NN, int N>
+__global__ void __launch_bounds__(kEBlock)
+k_expo(typename cplx_of<T>::type* __restrict__ spec, const typename cplx_of<T>::type* __restrict__ qs,
+       const T* __restrict__ kv, const T* __restrict__ coef, ExpoParams<T> p) {
+  using V = typename cplx_of<T>::type;
+  constexpr int n = NN, H = NN / 2;
+  constexpr int M = (N + 1) * (N + 1);
+  constexpr size_t MS = size_t(n) * n * H;
+  constexpr int JMAX = TaylorMax<T>::value;
+  const int pt = blockIdx.x * kEBlock + threadIdx.x;   // (kz * n + ky) * H + kx
+  if (pt >= n * n * H) return;
+  const int kxi = pt % H;
+  const int kyi = (pt / H) % n;
+  const int kzi = pt / (n * H);
+  const T kx = kv[kxi], ky = kv[kyi], kz = kv[kzi];
+  const double kk = std::sqrt(double(kx) * kx + double(ky) * ky + double(kz) * kz);
+  const double nu = p.ct * (kk + p.sigmax);
+  const int s = nu > p.theta ? int(std::ceil(nu / p.theta)) : 1;
+  const double nus = nu / s;
+  int J = 1;
+  double bound = 0.5 * nus * nus * std::exp(nus);
+  while (bound > p.eps && J < JMAX) {
+    ++J;
+    bound *= nus / (J + 1);
+  }
+  const T h = T(p.ct / s);
+  V a[M], t[M], nt[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    const V x = spec[i * MS + pt];
+    a[i] = cmk<V>(p.inv_n3 * x.x, p.inv_n3 * x.y);
+  }
+  const V* qp = qs ? qs + pt : nullptr;
+  // The operator's entries (k.B)[a][b] are loop invariant; left to itself
+  // the compiler keeps all of them in registers across the series (several
+  // hundred per point at N = 7) and spills. Making the wavenumbers and the
+  // table address opaque per term keeps them recomputed from the scalar
+  // cache instead (a few ALU operations per entry).
+  auto term = [&](const V* src, V* dst, T hj, bool first) __attribute__((always_inline)) {
+    T qx = kx, qy = ky, qz = kz;
+    const T* c = coef;
+    asm volatile("" : "+v"(qx), "+v"(qy), "+v"(qz));
+    if (first && qp) ExpoApply<V, T, N, 0, true>::run(src, dst, a, c, qx, qy, qz, p, hj, qp, MS);
+    else ExpoApply<V, T, N, 0, false>::run(src, dst, a, c, qx, qy, qz, p, hj, nullptr, MS);
+  };
+  for (int sub = 0; sub < s; ++sub) {
+#pragma unroll
+    for (int i = 0; i < M; ++i) t[i] = a[i];
+    term(t, nt, h, true);
+    // the latest term is in nt; alternate buffers to avoid copies
+    for (int j = 2; j <= J; j += 2) {
+      term(nt, t, h / T(j), false);
+      if (j + 1 > J) break;
+      term(t, nt, h / T(j + 1), false);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < M; ++i) spec[i * MS + pt] = a[i];
+}
+
 // ---------------------------------------------------------------- launch ---
 
 // Grids up to 128 points per axis keep a whole plane in LDS (plane passes);
@@ -640,6 +911,8 @@ hipError_t prepare_t(const StepArgs& a) {
     set(reinterpret_cast<const void*>(&k_rows_inv<T, NN, EPI_LAST>), rows_lds<T, NN>());
     set(reinterpret_cast<const void*>(&k_rows_inv<T, NN, EPI_ADJ>), rows_lds<T, NN>());
     set(reinterpret_cast<const void*>(&k_rows_inv<T, NN, EPI_EULER>), rows_lds<T, NN>());
+    set(reinterpret_cast<const void*>(&k_rows_inv<T, NN, EPI_APPLY>), rows_lds<T, NN>());
+    set(reinterpret_cast<const void*>(&k_rows_inv<T, NN, EPI_SET>), rows_lds<T, NN>());
     set(reinterpret_cast<const void*>(&k_pencil<T, NN, PENCIL_YFWD>), zd_lds<T, NN>());
     set(reinterpret_cast<const void*>(&k_pencil<T, NN, PENCIL_YINV>), zd_lds<T, NN>());
   } else {
@@ -649,8 +922,12 @@ hipError_t prepare_t(const StepArgs& a) {
     set(reinterpret_cast<const void*>(&k_inv_plane<T, NN, EPI_LAST>), plane_lds<T, NN>());
     set(reinterpret_cast<const void*>(&k_inv_plane<T, NN, EPI_ADJ>), plane_lds<T, NN>());
     set(reinterpret_cast<const void*>(&k_inv_plane<T, NN, EPI_EULER>), plane_lds<T, NN>());
+    set(reinterpret_cast<const void*>(&k_inv_plane<T, NN, EPI_APPLY>), plane_lds<T, NN>());
+    set(reinterpret_cast<const void*>(&k_inv_plane<T, NN, EPI_SET>), plane_lds<T, NN>());
   }
   set(reinterpret_cast<const void*>(&k_pencil<T, NN, PENCIL_ZDERIV>), zd_lds<T, NN>());
+  set(reinterpret_cast<const void*>(&k_pencil<T, NN, PENCIL_ZFWD>), zd_lds<T, NN>());
+  set(reinterpret_cast<const void*>(&k_pencil<T, NN, PENCIL_ZINV>), zd_lds<T, NN>());
   return e;
 }
 
@@ -663,7 +940,7 @@ template <int NN> constexpr int partial_count() {
 // One stage: out = MODE-epilogue of (u, src) with the streaming term
 // sgn * a h c (-B.grad src) (sgn = -1 gives the transposed streaming).
 template <typename T, int NN, int N, int MODE>
-hipError_t enqueue_stage(const StepArgs& a, ProfRec* pr, double hs, double sgn, const T* src, T* u, T* out) {
+void enqueue_stage(const StepArgs& a, ProfRec* pr, double hs, double sgn, const T* src, T* u, T* out) {
   using V = typename cplx_of<T>::type;
   using Z = ZdShape<T, NN>;
   constexpr int M = (N + 1) * (N + 1);
@@ -695,7 +972,8 @@ hipError_t enqueue_stage(const StepArgs& a, ProfRec* pr, double hs, double sgn, 
     hipLaunchKernelGGL((k_pencil<T, NN, PENCIL_YFWD>), dim3(pencils), zblk, lz, st, spec, spec, tw, kv, cctl);
     rec(PROF_Y_FWD);
   } else {
-    hipLaunchKernelGGL((k_fwd_plane<T, NN>), dim3(planes), pblk, lp, st, src, spec, tw, cctl);
+    hipLaunchKernelGGL((k_fwd_plane<T, NN>), dim3((planes + kFwdPlanes - 1) / kFwdPlanes), pblk, lp, st, src,
+                       spec, tw, cctl, planes);
     rec(PROF_FWD_PLANE);
   }
   hipLaunchKernelGGL((k_pencil<T, NN, PENCIL_ZDERIV>), dim3(pencils), zblk, lz, st, spec, dspec, tw, kv, cctl);
@@ -714,7 +992,67 @@ hipError_t enqueue_stage(const StepArgs& a, ProfRec* pr, double hs, double sgn, 
                        a.phi_int, a.partial, tw, M, T(hs), a.dt, cctl);
     rec(PROF_INV_PLANE);
   }
-  return hipSuccess;
+}
+
+// Exact propagation over time op.coef: 3D forward transforms of the state
+// (and of the source, into the derivative buffer), the per-point
+// exponential, inverse transforms written over the state.
+template <typename T, int NN, int N>
+hipError_t enqueue_expo(const StepArgs& a, const OpArgs& op) {
+  using V = typename cplx_of<T>::type;
+  using Z = ZdShape<T, NN>;
+  constexpr int M = (N + 1) * (N + 1);
+  constexpr int n = NN, H = NN / 2;
+  hipStream_t st = reinterpret_cast<hipStream_t>(a.stream);
+  V* spec = static_cast<V*>(a.spec);
+  V* dspec = static_cast<V*>(a.dspec);
+  const V* tw = static_cast<const V*>(a.tw);
+  const T* kv = static_cast<const T*>(a.kv);
+  const T* sig = static_cast<const T*>(a.sig);
+  const T* q = static_cast<const T*>(a.q);
+  T* u = static_cast<T*>(a.u);
+  const Ctl* cctl = static_cast<const Ctl*>(a.ctl);
+  const dim3 pblk(kPBlock), zblk(kZBlock);
+  const int planes = M * n;
+  const int pencils = M * n * Z::NTILE;
+  const int rblocks = M * n * (n / RowShape<NN>::RB);
+  const size_t lp = plane_lds<T, NN>(), lz = zd_lds<T, NN>(), lr = rows_lds<T, NN>();
+  auto forward = [&](const T* src, V* dst) {
+    if constexpr (split_planes<NN>()) {
+      hipLaunchKernelGGL((k_rows_fwd<T, NN>), dim3(rblocks), zblk, lr, st, src, dst, tw, cctl);
+      hipLaunchKernelGGL((k_pencil<T, NN, PENCIL_YFWD>), dim3(pencils), zblk, lz, st, dst, dst, tw, kv, cctl);
+    } else {
+      hipLaunchKernelGGL((k_fwd_plane<T, NN>), dim3((planes + kFwdPlanes - 1) / kFwdPlanes), pblk, lp, st, src,
+                         dst, tw, cctl, planes);
+    }
+    hipLaunchKernelGGL((k_pencil<T, NN, PENCIL_ZFWD>), dim3(pencils), zblk, lz, st, dst, dst, tw, kv, cctl);
+  };
+  if (q) forward(q, dspec);
+  forward(u, spec);
+  ExpoParams<T> p{};
+  double smax = 0.0;
+  for (int l = 0; l <= kMaxOrder; ++l) {
+    p.sig[l] = T(l <= N ? op.sigl[l] : 0.0);
+    if (l <= N) smax = op.sigl[l] > smax ? op.sigl[l] : smax;
+  }
+  p.ct = op.coef * a.c;
+  p.sigmax = smax;
+  p.theta = op.scale;
+  p.eps = op.eps;
+  p.inv_n3 = T(1.0 / (double(n) * n * n));
+  const int eblocks = (n * n * H + kEBlock - 1) / kEBlock;
+  hipLaunchKernelGGL((k_expo<T, NN, N>), dim3(eblocks), dim3(kEBlock), 0, st, spec, q ? dspec : nullptr, kv,
+                     static_cast<const T*>(a.coef), p);
+  hipLaunchKernelGGL((k_pencil<T, NN, PENCIL_ZINV>), dim3(pencils), zblk, lz, st, spec, spec, tw, kv, cctl);
+  if constexpr (split_planes<NN>()) {
+    hipLaunchKernelGGL((k_pencil<T, NN, PENCIL_YINV>), dim3(pencils), zblk, lz, st, spec, spec, tw, kv, cctl);
+    hipLaunchKernelGGL((k_rows_inv<T, NN, EPI_SET>), dim3(rblocks), zblk, lr, st, spec, u, u, u, sig,
+                       static_cast<const T*>(nullptr), a.qflag, a.phi_int, a.partial, tw, M, T(0), 0.0, cctl);
+  } else {
+    hipLaunchKernelGGL((k_inv_plane<T, NN, EPI_SET>), dim3(planes), pblk, lp, st, spec, u, u, u, sig,
+                       static_cast<const T*>(nullptr), a.qflag, a.phi_int, a.partial, tw, M, T(0), 0.0, cctl);
+  }
+  return hipGetLastError();
 }
 
 constexpr double kRkAlpha[4] = {0.25, 1.0 / 3.0, 0.5, 1.0};
@@ -724,6 +1062,7 @@ hipError_t enqueue_t(const StepArgs& a, const OpArgs& op, ProfRec* pr) {
   hipStream_t st = reinterpret_cast<hipStream_t>(a.stream);
   const double hc = a.dt * a.c;
   const long long nvox = (long long)NN * NN * NN;
+  constexpr int M = (N + 1) * (N + 1);
   switch (op.kind) {
     case OP_STEP: {
       T* u = static_cast<T*>(a.u);
@@ -773,6 +1112,39 @@ hipError_t enqueue_t(const StepArgs& a, const OpArgs& op, ProfRec* pr) {
                          -a.c * op.coef * a.dt);
       break;
     }
+    case OP_APPLY: {
+      // y = (S + Sigma) x
+      enqueue_stage<T, NN, N, EPI_APPLY>(a, nullptr, 1.0, 1.0, static_cast<const T*>(op.x),
+                                         static_cast<T*>(op.y), static_cast<T*>(op.y));
+      break;
+    }
+    case OP_WDOTS: {
+      const long long len = (long long)M * nvox;
+      hipLaunchKernelGGL((k_wdots<T>), dim3(kDotBlocks), dim3(kBlock), 0, st, static_cast<const T*>(op.x),
+                         len, op.count, static_cast<const T*>(op.y), M, nvox, op.gmua);
+      hipLaunchKernelGGL((k_cols_sum<T>), dim3(1), dim3(kBlock), 0, st, op.gmua, kDotBlocks, op.count, op.gmus);
+      break;
+    }
+    case OP_COMBINE: {
+      const long long len = (long long)M * nvox;
+      hipLaunchKernelGGL((k_combine<T>), dim3(kDotBlocks), dim3(kBlock), 0, st, static_cast<T*>(op.y),
+                         op.coef, static_cast<const T*>(op.x), len, op.count, op.djdr, op.scale, len);
+      break;
+    }
+    case OP_SCALE: {
+      const long long len = (long long)M * nvox;
+      hipLaunchKernelGGL((k_scale_by<T>), dim3(kDotBlocks), dim3(kBlock), 0, st, static_cast<T*>(op.y),
+                         static_cast<const T*>(op.x), op.djdr, len);
+      break;
+    }
+    case OP_RHS_MINUS: {
+      const long long len = (long long)M * nvox;
+      hipLaunchKernelGGL((k_rhs_minus<T>), dim3(kDotBlocks), dim3(kBlock), 0, st, static_cast<T*>(op.y),
+                         static_cast<const T*>(op.x), len);
+      break;
+    }
+    case OP_EXPO:
+      return enqueue_expo<T, NN, N>(a, op);
     case OP_ADJ_INJECT: {
       hipLaunchKernelGGL((k_adj_inject<T>), dim3(1), dim3(kBlock), 0, st, static_cast<T*>(op.u), a.det,
                          op.djdr, a.ndet);

@@ -130,6 +130,8 @@ struct rte_handle {
   hipGraphExec_t exec;
   bool graph_ready;
   bool use_graph;
+  bool homogeneous;                 // constant maps, no boundary layer
+  double sigl[rte::kMaxOrder + 1];  // per-degree loss (homogeneous media)
   template <typename P> P* at(size_t off) const { return reinterpret_cast<P*>(ws + off); }
 };
 
@@ -372,6 +374,10 @@ int rte_create(const rte_config* cfg, const rte_medium* med, void* dev_ws, size_
   h->ws = reinterpret_cast<unsigned char*>(dev_ws);
   h->lay = L;
   h->graph_ready = false;
+  h->homogeneous = cfg->pml_width == 0;
+  for (size_t i = 1; i < V && h->homogeneous; ++i)
+    h->homogeneous = med->mu_a[i] == med->mu_a[0] && med->mu_s[i] == med->mu_s[0] && med->g[i] == med->g[0];
+  for (int l = 0; l <= kMaxOrder; ++l) h->sigl[l] = l <= N ? sig[size_t(l) * V] : 0.0;
   const char* ng = std::getenv("RTE_NO_GRAPH");
   h->use_graph = (h->stream != nullptr) && !(ng && ng[0] == '1');
   StepArgs& A = h->args;
@@ -678,6 +684,210 @@ int rte_adjoint(rte_handle* h, int64_t steps, int64_t every, void* adj_ws, size_
   ok(hipMemcpyAsync(grad_mu_a, w + A.gmua, V * 8, hipMemcpyDeviceToHost, st));
   ok(hipMemcpyAsync(grad_mu_s, w + A.gmus, V * 8, hipMemcpyDeviceToHost, st));
   ok(hipStreamSynchronize(st));
+  return to_code(e);
+}
+
+size_t rte_krylov_workspace_bytes(const rte_config* cfg, int32_t restart) {
+  if (!rte::config_ok(cfg) || restart < 1 || restart + 1 > rte::kMaxBasisVectors) return 0;
+  const size_t n = cfg->n, M = size_t(cfg->order_N + 1) * (cfg->order_N + 1);
+  const size_t F = M * n * n * n * (cfg->precision == RTE_FP64 ? 8 : 4);
+  size_t o = rte::up(size_t(restart + 1) * F);            // Krylov basis
+  o = rte::up(o + size_t(rte::kDotPartials) * 8);         // dot partial sums
+  o = rte::up(o + 2 * size_t(rte::kMaxBasisVectors) * 8); // device coefficients
+  return o;
+}
+
+int rte_steady_gmres(rte_handle* h, int32_t restart, int64_t max_iters, double tol, void* kws, size_t kbytes,
+                     int64_t* iters, double* rel_residual) {
+  using namespace rte;
+  if (!h || restart < 1 || restart + 1 > kMaxBasisVectors || max_iters < 1 || !(tol > 0)) return RTE_EINVAL;
+  const size_t need = rte_krylov_workspace_bytes(&h->cfg, restart);
+  if (!kws || (reinterpret_cast<uintptr_t>(kws) % kAlign) != 0 || kbytes < need) return RTE_ENOMEM;
+  {
+    // kernels skip their work once a run has stopped: clear the stop flag
+    // (and the run bookkeeping, which a steady solve does not produce)
+    Ctl c;
+    int rc = read_ctl(h, &c);
+    if (rc == RTE_OK) rc = reset_run_state(h, c.growth_limit);
+    if (rc) return rc;
+  }
+  const int m = restart;
+  const size_t F = state_bytes(h);
+  unsigned char* w = static_cast<unsigned char*>(kws);
+  unsigned char* basis = w;
+  double* partial = reinterpret_cast<double*>(w + up(size_t(m + 1) * F));
+  double* dcoef = reinterpret_cast<double*>(w + up(up(size_t(m + 1) * F) + size_t(kDotPartials) * 8));
+  double* dout = dcoef + kMaxBasisVectors;
+  hipStream_t st = h->stream;
+  hipError_t e = hipSuccess;
+  auto op = [&](OpArgs o) {
+    if (e == hipSuccess) e = hipError_t(launch_enqueue_op(h->n, h->args, o, nullptr));
+  };
+  auto vec = [&](int i) { return static_cast<void*>(basis + size_t(i) * F); };
+  auto apply = [&](const void* x, void* y) {
+    OpArgs o{};
+    o.kind = OP_APPLY;
+    o.x = x;
+    o.y = y;
+    op(o);
+  };
+  // out[0..count) = <basis_0..count-1, y>_W, copied to host vals
+  auto wdots = [&](const void* base, int count, const void* y, double* vals) {
+    OpArgs o{};
+    o.kind = OP_WDOTS;
+    o.x = base;
+    o.y = const_cast<void*>(y);
+    o.count = count;
+    o.gmua = partial;
+    o.gmus = dout;
+    op(o);
+    if (e == hipSuccess) e = hipMemcpyAsync(vals, dout, size_t(count) * 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+  };
+  // y = sgn * y + scale * sum_i c[i] basis_i, with c uploaded first
+  auto combine = [&](void* y, double sgn, int count, const double* c, double scale) {
+    if (e == hipSuccess) e = hipMemcpyAsync(dcoef, c, size_t(count) * 8, hipMemcpyHostToDevice, st);
+    OpArgs o{};
+    o.kind = OP_COMBINE;
+    o.x = basis;
+    o.y = y;
+    o.coef = sgn;
+    o.count = count;
+    o.djdr = dcoef;
+    o.scale = scale;
+    op(o);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);   // dcoef is reused
+  };
+  auto scale_into = [&](void* y, const void* x, double s) {
+    if (e == hipSuccess) e = hipMemcpyAsync(dcoef, &s, 8, hipMemcpyHostToDevice, st);
+    OpArgs o{};
+    o.kind = OP_SCALE;
+    o.x = x;
+    o.y = y;
+    o.djdr = dcoef;
+    op(o);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+  };
+  auto residual_into = [&](void* r) {   // r = q - A u
+    apply(h->ws + h->lay.u, r);
+    OpArgs o{};
+    o.kind = OP_RHS_MINUS;
+    o.x = h->has_q ? h->ws + h->lay.q : nullptr;
+    o.y = r;
+    op(o);
+  };
+  double bnorm = 0.0;
+  if (h->has_q) {
+    wdots(h->ws + h->lay.q, 1, h->ws + h->lay.q, &bnorm);
+    bnorm = std::sqrt(bnorm);
+  }
+  int64_t it = 0;
+  double rel = 1.0;
+  std::vector<double> H(size_t(m + 1) * m), cs(m), sn(m), g(m + 1), hv(m + 1), h2(m + 1), y(m);
+  while (e == hipSuccess) {
+    residual_into(vec(0));
+    double beta = 0.0;
+    wdots(vec(0), 1, vec(0), &beta);
+    beta = std::sqrt(beta);
+    const double ref = bnorm > 0 ? bnorm : 1.0;
+    rel = beta / ref;
+    if (e != hipSuccess || rel <= tol || it >= max_iters || beta == 0.0) break;
+    scale_into(vec(0), vec(0), beta);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int j = 0;
+    for (; j < m && it < max_iters && e == hipSuccess; ++j, ++it) {
+      apply(vec(j), vec(j + 1));
+      // classical Gram-Schmidt, applied twice, against v_0..v_j
+      wdots(basis, j + 1, vec(j + 1), hv.data());
+      combine(vec(j + 1), 1.0, j + 1, hv.data(), -1.0);
+      wdots(basis, j + 1, vec(j + 1), h2.data());
+      combine(vec(j + 1), 1.0, j + 1, h2.data(), -1.0);
+      for (int i = 0; i <= j; ++i) hv[i] += h2[i];
+      double hn = 0.0;
+      wdots(vec(j + 1), 1, vec(j + 1), &hn);
+      hn = std::sqrt(hn);
+      hv[j + 1] = hn;
+      if (hn > 0) scale_into(vec(j + 1), vec(j + 1), hn);
+      // Givens rotations on the new Hessenberg column
+      for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * hv[i] + sn[i] * hv[i + 1];
+        hv[i + 1] = -sn[i] * hv[i] + cs[i] * hv[i + 1];
+        hv[i] = t;
+      }
+      const double r = std::hypot(hv[j], hv[j + 1]);
+      cs[j] = r > 0 ? hv[j] / r : 1.0;
+      sn[j] = r > 0 ? hv[j + 1] / r : 0.0;
+      hv[j] = r;
+      hv[j + 1] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      for (int i = 0; i <= j; ++i) H[size_t(i) * m + j] = hv[i];
+      if (std::fabs(g[j + 1]) / ref <= tol) {
+        ++j;
+        ++it;
+        break;
+      }
+    }
+    // solve the j x j triangular system and update u += sum y_i v_i
+    for (int i = j - 1; i >= 0; --i) {
+      double t = g[i];
+      for (int k = i + 1; k < j; ++k) t -= H[size_t(i) * m + k] * y[k];
+      y[i] = t / H[size_t(i) * m + i];
+    }
+    if (j > 0) combine(h->ws + h->lay.u, 1.0, j, y.data(), 1.0);
+  }
+  if (iters) *iters = it;
+  if (rel_residual) *rel_residual = rel;
+  if (e != hipSuccess) return RTE_EDEVICE;
+  return std::isfinite(rel) ? RTE_OK : RTE_EUNSTABLE;
+}
+
+namespace {
+// Largest per-substep norm theta for which the Taylor remainder bound
+// theta^(m+1) / (m+1)! * exp(theta) stays below eps (bisection on its log).
+double taylor_theta(int m, double eps) {
+  double lo = 0.0, hi = 64.0;
+  for (int it = 0; it < 200; ++it) {
+    const double t = 0.5 * (lo + hi);
+    const double lb = (m + 1) * std::log(t) - std::lgamma(double(m + 2)) + t;
+    if (lb <= std::log(eps)) lo = t;
+    else hi = t;
+  }
+  return lo;
+}
+}  // namespace
+
+int rte_expo_advance(rte_handle* h, double t_ps) {
+  using namespace rte;
+  if (!h || !std::isfinite(t_ps) || t_ps < 0) return RTE_EINVAL;
+  if (!h->homogeneous) return RTE_EINVAL;
+  if (t_ps == 0) return RTE_OK;
+  const bool f64 = h->prec == RTE_FP64;
+  const double eps = f64 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24);
+  const double theta = taylor_theta(f64 ? kTaylorMaxF64 : kTaylorMaxF32, eps);
+  double smax = 0.0;
+  for (int l = 0; l <= h->N; ++l) smax = std::max(smax, h->sigl[l]);
+  const double kmax = std::sqrt(3.0) * M_PI / h->cfg.dx_mm;
+  const double nu = h->cfg.c_mm_ps * t_ps * (kmax + smax);
+  if (nu / theta > 1e6) return RTE_EINVAL;   // split into shorter advances
+  Ctl c;
+  int rc = read_ctl(h, &c);
+  if (rc) return rc;
+  if (c.stop == 2) return RTE_EUNSTABLE;
+  if (c.stop) {
+    c.stop = 0;
+    rc = write_ctl(h, &c);
+    if (rc) return rc;
+  }
+  OpArgs o{};
+  o.kind = OP_EXPO;
+  o.coef = t_ps;
+  o.scale = theta;
+  o.eps = eps;
+  for (int l = 0; l <= kMaxOrder; ++l) o.sigl[l] = h->sigl[l];
+  hipError_t e = hipError_t(launch_enqueue_op(h->n, h->args, o, nullptr));
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   return to_code(e);
 }
 

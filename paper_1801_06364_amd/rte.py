@@ -26,7 +26,7 @@ EXPORTS = (
     "rte_readings", "rte_residuals", "rte_steps_done", "rte_get_state",
     "rte_set_state", "rte_coupling_dense", "rte_profile_kernels", "rte_destroy",
     "rte_strerror", "rte_adjoint_workspace_bytes", "rte_forward_checkpointed",
-    "rte_adjoint",
+    "rte_adjoint", "rte_krylov_workspace_bytes", "rte_steady_gmres", "rte_expo_advance",
 )
 KERNEL_CLASSES = ("fwd_plane", "zderiv", "couple", "inv_plane", "end_step",
                   "fwd_rows", "y_fwd", "y_inv", "inv_rows")
@@ -101,6 +101,12 @@ def lib():
         L.rte_forward_checkpointed.restype = C.c_int
         L.rte_adjoint.argtypes = [vp, C.c_int64, C.c_int64, vp, C.c_size_t, dp, dp, dp]
         L.rte_adjoint.restype = C.c_int
+        L.rte_krylov_workspace_bytes.argtypes = [C.POINTER(rte_config), C.c_int32]
+        L.rte_krylov_workspace_bytes.restype = C.c_size_t
+        L.rte_steady_gmres.argtypes = [vp, C.c_int32, C.c_int64, C.c_double, vp, C.c_size_t, i64p, dp]
+        L.rte_steady_gmres.restype = C.c_int
+        L.rte_expo_advance.argtypes = [vp, C.c_double]
+        L.rte_expo_advance.restype = C.c_int
         L.rte_destroy.argtypes = [vp]
         L.rte_destroy.restype = None
         L.rte_strerror.argtypes = [C.c_int]
@@ -244,6 +250,30 @@ class Solver:
     def set_state(self, psi: np.ndarray):
         a = _f64(psi).ravel()
         _check(lib().rte_set_state(self.h, _dptr(a), a.size), "rte_set_state")
+
+    # -- exact propagation (homogeneous media) -----------------------------
+    def expo_advance(self, t_ps: float):
+        """Advance the state by t_ps exactly (per-mode matrix exponential);
+        homogeneous medium without boundary layer only."""
+        _check(lib().rte_expo_advance(self.h, float(t_ps)), "rte_expo_advance")
+
+    # -- steady state by GMRES --------------------------------------------
+    def steady_gmres(self, tol: float = 1e-6, restart: int = 16, max_iters: int = 2000):
+        """Solve for the steady state in place (u <- solution of (S + Sigma)
+        u = q); returns (Arnoldi steps, final relative residual)."""
+        import torch
+        nbytes = int(lib().rte_krylov_workspace_bytes(C.byref(self.cfg), int(restart)))
+        if nbytes == 0:
+            raise RteError(RTE_EINVAL, "rte_krylov_workspace_bytes")
+        kws = torch.empty(nbytes, dtype=torch.uint8, device=self.workspace.device)
+        it = C.c_int64(0)
+        res = C.c_double(0.0)
+        rc = lib().rte_steady_gmres(self.h, int(restart), int(max_iters), float(tol),
+                                    C.c_void_p(kws.data_ptr()), nbytes, C.byref(it), C.byref(res))
+        self.stream.synchronize()
+        del kws
+        _check(rc, "rte_steady_gmres")
+        return int(it.value), float(res.value)
 
     # -- discrete adjoint ---------------------------------------------------
     def forward_checkpointed(self, steps: int, every: int = 0):
