@@ -158,6 +158,248 @@ def serving_bench(a):
     print(json.dumps(out), flush=True)
 
 
+FP32_VALU_PEAK = 157.3   # TFLOP/s, MI355X vector FP32 (published; counts packed FP32)
+
+
+def taylor_plan(kk, ct, sigmax, prec):
+    """Substeps s and Taylor terms J per spectral point of the exact
+    propagation (the kernel's rule: s = ceil(nu / theta), J the fewest terms
+    with (nu/s)^(J+1) / (J+1)! exp(nu/s) <= eps, nu = c T (|k| + max Sigma))."""
+    import math
+
+    import numpy as np
+    m, eps = (24, 2.0 ** -53) if prec == "f64" else (14, 2.0 ** -24)
+    lo, hi = 0.0, 64.0
+    for _ in range(200):
+        t = 0.5 * (lo + hi)
+        if (m + 1) * math.log(t) - math.lgamma(m + 2) + t <= math.log(eps):
+            lo = t
+        else:
+            hi = t
+    theta = lo
+    nu = ct * (kk + sigmax)
+    s = np.where(nu > theta, np.ceil(nu / theta), 1.0)
+    nus = nu / s
+    J = np.ones_like(nus)
+    bound = 0.5 * nus * nus * np.exp(nus)
+    for _ in range(m):
+        more = (bound > eps) & (J < m)
+        J = np.where(more, J + 1, J)
+        bound = np.where(more, bound * nus / (J + 1), bound)
+    return s, J, theta
+
+
+def expo_term_flops(N: int):
+    """Floating-point operations of one Taylor term at one spectral point:
+    per non-zero streaming entry, its value from k (1 flop for a z entry,
+    3 for an x/y entry) and the complex-by-real multiply-add (4); per
+    moment the loss, step scale and accumulation (8)."""
+    import numpy as np
+    from paper_1801_06364_amd.rte import rte_coupling_dense
+    bx, by, bz = rte_coupling_dense(N)
+    nz_z = int((bz != 0).sum())
+    nz_xy = int(((bx != 0) | (by != 0)).sum())
+    M = (N + 1) ** 2
+    return nz_z * 5 + nz_xy * 7 + 8 * M
+
+
+def expo_bench(a):
+    """Exact propagation (homogeneous medium, periodic grid) over the time
+    of 100 RK4 steps against marching those steps, both on the GPU."""
+    import numpy as np
+    import torch
+
+    import rte_inputs as ri
+    from paper_1801_06364_amd.rte import Solver
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    n, N, dx, c, prec = 128, 7, 0.25, 0.3, "f32"
+    mua, mus, g = 0.01, 10.0, 0.9
+    dt = 0.2 * dx / c
+    K = 100
+    T = K * dt
+    ma, ms_, gg = ri.homogeneous_maps(n, mua, mus, g)
+    psi0 = ri.gaussian_ic(n, 0, sigma=2.0)
+    M = (N + 1) ** 2
+
+    def solver(step_dt):
+        return Solver(n, N, dx, c, step_dt, ma, ms_, gg, psi0=psi0, W=0, precision=prec,
+                      stream=stream)
+
+    s = solver(dt)
+    s.expo_advance(T)                   # warm-up
+    s.set_state(np.concatenate([psi0, np.zeros((M - 1, n, n, n))]))
+    reps = max(1, a.expo_reps)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(reps):
+        s.expo_advance(T)
+    ev1.record(stream)
+    stream.synchronize()
+    ms_expo = ev0.elapsed_time(ev1) / reps
+    print(f"[expo] {reps} advances of {T:.3f} ps: {ms_expo:.2f} ms each", file=sys.stderr, flush=True)
+    s.set_state(np.concatenate([psi0, np.zeros((M - 1, n, n, n))]))
+    s.expo_advance(T)
+    ex = s.fluence()
+    prof = s.profile_expo(T)
+    s.close()
+
+    r = solver(dt)
+    r.step(5)
+    stream.synchronize()
+    r.set_state(np.concatenate([psi0, np.zeros((M - 1, n, n, n))]))
+    ev0.record(stream)
+    r.step(K)
+    ev1.record(stream)
+    stream.synchronize()
+    ms_rk4 = ev0.elapsed_time(ev1)
+    rk = r.fluence()
+    r.close()
+    print(f"[expo] {K} RK4 steps: {ms_rk4:.2f} ms", file=sys.stderr, flush=True)
+
+    k = 2 * np.pi * np.fft.fftfreq(n, d=dx)
+    k[n // 2] = 0.0
+    kz, ky, kx = np.meshgrid(k, k, k[: n // 2], indexing="ij")
+    kk = np.sqrt(kx * kx + ky * ky + kz * kz)
+    sigmax = max(mua + mus * (1 - g ** l) for l in range(N + 1))
+    sub, J, theta = taylor_plan(kk, c * T, sigmax, prec)
+    terms = float((sub * J).sum())
+    flops = terms * expo_term_flops(N)
+    t_expo = prof["expo"][0] / prof["expo"][1]
+    achieved = flops / (t_expo / 1e3) / 1e12
+    per = {k_: t / cnt for k_, (t, cnt) in prof.items()}
+    out = {"metric": "simulated time per second, exact propagation in a homogeneous medium",
+           "value": T / (ms_expo / 1e3), "unit": "ps/s", "n_gpus": 1, "steps": reps,
+           "warmup": 1, "ms_per_step": ms_expo, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": prec, "data": "synthetic",
+           "config": {"workload": f"homogeneous {n}^3 P_{N} (mu_a {mua}, mu_s {mus}, g {g}), "
+                                  f"dx {dx} mm, periodic grid, Gaussian pulse (sigma 2 voxels); "
+                                  f"one advance = {T:.4f} ps = {K} RK4 steps of dt 0.2 dx/c",
+                      "n": n, "order_N": N},
+           "rk4_ms_same_interval": ms_rk4, "speedup_vs_rk4": ms_rk4 / ms_expo,
+           "rk4_vs_exact_fluence_rel_l2": float(np.linalg.norm(rk - ex) / np.linalg.norm(ex)),
+           "kernel_ms_per_launch": per,
+           "taylor": {"theta": theta, "mean_substeps": float(sub.mean()), "max_substeps": float(sub.max()),
+                      "mean_terms_per_point": terms / sub.size},
+           "roofline": {"bound": "alu", "kernel": "expo", "achieved": achieved,
+                        "peak": FP32_VALU_PEAK, "unit": "TFLOP/s", "frac": achieved / FP32_VALU_PEAK,
+                        "traffic": None, "algorithmic_flops": flops, "avg_launch_ms": t_expo,
+                        "peak_without_packed_fp32": FP32_VALU_PEAK / 2}}
+    print(json.dumps(out), flush=True)
+
+
+def gmres_iteration_bytes(n, M, N, s, m, K):
+    """Compulsory HBM bytes of one Arnoldi step averaged over a restart
+    cycle of m steps. The operator: with K = 0 one application of S + Sigma
+    (forward plane pass 2F, z derivative 2F, coupling 3F, inverse pass
+    reading the spectrum, input and loss maps and writing the output
+    3F + maps); with K > 0 a copy (2F), K RK4 steps without bookkeeping (per
+    stage 2F + 2F + 3F and an inverse pass reading spectrum, stage input, u
+    and maps and writing 1: 4F + maps, the first stage reading u once: one F
+    less) and the difference (3F). Then two classical Gram-Schmidt passes
+    against j + 1 basis vectors (inner products read j + 2 vectors, the
+    update reads j + 2 and writes 1), the norm (F) and the normalisation
+    (2F)."""
+    F = M * n ** 3 * s
+    maps = (N + 1) * n ** 3 * s
+    if K == 0:
+        op = 10 * F + maps
+    else:
+        op = 2 * F + K * (4 * (11 * F + maps) - F) + 3 * F
+    tot = 0.0
+    for j in range(m):
+        tot += op + 2 * ((j + 2) * F + (j + 3) * F) + 3 * F
+    return tot / m
+
+
+def steady_bench(a):
+    """Steady state of the absorbing-layer recipe (log-normal medium,
+    collimated slab source) at 64^3 / P_5 by device GMRES against time
+    marching, both in FP32, each measured to the same distance from an FP64
+    GMRES reference."""
+    import numpy as np
+    import torch
+
+    import rte_inputs as ri
+    from paper_1801_06364_amd.rte import Solver
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    n = 64
+    ref_wl = ri.workload("p5_steady", n=n, steps=0, precision="f64")
+    r = Solver.from_workload(ref_wl, stream=stream)
+    it_ref, res_ref = r.steady_gmres(tol=1e-10, restart=30, max_iters=4000, steps_per_apply=a.steady_k)
+    ref = r.fluence()
+    r.close()
+    print(f"[steady] FP64 reference: {it_ref} Arnoldi steps, residual {res_ref:.1e}", file=sys.stderr,
+          flush=True)
+
+    def err(x):
+        return float(np.linalg.norm(x - ref) / np.linalg.norm(ref))
+
+    wl = ri.workload("p5_steady", n=n, steps=0, precision="f32")
+    g = Solver.from_workload(wl, stream=stream)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    it, res = g.steady_gmres(tol=a.steady_tol, restart=30, max_iters=4000, steps_per_apply=a.steady_k)
+    t_gmres = time.perf_counter() - t0
+    e_gmres = err(g.fluence())
+    g.close()
+    print(f"[steady] GMRES FP32: {it} Arnoldi steps, {t_gmres:.2f} s, fluence error {e_gmres:.2e}",
+          file=sys.stderr, flush=True)
+    # the same solve on the steady-state operator itself (no time steps)
+    g = Solver.from_workload(wl, stream=stream)
+    t0 = time.perf_counter()
+    it_a, res_a = g.steady_gmres(tol=a.steady_tol, restart=30, max_iters=4000, steps_per_apply=0)
+    t_a = time.perf_counter() - t0
+    e_a = err(g.fluence())
+    g.close()
+    print(f"[steady] GMRES on S + Sigma FP32: {it_a} Arnoldi steps, {t_a:.2f} s, fluence error {e_a:.2e}",
+          file=sys.stderr, flush=True)
+
+    m = Solver.from_workload(wl, stream=stream, record_steps=0)
+    steps, t_march, e_march = 0, 0.0, 1.0
+    chunk = 100
+    while e_march > e_gmres and t_march < a.steady_march_limit:
+        ev0.record(stream)
+        m.step(chunk)
+        ev1.record(stream)
+        stream.synchronize()
+        t_march += ev0.elapsed_time(ev1) / 1e3
+        steps += chunk
+        e_march = err(m.fluence())
+    m.close()
+    print(f"[steady] marching FP32: {steps} steps, {t_march:.2f} s, fluence error {e_march:.2e}",
+          file=sys.stderr, flush=True)
+    bytes_it = gmres_iteration_bytes(n, wl.M, wl.N, 4, 30, a.steady_k)
+    gbs = bytes_it * it / t_gmres / 1e9
+    out = {"metric": "time to steady state (device GMRES vs time marching)",
+           "value": t_gmres, "unit": "s", "n_gpus": 1, "steps": it, "warmup": 0,
+           "ms_per_step": 1e3 * t_gmres / max(it, 1), "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"p5_steady recipe at {n}^3 (P_5, log-normal medium, absorbing "
+                                  "layer, collimated slab source); target: the "
+                                  f"fluence error GMRES reaches at relative residual {a.steady_tol:g} "
+                                  f"(operator I - P^{a.steady_k}, P one RK4 step), against an FP64 "
+                                  "GMRES solve at 1e-10",
+                      "n": n, "order_N": wl.N, "restart": 30, "steps_per_apply": a.steady_k},
+           "gmres": {"arnoldi_steps": it, "residual": res, "seconds": t_gmres,
+                     "fluence_error": e_gmres},
+           "gmres_on_S_plus_Sigma": {"arnoldi_steps": it_a, "residual": res_a, "seconds": t_a,
+                                     "fluence_error": e_a},
+           "marching": {"steps": steps, "seconds": t_march, "fluence_error": e_march,
+                        "reached_target": e_march <= e_gmres},
+           "speedup_vs_marching": t_march / t_gmres,
+           "roofline": {"bound": "hbm", "kernel": "arnoldi step (operator + CGS2)",
+                        "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                        "algorithmic_bytes": bytes_it}}
+    print(json.dumps(out), flush=True)
+
+
 def accuracy_report():
     """FP32 and FP64 GPU results against the FP64 oracle on the bench recipe
     at a reduced size (p7_spheres, 32^3, 12 steps): relative L2 per result
@@ -207,6 +449,15 @@ def main():
     ap.add_argument("--slots", type=int, default=16)
     ap.add_argument("--large-slots", type=int, default=2)
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--expo", action="store_true",
+                    help="exact propagation vs RK4 marching in a homogeneous medium (separate JSON line)")
+    ap.add_argument("--expo-reps", type=int, default=5)
+    ap.add_argument("--steady", action="store_true",
+                    help="steady state by device GMRES vs time marching (separate JSON line)")
+    ap.add_argument("--steady-tol", type=float, default=1e-5)
+    ap.add_argument("--steady-k", type=int, default=20,
+                    help="time steps per operator application of the steady GMRES")
+    ap.add_argument("--steady-march-limit", type=float, default=60.0)
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the hot path is a single-GPU solve; "
@@ -221,6 +472,10 @@ def main():
 
     if a.serving:
         return serving_bench(a)
+    if a.expo:
+        return expo_bench(a)
+    if a.steady:
+        return steady_bench(a)
 
     wl = ri.workload(a.workload, steps=a.steps + a.warmup)
     torch.cuda.set_device(0)

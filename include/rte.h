@@ -176,23 +176,32 @@ int rte_adjoint(rte_handle* h, int64_t steps, int64_t every, void* adj_ws, size_
                 const double* dj_dr, double* grad_mu_a, double* grad_mu_s);
 
 /* ---- Steady state by a Krylov solve ---------------------------------
- * Instead of marching to steady state (Sec. II.A notes the steady state can
- * be found from the time-integrated operator with a Krylov method), solve
- * A u = q with A = S + Sigma (streaming plus per-degree loss, so that
- * c (-A u + q) = 0) by restarted GMRES. Vectors stay on the device; only the
- * small Hessenberg system crosses to the host. Inner product: sum over
- * moments of (2l+1) x_a y_a (orthonormal-basis coefficients), in which A is
- * positive real. The current state u is the initial guess and receives the
- * solution (read it back with rte_fluence / rte_get_state).
+ * Instead of marching to steady state, solve for it with a Krylov method
+ * (Sec. II.A: the time-integrated form gives an operator whose steady state
+ * a Krylov solver can find; Sec. IV: host-side Krylov solvers were limited
+ * by transfers). Restarted GMRES with every vector on the device; only the
+ * small Hessenberg system lives on the host. Inner product: sum over
+ * moments of (2l+1) x_a y_a (orthonormal-basis coefficients). The current
+ * state u is the initial guess and receives the solution (read it back with
+ * rte_fluence / rte_get_state). Two operators:
+ *   steps_per_apply = 0: A u = q with A = S + Sigma (streaming plus
+ *     per-degree loss, so that c (-A u + q) = 0);
+ *   steps_per_apply = K > 0: (I - P^K) u = P_q^K(0), P one source-free time
+ *     step of the handle's scheme and P_q^K(0) K steps with the source from
+ *     a zero state: the steady state as the fixed point of K steps. Fast
+ *     decaying modes are damped by the steps, which leaves GMRES the few
+ *     slow ones.
  *
  * rte_krylov_workspace_bytes: device bytes of the GMRES workspace
- * (restart + 1 basis vectors), 1 <= restart <= 31.
- * rte_steady_gmres: iterate until ||q - A u|| / ||q|| <= tol (weighted
- * norms) or max_iters Arnoldi steps; *iters and *rel_residual receive the
- * Arnoldi steps taken and the final true relative residual. */
+ * (restart + 3 state-sized vectors), 1 <= restart <= 31.
+ * rte_steady_gmres: iterate until the relative residual of the solved
+ * system (weighted norm) is <= tol or max_iters Arnoldi steps; *iters and
+ * *rel_residual receive the Arnoldi steps taken and the final relative
+ * residual ||q - A u|| / ||q|| of the steady-state equation. Resets the
+ * run bookkeeping (step count, readings, integrated fluence). */
 size_t rte_krylov_workspace_bytes(const rte_config* cfg, int32_t restart);
-int rte_steady_gmres(rte_handle* h, int32_t restart, int64_t max_iters, double tol, void* kws,
-                     size_t kbytes, int64_t* iters, double* rel_residual);
+int rte_steady_gmres(rte_handle* h, int32_t restart, int64_t max_iters, double tol, int32_t steps_per_apply,
+                     void* kws, size_t kbytes, int64_t* iters, double* rel_residual);
 
 /* ---- Exact propagation in homogeneous media --------------------------
  * The paper integrates the time-domain form analytically to obtain an
@@ -218,13 +227,18 @@ int rte_expo_advance(rte_handle* h, double t_ps);
 
 /* Run nsteps steps with plain launches, timing every kernel with HIP
  * events on the handle's stream, and store the summed milliseconds of each
- * kernel class in ms[0..8] and the launch counts in counts[0..8]. Classes:
+ * kernel class in ms[0..11] and the launch counts in counts[0..11]. Classes:
  * 0 forward plane pass, 1 z-derivative pass, 2 moment coupling pass,
  * 3 inverse plane pass with epilogue, 4 end-of-step bookkeeping; on grids
  * split into row and pencil passes (n = 256): 5 forward row pass,
  * 6 forward y pencil pass, 7 inverse y pencil pass, 8 inverse row pass with
- * epilogue. Synchronises the stream. */
+ * epilogue; of the exact propagation: 9 forward z pass, 10 per-point
+ * exponential, 11 inverse z pass. Synchronises the stream. */
 int rte_profile_kernels(rte_handle* h, int64_t nsteps, double* ms, int64_t* counts);
+
+/* rte_expo_advance with the same per-class event timing (ms[0..11],
+ * counts[0..11] as for rte_profile_kernels). */
+int rte_profile_expo(rte_handle* h, double t_ps, double* ms, int64_t* counts);
 
 /* Release the handle (and its captured graph). The workspace stays the
  * caller's. Safe on NULL. */

@@ -127,7 +127,8 @@ struct StepArgs {
 // Kernel classes timed by the profiling entry point.
 enum {
   PROF_FWD_PLANE = 0, PROF_ZDERIV, PROF_COUPLE, PROF_INV_PLANE, PROF_END,
-  PROF_FWD_ROWS, PROF_Y_FWD, PROF_Y_INV, PROF_INV_ROWS, PROF_CLASSES
+  PROF_FWD_ROWS, PROF_Y_FWD, PROF_Y_INV, PROF_INV_ROWS,
+  PROF_Z_FWD, PROF_EXPO, PROF_Z_INV, PROF_CLASSES
 };
 constexpr int kMaxProfLaunches = 32;
 
@@ -152,7 +153,8 @@ enum {
   OP_COMBINE = 7,    // y = coef * y + scale * sum_i djdr[i] x_i
   OP_SCALE = 8,      // y = x / djdr[0]
   OP_RHS_MINUS = 9,  // y = x - y (x may be null)
-  OP_EXPO = 10       // u <- exact propagation over time coef (homogeneous medium)
+  OP_EXPO = 10,      // u <- exact propagation over time coef (homogeneous medium)
+  OP_PSTEP = 11      // u <- one time step of u (y: stage scratch), no bookkeeping
 };
 struct OpArgs {
   int kind;

@@ -998,7 +998,7 @@ void enqueue_stage(const StepArgs& a, ProfRec* pr, double hs, double sgn, const 
 // (and of the source, into the derivative buffer), the per-point
 // exponential, inverse transforms written over the state.
 template <typename T, int NN, int N>
-hipError_t enqueue_expo(const StepArgs& a, const OpArgs& op) {
+hipError_t enqueue_expo(const StepArgs& a, const OpArgs& op, ProfRec* pr) {
   using V = typename cplx_of<T>::type;
   using Z = ZdShape<T, NN>;
   constexpr int M = (N + 1) * (N + 1);
@@ -1017,15 +1017,29 @@ hipError_t enqueue_expo(const StepArgs& a, const OpArgs& op) {
   const int pencils = M * n * Z::NTILE;
   const int rblocks = M * n * (n / RowShape<NN>::RB);
   const size_t lp = plane_lds<T, NN>(), lz = zd_lds<T, NN>(), lr = rows_lds<T, NN>();
+  auto rec = [&](int cls) {
+    if (pr && pr->count < kMaxProfLaunches) {
+      (void)hipEventRecord(static_cast<hipEvent_t>(pr->ev[pr->count]), st);
+      pr->cls[pr->count++] = cls;
+    }
+  };
+  if (pr) {
+    (void)hipEventRecord(static_cast<hipEvent_t>(pr->ev0), st);
+    pr->count = 0;
+  }
   auto forward = [&](const T* src, V* dst) {
     if constexpr (split_planes<NN>()) {
       hipLaunchKernelGGL((k_rows_fwd<T, NN>), dim3(rblocks), zblk, lr, st, src, dst, tw, cctl);
+      rec(PROF_FWD_ROWS);
       hipLaunchKernelGGL((k_pencil<T, NN, PENCIL_YFWD>), dim3(pencils), zblk, lz, st, dst, dst, tw, kv, cctl);
+      rec(PROF_Y_FWD);
     } else {
       hipLaunchKernelGGL((k_fwd_plane<T, NN>), dim3((planes + kFwdPlanes - 1) / kFwdPlanes), pblk, lp, st, src,
                          dst, tw, cctl, planes);
+      rec(PROF_FWD_PLANE);
     }
     hipLaunchKernelGGL((k_pencil<T, NN, PENCIL_ZFWD>), dim3(pencils), zblk, lz, st, dst, dst, tw, kv, cctl);
+    rec(PROF_Z_FWD);
   };
   if (q) forward(q, dspec);
   forward(u, spec);
@@ -1043,14 +1057,19 @@ hipError_t enqueue_expo(const StepArgs& a, const OpArgs& op) {
   const int eblocks = (n * n * H + kEBlock - 1) / kEBlock;
   hipLaunchKernelGGL((k_expo<T, NN, N>), dim3(eblocks), dim3(kEBlock), 0, st, spec, q ? dspec : nullptr, kv,
                      static_cast<const T*>(a.coef), p);
+  rec(PROF_EXPO);
   hipLaunchKernelGGL((k_pencil<T, NN, PENCIL_ZINV>), dim3(pencils), zblk, lz, st, spec, spec, tw, kv, cctl);
+  rec(PROF_Z_INV);
   if constexpr (split_planes<NN>()) {
     hipLaunchKernelGGL((k_pencil<T, NN, PENCIL_YINV>), dim3(pencils), zblk, lz, st, spec, spec, tw, kv, cctl);
+    rec(PROF_Y_INV);
     hipLaunchKernelGGL((k_rows_inv<T, NN, EPI_SET>), dim3(rblocks), zblk, lr, st, spec, u, u, u, sig,
                        static_cast<const T*>(nullptr), a.qflag, a.phi_int, a.partial, tw, M, T(0), 0.0, cctl);
+    rec(PROF_INV_ROWS);
   } else {
     hipLaunchKernelGGL((k_inv_plane<T, NN, EPI_SET>), dim3(planes), pblk, lp, st, spec, u, u, u, sig,
                        static_cast<const T*>(nullptr), a.qflag, a.phi_int, a.partial, tw, M, T(0), 0.0, cctl);
+    rec(PROF_INV_PLANE);
   }
   return hipGetLastError();
 }
@@ -1144,7 +1163,22 @@ hipError_t enqueue_t(const StepArgs& a, const OpArgs& op, ProfRec* pr) {
       break;
     }
     case OP_EXPO:
-      return enqueue_expo<T, NN, N>(a, op);
+      return enqueue_expo<T, NN, N>(a, op, pr);
+    case OP_PSTEP: {
+      // one step of the handle's scheme on op.u in place (op.y holds the
+      // stage values); the source is the one in a (null: none)
+      T* x = static_cast<T*>(op.u);
+      T* tmp = static_cast<T*>(op.y);
+      if (a.scheme == 1) {
+        enqueue_stage<T, NN, N, EPI_FIRST>(a, nullptr, hc, 1.0, x, x, x);
+      } else {
+        enqueue_stage<T, NN, N, EPI_FIRST>(a, nullptr, kRkAlpha[0] * hc, 1.0, x, x, tmp);
+        enqueue_stage<T, NN, N, EPI_MID>(a, nullptr, kRkAlpha[1] * hc, 1.0, tmp, x, tmp);
+        enqueue_stage<T, NN, N, EPI_MID>(a, nullptr, kRkAlpha[2] * hc, 1.0, tmp, x, tmp);
+        enqueue_stage<T, NN, N, EPI_MID>(a, nullptr, kRkAlpha[3] * hc, 1.0, tmp, x, x);
+      }
+      break;
+    }
     case OP_ADJ_INJECT: {
       hipLaunchKernelGGL((k_adj_inject<T>), dim3(1), dim3(kBlock), 0, st, static_cast<T*>(op.u), a.det,
                          op.djdr, a.ndet);

@@ -691,16 +691,17 @@ size_t rte_krylov_workspace_bytes(const rte_config* cfg, int32_t restart) {
   if (!rte::config_ok(cfg) || restart < 1 || restart + 1 > rte::kMaxBasisVectors) return 0;
   const size_t n = cfg->n, M = size_t(cfg->order_N + 1) * (cfg->order_N + 1);
   const size_t F = M * n * n * n * (cfg->precision == RTE_FP64 ? 8 : 4);
-  size_t o = rte::up(size_t(restart + 1) * F);            // Krylov basis
+  size_t o = rte::up(size_t(restart + 3) * F);            // basis, right-hand side, stage scratch
   o = rte::up(o + size_t(rte::kDotPartials) * 8);         // dot partial sums
   o = rte::up(o + 2 * size_t(rte::kMaxBasisVectors) * 8); // device coefficients
   return o;
 }
 
-int rte_steady_gmres(rte_handle* h, int32_t restart, int64_t max_iters, double tol, void* kws, size_t kbytes,
-                     int64_t* iters, double* rel_residual) {
+int rte_steady_gmres(rte_handle* h, int32_t restart, int64_t max_iters, double tol, int32_t steps_per_apply,
+                     void* kws, size_t kbytes, int64_t* iters, double* rel_residual) {
   using namespace rte;
-  if (!h || restart < 1 || restart + 1 > kMaxBasisVectors || max_iters < 1 || !(tol > 0)) return RTE_EINVAL;
+  if (!h || restart < 1 || restart + 1 > kMaxBasisVectors || max_iters < 1 || !(tol > 0) || steps_per_apply < 0)
+    return RTE_EINVAL;
   const size_t need = rte_krylov_workspace_bytes(&h->cfg, restart);
   if (!kws || (reinterpret_cast<uintptr_t>(kws) % kAlign) != 0 || kbytes < need) return RTE_ENOMEM;
   {
@@ -712,24 +713,52 @@ int rte_steady_gmres(rte_handle* h, int32_t restart, int64_t max_iters, double t
     if (rc) return rc;
   }
   const int m = restart;
+  const int K = steps_per_apply;
   const size_t F = state_bytes(h);
   unsigned char* w = static_cast<unsigned char*>(kws);
   unsigned char* basis = w;
-  double* partial = reinterpret_cast<double*>(w + up(size_t(m + 1) * F));
-  double* dcoef = reinterpret_cast<double*>(w + up(up(size_t(m + 1) * F) + size_t(kDotPartials) * 8));
+  unsigned char* bvec = w + size_t(m + 1) * F;     // right-hand side of the propagator system
+  unsigned char* tmp = w + size_t(m + 2) * F;      // stage values of the time steps
+  double* partial = reinterpret_cast<double*>(w + up(size_t(m + 3) * F));
+  double* dcoef = reinterpret_cast<double*>(w + up(up(size_t(m + 3) * F) + size_t(kDotPartials) * 8));
   double* dout = dcoef + kMaxBasisVectors;
   hipStream_t st = h->stream;
   hipError_t e = hipSuccess;
-  auto op = [&](OpArgs o) {
-    if (e == hipSuccess) e = hipError_t(launch_enqueue_op(h->n, h->args, o, nullptr));
+  StepArgs nosrc = h->args;
+  nosrc.q = nullptr;
+  auto op = [&](const StepArgs& args, OpArgs o) {
+    if (e == hipSuccess) e = hipError_t(launch_enqueue_op(h->n, args, o, nullptr));
   };
   auto vec = [&](int i) { return static_cast<void*>(basis + size_t(i) * F); };
-  auto apply = [&](const void* x, void* y) {
+  auto steps_on = [&](const StepArgs& args, void* x) {   // K time steps of x in place
+    for (int k = 0; k < K; ++k) {
+      OpArgs o{};
+      o.kind = OP_PSTEP;
+      o.u = x;
+      o.y = tmp;
+      op(args, o);
+    }
+  };
+  auto rhs_minus = [&](const void* b, void* y) {   // y = b - y
     OpArgs o{};
-    o.kind = OP_APPLY;
-    o.x = x;
+    o.kind = OP_RHS_MINUS;
+    o.x = b;
     o.y = y;
-    op(o);
+    op(h->args, o);
+  };
+  // y = A x with A = S + Sigma, or y = x - P^K x with P one source-free time step
+  auto apply = [&](const void* x, void* y) {
+    if (K == 0) {
+      OpArgs o{};
+      o.kind = OP_APPLY;
+      o.x = x;
+      o.y = y;
+      op(h->args, o);
+    } else {
+      if (e == hipSuccess) e = hipMemcpyAsync(y, x, F, hipMemcpyDeviceToDevice, st);
+      steps_on(nosrc, y);
+      rhs_minus(x, y);
+    }
   };
   // out[0..count) = <basis_0..count-1, y>_W, copied to host vals
   auto wdots = [&](const void* base, int count, const void* y, double* vals) {
@@ -740,7 +769,7 @@ int rte_steady_gmres(rte_handle* h, int32_t restart, int64_t max_iters, double t
     o.count = count;
     o.gmua = partial;
     o.gmus = dout;
-    op(o);
+    op(h->args, o);
     if (e == hipSuccess) e = hipMemcpyAsync(vals, dout, size_t(count) * 8, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
   };
@@ -755,7 +784,7 @@ int rte_steady_gmres(rte_handle* h, int32_t restart, int64_t max_iters, double t
     o.count = count;
     o.djdr = dcoef;
     o.scale = scale;
-    op(o);
+    op(h->args, o);
     if (e == hipSuccess) e = hipStreamSynchronize(st);   // dcoef is reused
   };
   auto scale_into = [&](void* y, const void* x, double s) {
@@ -765,20 +794,24 @@ int rte_steady_gmres(rte_handle* h, int32_t restart, int64_t max_iters, double t
     o.x = x;
     o.y = y;
     o.djdr = dcoef;
-    op(o);
+    op(h->args, o);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
   };
-  auto residual_into = [&](void* r) {   // r = q - A u
+  const void* qv = h->has_q ? static_cast<const void*>(h->ws + h->lay.q) : nullptr;
+  // right-hand side: q, or the K source-driven steps from zero
+  const void* b = qv;
+  if (K > 0) {
+    if (e == hipSuccess) e = hipMemsetAsync(bvec, 0, F, st);
+    if (h->has_q) steps_on(h->args, bvec);
+    b = bvec;
+  }
+  auto residual_into = [&](void* r) {   // r = b - B u
     apply(h->ws + h->lay.u, r);
-    OpArgs o{};
-    o.kind = OP_RHS_MINUS;
-    o.x = h->has_q ? h->ws + h->lay.q : nullptr;
-    o.y = r;
-    op(o);
+    rhs_minus(b, r);
   };
   double bnorm = 0.0;
-  if (h->has_q) {
-    wdots(h->ws + h->lay.q, 1, h->ws + h->lay.q, &bnorm);
+  if (b) {
+    wdots(b, 1, b, &bnorm);
     bnorm = std::sqrt(bnorm);
   }
   int64_t it = 0;
@@ -837,6 +870,19 @@ int rte_steady_gmres(rte_handle* h, int32_t restart, int64_t max_iters, double t
     }
     if (j > 0) combine(h->ws + h->lay.u, 1.0, j, y.data(), 1.0);
   }
+  if (K > 0 && e == hipSuccess) {
+    // report the residual of the steady-state equation A u = q itself
+    OpArgs o{};
+    o.kind = OP_APPLY;
+    o.x = h->ws + h->lay.u;
+    o.y = vec(0);
+    op(h->args, o);
+    rhs_minus(qv, vec(0));
+    double rn = 0.0, qn = 0.0;
+    wdots(vec(0), 1, vec(0), &rn);
+    if (qv) wdots(qv, 1, qv, &qn);
+    rel = std::sqrt(rn) / (qn > 0 ? std::sqrt(qn) : 1.0);
+  }
   if (iters) *iters = it;
   if (rel_residual) *rel_residual = rel;
   if (e != hipSuccess) return RTE_EDEVICE;
@@ -858,7 +904,8 @@ double taylor_theta(int m, double eps) {
 }
 }  // namespace
 
-int rte_expo_advance(rte_handle* h, double t_ps) {
+namespace {
+int expo_run(rte_handle* h, double t_ps, rte::ProfRec* pr) {
   using namespace rte;
   if (!h || !std::isfinite(t_ps) || t_ps < 0) return RTE_EINVAL;
   if (!h->homogeneous) return RTE_EINVAL;
@@ -886,9 +933,49 @@ int rte_expo_advance(rte_handle* h, double t_ps) {
   o.scale = theta;
   o.eps = eps;
   for (int l = 0; l <= kMaxOrder; ++l) o.sigl[l] = h->sigl[l];
-  hipError_t e = hipError_t(launch_enqueue_op(h->n, h->args, o, nullptr));
+  hipError_t e = hipError_t(launch_enqueue_op(h->n, h->args, o, pr));
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   return to_code(e);
+}
+
+// Per-class sums of the event intervals of one recorded launch sequence.
+int collect_profile(const rte::ProfRec& pr, double* ms, int64_t* counts) {
+  for (int i = 0; i < pr.count; ++i) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, i == 0 ? static_cast<hipEvent_t>(pr.ev0) : static_cast<hipEvent_t>(pr.ev[i - 1]),
+                            static_cast<hipEvent_t>(pr.ev[i])) != hipSuccess)
+      return RTE_EDEVICE;
+    ms[pr.cls[i]] += t;
+    counts[pr.cls[i]] += 1;
+  }
+  return RTE_OK;
+}
+}  // namespace
+
+int rte_expo_advance(rte_handle* h, double t_ps) { return expo_run(h, t_ps, nullptr); }
+
+int rte_profile_expo(rte_handle* h, double t_ps, double* ms, int64_t* counts) {
+  using namespace rte;
+  if (!h || !ms || !counts) return RTE_EINVAL;
+  for (int c = 0; c < PROF_CLASSES; ++c) {
+    ms[c] = 0.0;
+    counts[c] = 0;
+  }
+  ProfRec pr{};
+  hipEvent_t e0;
+  hipEvent_t ev[kMaxProfLaunches];
+  if (hipEventCreate(&e0) != hipSuccess) return RTE_EDEVICE;
+  int made = 0;
+  for (; made < kMaxProfLaunches; ++made)
+    if (hipEventCreate(&ev[made]) != hipSuccess) break;
+  int rc = made == kMaxProfLaunches ? RTE_OK : RTE_EDEVICE;
+  pr.ev0 = e0;
+  for (int i = 0; i < made; ++i) pr.ev[i] = ev[i];
+  if (rc == RTE_OK) rc = expo_run(h, t_ps, &pr);
+  if (rc == RTE_OK) rc = collect_profile(pr, ms, counts);
+  (void)hipEventDestroy(e0);
+  for (int i = 0; i < made; ++i) (void)hipEventDestroy(ev[i]);
+  return rc;
 }
 
 int rte_profile_kernels(rte_handle* h, int64_t nsteps, double* ms, int64_t* counts) {
@@ -898,15 +985,16 @@ int rte_profile_kernels(rte_handle* h, int64_t nsteps, double* ms, int64_t* coun
   hipEvent_t e0;
   hipEvent_t ev[kMaxProfLaunches];
   if (hipEventCreate(&e0) != hipSuccess) return RTE_EDEVICE;
-  for (int i = 0; i < kMaxProfLaunches; ++i)
-    if (hipEventCreate(&ev[i]) != hipSuccess) return RTE_EDEVICE;
+  int made = 0;
+  for (; made < kMaxProfLaunches; ++made)
+    if (hipEventCreate(&ev[made]) != hipSuccess) break;
   pr.ev0 = e0;
-  for (int i = 0; i < kMaxProfLaunches; ++i) pr.ev[i] = ev[i];
+  for (int i = 0; i < made; ++i) pr.ev[i] = ev[i];
   for (int c = 0; c < PROF_CLASSES; ++c) {
     ms[c] = 0.0;
     counts[c] = 0;
   }
-  int rc = RTE_OK;
+  int rc = made == kMaxProfLaunches ? RTE_OK : RTE_EDEVICE;
   for (int64_t s = 0; s < nsteps && rc == RTE_OK; ++s) {
     hipError_t e = hipError_t(launch_enqueue_op(h->n, h->args, step_op(), &pr));
     if (e == hipSuccess && pr.count > 0) e = hipEventSynchronize(ev[pr.count - 1]);
@@ -914,18 +1002,10 @@ int rte_profile_kernels(rte_handle* h, int64_t nsteps, double* ms, int64_t* coun
       rc = RTE_EDEVICE;
       break;
     }
-    for (int i = 0; i < pr.count; ++i) {
-      float t = 0.f;
-      if (hipEventElapsedTime(&t, i == 0 ? e0 : ev[i - 1], ev[i]) != hipSuccess) {
-        rc = RTE_EDEVICE;
-        break;
-      }
-      ms[pr.cls[i]] += t;
-      counts[pr.cls[i]] += 1;
-    }
+    rc = collect_profile(pr, ms, counts);
   }
   (void)hipEventDestroy(e0);
-  for (int i = 0; i < kMaxProfLaunches; ++i) (void)hipEventDestroy(ev[i]);
+  for (int i = 0; i < made; ++i) (void)hipEventDestroy(ev[i]);
   return rc;
 }
 

@@ -27,9 +27,10 @@ EXPORTS = (
     "rte_set_state", "rte_coupling_dense", "rte_profile_kernels", "rte_destroy",
     "rte_strerror", "rte_adjoint_workspace_bytes", "rte_forward_checkpointed",
     "rte_adjoint", "rte_krylov_workspace_bytes", "rte_steady_gmres", "rte_expo_advance",
+    "rte_profile_expo",
 )
 KERNEL_CLASSES = ("fwd_plane", "zderiv", "couple", "inv_plane", "end_step",
-                  "fwd_rows", "y_fwd", "y_inv", "inv_rows")
+                  "fwd_rows", "y_fwd", "y_inv", "inv_rows", "z_fwd", "expo", "z_inv")
 
 
 class RteError(RuntimeError):
@@ -103,10 +104,13 @@ def lib():
         L.rte_adjoint.restype = C.c_int
         L.rte_krylov_workspace_bytes.argtypes = [C.POINTER(rte_config), C.c_int32]
         L.rte_krylov_workspace_bytes.restype = C.c_size_t
-        L.rte_steady_gmres.argtypes = [vp, C.c_int32, C.c_int64, C.c_double, vp, C.c_size_t, i64p, dp]
+        L.rte_steady_gmres.argtypes = [vp, C.c_int32, C.c_int64, C.c_double, C.c_int32, vp, C.c_size_t,
+                                       i64p, dp]
         L.rte_steady_gmres.restype = C.c_int
         L.rte_expo_advance.argtypes = [vp, C.c_double]
         L.rte_expo_advance.restype = C.c_int
+        L.rte_profile_expo.argtypes = [vp, C.c_double, dp, C.POINTER(C.c_int64)]
+        L.rte_profile_expo.restype = C.c_int
         L.rte_destroy.argtypes = [vp]
         L.rte_destroy.restype = None
         L.rte_strerror.argtypes = [C.c_int]
@@ -258,9 +262,12 @@ class Solver:
         _check(lib().rte_expo_advance(self.h, float(t_ps)), "rte_expo_advance")
 
     # -- steady state by GMRES --------------------------------------------
-    def steady_gmres(self, tol: float = 1e-6, restart: int = 16, max_iters: int = 2000):
+    def steady_gmres(self, tol: float = 1e-6, restart: int = 16, max_iters: int = 2000,
+                     steps_per_apply: int = 0):
         """Solve for the steady state in place (u <- solution of (S + Sigma)
-        u = q); returns (Arnoldi steps, final relative residual)."""
+        u = q), by GMRES on that operator (steps_per_apply = 0) or on
+        I - P^K with P one time step (steps_per_apply = K); returns (Arnoldi
+        steps, final relative residual of the steady-state equation)."""
         import torch
         nbytes = int(lib().rte_krylov_workspace_bytes(C.byref(self.cfg), int(restart)))
         if nbytes == 0:
@@ -268,7 +275,7 @@ class Solver:
         kws = torch.empty(nbytes, dtype=torch.uint8, device=self.workspace.device)
         it = C.c_int64(0)
         res = C.c_double(0.0)
-        rc = lib().rte_steady_gmres(self.h, int(restart), int(max_iters), float(tol),
+        rc = lib().rte_steady_gmres(self.h, int(restart), int(max_iters), float(tol), int(steps_per_apply),
                                     C.c_void_p(kws.data_ptr()), nbytes, C.byref(it), C.byref(res))
         self.stream.synchronize()
         del kws
@@ -311,6 +318,15 @@ class Solver:
         _check(lib().rte_profile_kernels(self.h, int(nsteps), _dptr(ms),
                                          cnt.ctypes.data_as(C.POINTER(C.c_int64))),
                "rte_profile_kernels")
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNEL_CLASSES) if cnt[i]}
+
+    def profile_expo(self, t_ps: float):
+        """expo_advance(t_ps) with per-kernel-class event timing."""
+        ms = np.zeros(len(KERNEL_CLASSES))
+        cnt = np.zeros(len(KERNEL_CLASSES), np.int64)
+        _check(lib().rte_profile_expo(self.h, float(t_ps), _dptr(ms),
+                                      cnt.ctypes.data_as(C.POINTER(C.c_int64))),
+               "rte_profile_expo")
         return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNEL_CLASSES) if cnt[i]}
 
     def close(self):

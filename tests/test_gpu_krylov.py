@@ -132,3 +132,25 @@ def test_gmres_single_mode_full_size(torch_cuda):
     print(f"[gmres] {it} Arnoldi steps, residual {res:.2e}, error {np.sqrt(err2 / ref2):.2e}", flush=True)
     assert res <= 1e-6
     assert np.sqrt(err2 / ref2) <= 1e-5
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-12), ("f32", 1e-6)])
+def test_propagator_gmres_matches_oracle(torch_cuda, steady16, prec, tol):
+    """GMRES on I - P^K (P one RK4 step without source, K = 20) reaches the
+    same steady state: the oracle's operator, applied to the result, gives a
+    residual within the tolerance the error bound below assumes, and the
+    state is within 30 x tol of the oracle's steady state."""
+    from paper_1801_06364_amd.rte import Solver
+    wl, ref = steady16
+    wl = ri.workload("p5_steady", n=16, steps=0, precision=prec)
+    s = Solver.from_workload(wl)
+    it, res = s.steady_gmres(tol=tol, restart=30, max_iters=500, steps_per_apply=20)
+    st = s.get_state()
+    s.close()
+    err = rel(st, ref)
+    ores = _oracle_residual(wl, st)
+    print(f"\n[gmres] propagator {prec}: {it} Arnoldi steps, residual {res:.2e} "
+          f"(oracle operator {ores:.2e}), error {err:.2e}", flush=True)
+    assert it < 200
+    assert ores <= 1.5 * max(res, tol)
+    assert err <= 30 * tol
