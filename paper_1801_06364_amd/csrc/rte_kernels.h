@@ -26,6 +26,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "rte_coupling_ct.h"
 #include "rte_fft.h"
 #include "rte_internal.h"
 
@@ -777,26 +778,34 @@ template <typename T> struct ExpoParams {
   T inv_n3;               // 1 / n^3 (unnormalised transforms)
 };
 
-// (k.B t)_A accumulated over the compile-time slots of row A: equal-order
-// slots carry Bz only, the others Bx and By only.
+// (B_j t)_A for j = x, y, z accumulated over the compile-time slots of row
+// A with the coefficients as instruction constants (every non-zero entry
+// of the real-basis matrices belongs to exactly one axis): acc holds
+// (re, im) per axis.
 template <typename V, typename T, int N, int A, int S>
 struct ExpoRowAcc {
-  static __device__ __forceinline__ void run(const V* t, const T* __restrict__ c, T kx, T ky, T kz, T& re,
-                                             T& im) {
+  static __device__ __forceinline__ void run(const V* t, T* acc) {
     constexpr int l = isqrt_c(A);
     constexpr int m = A - l * l - l;
     constexpr SlotList sl = slots_of(N, l, m);
     if constexpr (S < sl.count) {
       constexpr int b = sl.b[S];
-      constexpr int lb = isqrt_c(b);
-      constexpr int mb = b - lb * lb - lb;
-      const T* e = c + (A * kMaxSlots + S) * 3;
-      T cf;
-      if constexpr (mb == m) cf = e[2] * kz;
-      else cf = e[0] * kx + e[1] * ky;
-      re += cf * t[b].x;
-      im += cf * t[b].y;
-      ExpoRowAcc<V, T, N, A, S + 1>::run(t, c, kx, ky, kz, re, im);
+      constexpr double c0 = ct::real_coef(N, 0, A, b);
+      constexpr double c1 = ct::real_coef(N, 1, A, b);
+      constexpr double c2 = ct::real_coef(N, 2, A, b);
+      if constexpr (c0 != 0.0) {
+        acc[0] += T(c0) * t[b].x;
+        acc[1] += T(c0) * t[b].y;
+      }
+      if constexpr (c1 != 0.0) {
+        acc[2] += T(c1) * t[b].x;
+        acc[3] += T(c1) * t[b].y;
+      }
+      if constexpr (c2 != 0.0) {
+        acc[4] += T(c2) * t[b].x;
+        acc[5] += T(c2) * t[b].y;
+      }
+      ExpoRowAcc<V, T, N, A, S + 1>::run(t, acc);
     }
   }
 };
@@ -805,13 +814,15 @@ struct ExpoRowAcc {
 // moments of one point; M t / c = -i (k.B) t - Sigma t.
 template <typename V, typename T, int N, int A, bool SRC>
 struct ExpoApply {
-  static __device__ __forceinline__ void run(const V* t, V* nt, V* acc, const T* __restrict__ c, T kx, T ky,
-                                             T kz, const ExpoParams<T>& p, T h, const V* __restrict__ qp,
+  static __device__ __forceinline__ void run(const V* t, V* nt, V* acc, T kx, T ky, T kz,
+                                             const ExpoParams<T>& p, T h, const V* __restrict__ qp,
                                              size_t ms) {
     if constexpr (A < (N + 1) * (N + 1)) {
       constexpr int l = isqrt_c(A);
-      T re = 0, im = 0;
-      ExpoRowAcc<V, T, N, A, 0>::run(t, c, kx, ky, kz, re, im);
+      T r[6] = {0, 0, 0, 0, 0, 0};
+      ExpoRowAcc<V, T, N, A, 0>::run(t, r);
+      const T re = kx * r[0] + ky * r[2] + kz * r[4];
+      const T im = kx * r[1] + ky * r[3] + kz * r[5];
       T ox = im - p.sig[l] * t[A].x;
       T oy = -re - p.sig[l] * t[A].y;
       if constexpr (SRC) {
@@ -821,7 +832,7 @@ struct ExpoApply {
       }
       nt[A] = cmk<V>(h * ox, h * oy);
       acc[A] = cmk<V>(acc[A].x + nt[A].x, acc[A].y + nt[A].y);
-      ExpoApply<V, T, N, A + 1, SRC>::run(t, nt, acc, c, kx, ky, kz, p, h, qp, ms);
+      ExpoApply<V, T, N, A + 1, SRC>::run(t, nt, acc, kx, ky, kz, p, h, qp, ms);
     }
   }
 };
@@ -835,7 +846,7 @@ constexpr int kEBlock = 256;
 template <typename T, int NN, int N>
 __global__ void __launch_bounds__(kEBlock)
 k_expo(typename cplx_of<T>::type* __restrict__ spec, const typename cplx_of<T>::type* __restrict__ qs,
-       const T* __restrict__ kv, const T* __restrict__ coef, ExpoParams<T> p) {
+       const T* __restrict__ kv, ExpoParams<T> p) {
   using V = typename cplx_of<T>::type;
   constexpr int n = NN, H = NN / 2;
   constexpr int M = (N + 1) * (N + 1);
@@ -865,17 +876,9 @@ k_expo(typename cplx_of<T>::type* __restrict__ spec, const typename cplx_of<T>::
     a[i] = cmk<V>(p.inv_n3 * x.x, p.inv_n3 * x.y);
   }
   const V* qp = qs ? qs + pt : nullptr;
-  // The operator's entries (k.B)[a][b] are loop invariant; left to itself
-  // the compiler keeps all of them in registers across the series (several
-  // hundred per point at N = 7) and spills. Making the wavenumbers and the
-  // table address opaque per term keeps them recomputed from the scalar
-  // cache instead (a few ALU operations per entry).
   auto term = [&](const V* src, V* dst, T hj, bool first) __attribute__((always_inline)) {
-    T qx = kx, qy = ky, qz = kz;
-    const T* c = coef;
-    asm volatile("" : "+v"(qx), "+v"(qy), "+v"(qz));
-    if (first && qp) ExpoApply<V, T, N, 0, true>::run(src, dst, a, c, qx, qy, qz, p, hj, qp, MS);
-    else ExpoApply<V, T, N, 0, false>::run(src, dst, a, c, qx, qy, qz, p, hj, nullptr, MS);
+    if (first && qp) ExpoApply<V, T, N, 0, true>::run(src, dst, a, kx, ky, kz, p, hj, qp, MS);
+    else ExpoApply<V, T, N, 0, false>::run(src, dst, a, kx, ky, kz, p, hj, nullptr, MS);
   };
   for (int sub = 0; sub < s; ++sub) {
 #pragma unroll
@@ -1055,8 +1058,7 @@ hipError_t enqueue_expo(const StepArgs& a, const OpArgs& op, ProfRec* pr) {
   p.eps = op.eps;
   p.inv_n3 = T(1.0 / (double(n) * n * n));
   const int eblocks = (n * n * H + kEBlock - 1) / kEBlock;
-  hipLaunchKernelGGL((k_expo<T, NN, N>), dim3(eblocks), dim3(kEBlock), 0, st, spec, q ? dspec : nullptr, kv,
-                     static_cast<const T*>(a.coef), p);
+  hipLaunchKernelGGL((k_expo<T, NN, N>), dim3(eblocks), dim3(kEBlock), 0, st, spec, q ? dspec : nullptr, kv, p);
   rec(PROF_EXPO);
   hipLaunchKernelGGL((k_pencil<T, NN, PENCIL_ZINV>), dim3(pencils), zblk, lz, st, spec, spec, tw, kv, cctl);
   rec(PROF_Z_INV);
