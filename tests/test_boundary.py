@@ -2,6 +2,7 @@
 validates configurations; its host-built streaming tables agree with the
 oracle's independent construction (no GPU needed)."""
 import os
+import pathlib
 import re
 
 import numpy as np
@@ -65,3 +66,51 @@ def test_real_basis_tables_match_oracle(N):
     for mine, B in zip((bx, by, bz), pn.coupling_matrices(N)):
         ref = (U.conj() @ B @ U.T).real
         assert np.abs(mine - ref).max() < 1e-14
+
+
+def test_compile_time_coefficients_match_host_tables(tmp_path):
+    """The streaming coefficients the exact-propagation kernel carries as
+    compile-time constants equal the host tables (N = 0..7), built and run
+    on the CPU with g++."""
+    import shutil
+    import subprocess
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    src = tmp_path / "ct_check.cpp"
+    src.write_text(r'''
+#include <cmath>
+#include <cstdio>
+#include <vector>
+#include "rte_coupling_ct.h"
+namespace rte { bool coupling_dense(int, std::vector<double>&, std::vector<double>&, std::vector<double>&); }
+int main() {
+  double worst = 0.0;
+  for (int N = 0; N <= 7; ++N) {
+    std::vector<double> b[3];
+    if (!rte::coupling_dense(N, b[0], b[1], b[2])) return 2;
+    const int M = (N + 1) * (N + 1);
+    for (int a = 0; a < M; ++a)
+      for (int d = 0; d < M; ++d) {
+        int axes = 0;
+        for (int ax = 0; ax < 3; ++ax) {
+          const double c = rte::ct::real_coef(N, ax, a, d);
+          const double t = b[ax][a * M + d];
+          if ((t == 0.0) != (std::fabs(c) < 1e-15)) return 3;
+          worst = std::fmax(worst, std::fabs(c - t));
+          axes += t != 0.0;
+        }
+        if (axes > 1) return 4;   // every non-zero belongs to one axis
+      }
+  }
+  std::printf("%.3e\n", worst);
+  return worst < 1e-15 ? 0 : 5;
+}
+''')
+    root = pathlib.Path(__file__).resolve().parents[1]
+    cs = root / "paper_1801_06364_amd" / "csrc"
+    exe = tmp_path / "ct_check"
+    subprocess.run([gxx, "-std=c++17", "-O1", f"-I{cs}", f"-I{root / 'include'}", str(src),
+                    str(cs / "rte_tables.cpp"), "-o", str(exe)], check=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0, (r.returncode, r.stdout)
