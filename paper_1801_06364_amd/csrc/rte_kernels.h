@@ -318,26 +318,31 @@ k_rows_fwd(const T* __restrict__ src, typename cplx_of<T>::type* __restrict__ sp
 // with Bz non-zero only between equal orders m.
 template <typename V, typename T, int N, int A, int S>
 struct RowAcc {
-  static __device__ __forceinline__ void run(const V* in, const V* __restrict__ dcol, size_t mstride,
-                                             const T* __restrict__ c, T kx, T ky, T& re, T& im,
-                                             T& dre, T& dim) {
+  // acc: (re, im) of the x and y sums of S, then of the z sum of D; the
+  // coefficients are instruction constants (one axis per non-zero)
+  static __device__ __forceinline__ void run(const V* in, const V* __restrict__ dcol, size_t mstride, T* acc) {
     constexpr int l = isqrt_c(A);
     constexpr int m = A - l * l - l;
     constexpr SlotList sl = slots_of(N, l, m);
     if constexpr (S < sl.count) {
       constexpr int b = sl.b[S];
-      constexpr int lb = isqrt_c(b);
-      constexpr int mb = b - lb * lb - lb;
-      const T* t = c + (A * kMaxSlots + S) * 3;
-      const T cf = t[0] * kx + t[1] * ky;
-      re += cf * in[b].x;
-      im += cf * in[b].y;
-      if constexpr (mb == m) {
-        const V d = dcol[b * mstride];
-        dre += t[2] * d.x;
-        dim += t[2] * d.y;
+      constexpr double c0 = ct::real_coef(N, 0, A, b);
+      constexpr double c1 = ct::real_coef(N, 1, A, b);
+      constexpr double c2 = ct::real_coef(N, 2, A, b);
+      if constexpr (c0 != 0.0) {
+        acc[0] += T(c0) * in[b].x;
+        acc[1] += T(c0) * in[b].y;
       }
-      RowAcc<V, T, N, A, S + 1>::run(in, dcol, mstride, c, kx, ky, re, im, dre, dim);
+      if constexpr (c1 != 0.0) {
+        acc[2] += T(c1) * in[b].x;
+        acc[3] += T(c1) * in[b].y;
+      }
+      if constexpr (c2 != 0.0) {
+        const V d = dcol[b * mstride];
+        acc[4] += T(c2) * d.x;
+        acc[5] += T(c2) * d.y;
+      }
+      RowAcc<V, T, N, A, S + 1>::run(in, dcol, mstride, acc);
     }
   }
 };
@@ -357,8 +362,7 @@ __device__ __forceinline__ void load_shell(V* in, const V* __restrict__ sp, size
 template <typename V, typename T, int N, int A>
 struct Rows {
   static __device__ __forceinline__ void run(V* in, V* out, const V* __restrict__ dcol,
-                                             size_t mstride, const T* __restrict__ c, T kx, T ky,
-                                             T sc) {
+                                             size_t mstride, T kx, T ky, T sc) {
     if constexpr (A < (N + 1) * (N + 1)) {
       constexpr int l = isqrt_c(A);
       if constexpr (A == l * l && l >= 1) {
@@ -366,11 +370,12 @@ struct Rows {
         __builtin_amdgcn_sched_barrier(0);
         load_shell<V, l + 1, N>(in, out, mstride);
       }
-      T re = 0, im = 0, dre = 0, dim = 0;
-      RowAcc<V, T, N, A, 0>::run(in, dcol, mstride, c, kx, ky, re, im, dre, dim);
+      T acc[6] = {0, 0, 0, 0, 0, 0};
+      RowAcc<V, T, N, A, 0>::run(in, dcol, mstride, acc);
+      const T re = kx * acc[0] + ky * acc[2], im = kx * acc[1] + ky * acc[3];
       // -i (re + i im) - (dre + i dim)
-      out[A * mstride] = cmk<V>(sc * (im - dre), sc * (-re - dim));
-      Rows<V, T, N, A + 1>::run(in, out, dcol, mstride, c, kx, ky, sc);
+      out[A * mstride] = cmk<V>(sc * (im - acc[4]), sc * (-re - acc[5]));
+      Rows<V, T, N, A + 1>::run(in, out, dcol, mstride, kx, ky, sc);
     }
   }
 };
@@ -380,7 +385,7 @@ struct Rows {
 template <typename T, int NN, int N>
 __global__ void __launch_bounds__(kCBlock)
 k_couple(typename cplx_of<T>::type* __restrict__ spec, const typename cplx_of<T>::type* __restrict__ dspec,
-         const T* __restrict__ kv, const T* __restrict__ coef, T sc, const Ctl* __restrict__ ctl) {
+         const T* __restrict__ kv, T sc, const Ctl* __restrict__ ctl) {
   using V = typename cplx_of<T>::type;
   constexpr int n = NN, H = NN / 2;
   constexpr int M = (N + 1) * (N + 1);
@@ -393,7 +398,7 @@ k_couple(typename cplx_of<T>::type* __restrict__ spec, const typename cplx_of<T>
   V in[M];
   load_shell<V, 0, N>(in, spec + pt, MS);
   load_shell<V, 1, N>(in, spec + pt, MS);
-  Rows<V, T, N, 0>::run(in, spec + pt, dspec + pt, MS, coef, kv[kx], kv[ky], sc);
+  Rows<V, T, N, 0>::run(in, spec + pt, dspec + pt, MS, kv[kx], kv[ky], sc);
 }
 
 // ------------------------------------------- P: inverse + epilogue -------
@@ -952,7 +957,6 @@ void enqueue_stage(const StepArgs& a, ProfRec* pr, double hs, double sgn, const 
   V* dspec = static_cast<V*>(a.dspec);
   const V* tw = static_cast<const V*>(a.tw);
   const T* kv = static_cast<const T*>(a.kv);
-  const T* coef = static_cast<const T*>(a.coef);
   const T* sig = static_cast<const T*>(a.sig);
   const T* q = static_cast<const T*>(a.q);
   const Ctl* cctl = static_cast<const Ctl*>(a.ctl);
@@ -981,7 +985,7 @@ void enqueue_stage(const StepArgs& a, ProfRec* pr, double hs, double sgn, const 
   }
   hipLaunchKernelGGL((k_pencil<T, NN, PENCIL_ZDERIV>), dim3(pencils), zblk, lz, st, spec, dspec, tw, kv, cctl);
   rec(PROF_ZDERIV);
-  hipLaunchKernelGGL((k_couple<T, NN, N>), dim3(cblocks), cblk, 0, st, spec, dspec, kv, coef, T(sgn * hs / n2),
+  hipLaunchKernelGGL((k_couple<T, NN, N>), dim3(cblocks), cblk, 0, st, spec, dspec, kv, T(sgn * hs / n2),
                      cctl);
   rec(PROF_COUPLE);
   if constexpr (split_planes<NN>()) {
