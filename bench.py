@@ -283,7 +283,9 @@ def expo_bench(a):
                       "mean_terms_per_point": terms / sub.size},
            "roofline": {"bound": "alu", "kernel": "expo", "achieved": achieved,
                         "peak": FP32_VALU_PEAK, "unit": "TFLOP/s", "frac": achieved / FP32_VALU_PEAK,
-                        "traffic": None, "algorithmic_flops": flops, "avg_launch_ms": t_expo,
+                        "traffic": traffic_for("expo", "expo_homogeneous_128"),
+                        "compulsory_bytes": 2 * M * n ** 3 * 4,
+                        "algorithmic_flops": flops, "avg_launch_ms": t_expo,
                         "peak_without_packed_fp32": FP32_VALU_PEAK / 2}}
     print(json.dumps(out), flush=True)
 
