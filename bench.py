@@ -400,6 +400,64 @@ def steady_bench(a):
     print(json.dumps(out), flush=True)
 
 
+def paper_bench(a):
+    """The paper's two experiments as synthetic workloads (Sec. III.A: P_21,
+    64^3, 400 Euler steps; Sec. III.B: P_7, 64^3 with absorbing layer,
+    25,000 Euler steps), timed on the GPU beside the paper's reported wall
+    times (Tesla K40: 70 s and 223 s; context, other hardware)."""
+    import numpy as np
+    import torch
+
+    import rte_inputs as ri
+    from paper_1801_06364_amd.rte import Solver
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    out = {}
+    for key, name, paper_s in (("E1_transient_P21", "paper_transient", 70.0),
+                               ("E2_steady_pml_P7", "paper_pml_steady", 223.0)):
+        wl = ri.workload(name, precision="f32")
+        t0 = time.perf_counter()
+        s = Solver.from_workload(wl, stream=stream)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        s.step(wl.steps)
+        ev1.record(stream)
+        stream.synchronize()
+        wall = time.perf_counter() - t0
+        ms = ev0.elapsed_time(ev1)
+        fl = s.fluence()
+        assert s.steps_done() == wl.steps and np.all(np.isfinite(fl))
+        upd = wl.n ** 3 * wl.M * wl.steps
+        out[key] = {"workload": f"{name}: {wl.n}^3, P_{wl.N} ({wl.M} moments), {wl.steps} forward "
+                                f"Euler steps of {wl.dt} ps, FP32",
+                    "gpu_seconds_stepping": ms / 1e3, "wall_seconds_with_setup": wall,
+                    "ms_per_step": ms / wl.steps, "updates_per_s": upd / (ms / 1e3),
+                    "paper_seconds_k40": paper_s, "ratio_vs_paper": paper_s / wall}
+        s.close()
+        print(f"[paper] {key}: {ms / 1e3:.2f} s stepping, {wall:.2f} s with setup "
+              f"(paper {paper_s} s on a K40)", file=sys.stderr, flush=True)
+        if name == "paper_pml_steady":
+            g = Solver.from_workload(ri.workload(name, precision="f32", steps=0), stream=stream)
+            t0 = time.perf_counter()
+            it, res = g.steady_gmres(tol=1e-6, restart=30, max_iters=2000, steps_per_apply=20)
+            t_g = time.perf_counter() - t0
+            fg = g.fluence()
+            g.close()
+            out[key]["gmres_same_steady_state"] = {
+                "seconds": t_g, "arnoldi_steps": it, "residual": res,
+                "fluence_rel_diff_vs_25000_steps": float(np.linalg.norm(fg - fl) / np.linalg.norm(fl))}
+            print(f"[paper] E2 by GMRES: {t_g:.2f} s, {it} Arnoldi steps", file=sys.stderr, flush=True)
+    line = {"metric": "wall time of the paper's experiments (synthetic stand-ins)",
+            "value": out["E2_steady_pml_P7"]["wall_seconds_with_setup"], "unit": "s", "n_gpus": 1,
+            "higher_is_better": False, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "Sec. III.A transient (P_21) and Sec. III.B steady state with "
+                                   "absorbing layer (P_7), 64^3 each"},
+            "vs_baseline": None, "experiments": out}
+    print(json.dumps(line), flush=True)
+
+
 def accuracy_report():
     """FP32 and FP64 GPU results against the FP64 oracle on the bench recipe
     at a reduced size (p7_spheres, 32^3, 12 steps): relative L2 per result
@@ -454,6 +512,8 @@ def main():
     ap.add_argument("--expo-reps", type=int, default=5)
     ap.add_argument("--steady", action="store_true",
                     help="steady state by device GMRES vs time marching (separate JSON line)")
+    ap.add_argument("--paper", action="store_true",
+                    help="the paper's two experiments, timed (separate JSON line)")
     ap.add_argument("--steady-tol", type=float, default=1e-5)
     ap.add_argument("--steady-k", type=int, default=20,
                     help="time steps per operator application of the steady GMRES")
@@ -476,6 +536,8 @@ def main():
         return expo_bench(a)
     if a.steady:
         return steady_bench(a)
+    if a.paper:
+        return paper_bench(a)
 
     wl = ri.workload(a.workload, steps=a.steps + a.warmup)
     torch.cuda.set_device(0)

@@ -8,8 +8,16 @@
 
 namespace rte {
 
-constexpr int kMaxOrder = 7;                       // N <= 7
-constexpr int kMaxMoments = (kMaxOrder + 1) * (kMaxOrder + 1);
+// Orders built: every N <= kDenseOrder on every grid, and the high order
+// kHighOrder (484 moments, the paper's first experiment) on grids of at
+// most kHighOrderMaxGrid points per axis.
+constexpr int kDenseOrder = 7;
+constexpr int kHighOrder = 21;
+constexpr int kHighOrderMaxGrid = 64;
+constexpr int kMaxOrder = kHighOrder;              // largest order of any table
+constexpr bool order_built(int N, int n) {
+  return (N >= 0 && N <= kDenseOrder) || (N == kHighOrder && n <= kHighOrderMaxGrid);
+}
 // Largest Taylor degree of the exact propagation per working precision.
 constexpr int kTaylorMaxF32 = 14;
 constexpr int kTaylorMaxF64 = 24;
@@ -25,8 +33,8 @@ constexpr int isqrt_c(int a) {
 // operator of eq. (6) moves degree l to l +- 1 and order m to m or m +- 1;
 // in the real basis (cos / sin pairs) a row (l, m) can therefore only reach
 // (l +- 1, m') with m' in {m-1, m, m+1, -m-1, -m, -m+1}. The slots list those
-// partners (in range, de-duplicated, ascending l' then m'); the host table
-// stores one coefficient triple (Bx, By, Bz) per slot, possibly zero.
+// partners (in range, de-duplicated, ascending l' then m'); the kernels
+// unroll their coupling sums over these slots at compile time.
 struct SlotList {
   int count;
   int b[kMaxSlots];
@@ -57,8 +65,11 @@ constexpr SlotList slots_of(int N, int l, int m) {
 bool coupling_dense(int N, std::vector<double>& bx, std::vector<double>& by,
                     std::vector<double>& bz);
 
-// Per-slot coefficient table [a][kMaxSlots][3] (FP64) for the kernels.
-bool coupling_slots(int N, std::vector<double>& tab);
+// Coupling slot table of the high-order pass: per row a, the non-zeros of
+// the real-basis streaming matrices as codes (b << 2 | axis) in slot order,
+// -1 after the last, and their FP64 values. Returns false for an order that
+// is not built.
+bool coupling_table(int N, std::vector<int>& code, std::vector<double>& val);
 
 // Twiddles exp(-2 pi i t / n), t in [0, n), as interleaved (cos, sin) FP64.
 void twiddles(int n, std::vector<double>& tw);
@@ -107,9 +118,12 @@ struct StepArgs {
   void* spec;               // xy spectrum [M][n][n][n/2] complex (kx = 0 packs
                             // the real kx = 0 and kx = n/2 columns)
   void* dspec;              // its z derivative, same layout
+  void* wspec;              // coupled spectrum (orders above kDenseOrder only)
+  const int* ctab;          // coupling slots [M][kMaxSlots]: (b << 2 | axis), -1 ends
+                            // (orders above kDenseOrder only)
+  const void* cval;         // their coefficients [M][kMaxSlots] (working precision)
   const void* tw;           // twiddles exp(-2 pi i t / n), n complex
   const void* kv;           // wavenumbers, n
-  const void* coef;         // streaming slots [M][kMaxSlots][3]
   const void* sig;          // per-degree loss [N+1][n^3]
   const void* q;            // source [M][n^3] or nullptr
   const int* qflag;         // per z-plane: source present

@@ -401,6 +401,39 @@ k_couple(typename cplx_of<T>::type* __restrict__ spec, const typename cplx_of<T>
   Rows<V, T, N, 0>::run(in, spec + pt, dspec + pt, MS, kv[kx], kv[ky], sc);
 }
 
+// High orders (more moments than registers hold): one thread per spectral
+// point walks the rows at run time with the slot table, reading each input
+// from the spectrum (neighbouring shells stay in L1/L2 across rows) and
+// writing W to a separate buffer, since later rows still need the inputs.
+template <typename T, int NN>
+__global__ void __launch_bounds__(kCBlock)
+k_couple_rt(const typename cplx_of<T>::type* __restrict__ spec,
+            const typename cplx_of<T>::type* __restrict__ dspec, typename cplx_of<T>::type* __restrict__ out,
+            const T* __restrict__ kv, const int* __restrict__ code, const T* __restrict__ val, int M, T sc,
+            const Ctl* __restrict__ ctl) {
+  using V = typename cplx_of<T>::type;
+  constexpr int n = NN, H = NN / 2;
+  constexpr size_t MS = size_t(n) * n * H;
+  if (ctl->stop) return;
+  const int pt = blockIdx.x * kCBlock + threadIdx.x;   // (z * n + ky) * H + kx
+  if (pt >= n * n * H) return;
+  const T kx = kv[pt % H], ky = kv[(pt / H) % n];
+  for (int a = 0; a < M; ++a) {
+    T acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int s = 0; s < kMaxSlots; ++s) {
+      const int c = code[a * kMaxSlots + s];
+      if (c < 0) break;
+      const int b = c >> 2, ax = c & 3;
+      const T w = val[a * kMaxSlots + s];
+      const V x = ax == 2 ? dspec[b * MS + pt] : spec[b * MS + pt];
+      acc[2 * ax] += w * x.x;
+      acc[2 * ax + 1] += w * x.y;
+    }
+    const T re = kx * acc[0] + ky * acc[2], im = kx * acc[1] + ky * acc[3];
+    out[a * MS + pt] = cmk<V>(sc * (im - acc[4]), sc * (-re - acc[5]));
+  }
+}
+
 // ------------------------------------------- P: inverse + epilogue -------
 
 // Complex-to-real merge of RB packed spectral rows in LDS (pitch LP):
@@ -985,18 +1018,26 @@ void enqueue_stage(const StepArgs& a, ProfRec* pr, double hs, double sgn, const 
   }
   hipLaunchKernelGGL((k_pencil<T, NN, PENCIL_ZDERIV>), dim3(pencils), zblk, lz, st, spec, dspec, tw, kv, cctl);
   rec(PROF_ZDERIV);
-  hipLaunchKernelGGL((k_couple<T, NN, N>), dim3(cblocks), cblk, 0, st, spec, dspec, kv, T(sgn * hs / n2),
-                     cctl);
+  V* coupled = spec;   // the inverse passes read the coupled spectrum from here
+  if constexpr (N <= kDenseOrder) {
+    hipLaunchKernelGGL((k_couple<T, NN, N>), dim3(cblocks), cblk, 0, st, spec, dspec, kv, T(sgn * hs / n2),
+                       cctl);
+  } else {
+    coupled = static_cast<V*>(a.wspec);
+    hipLaunchKernelGGL((k_couple_rt<T, NN>), dim3(cblocks), cblk, 0, st, spec, dspec, coupled, kv, a.ctab,
+                       static_cast<const T*>(a.cval), M, T(sgn * hs / n2), cctl);
+  }
   rec(PROF_COUPLE);
   if constexpr (split_planes<NN>()) {
-    hipLaunchKernelGGL((k_pencil<T, NN, PENCIL_YINV>), dim3(pencils), zblk, lz, st, spec, spec, tw, kv, cctl);
+    hipLaunchKernelGGL((k_pencil<T, NN, PENCIL_YINV>), dim3(pencils), zblk, lz, st, coupled, coupled, tw, kv,
+                       cctl);
     rec(PROF_Y_INV);
-    hipLaunchKernelGGL((k_rows_inv<T, NN, MODE>), dim3(rblocks), zblk, lr, st, spec, src, u, out, sig, q, a.qflag,
-                       a.phi_int, a.partial, tw, M, T(hs), a.dt, cctl);
+    hipLaunchKernelGGL((k_rows_inv<T, NN, MODE>), dim3(rblocks), zblk, lr, st, coupled, src, u, out, sig, q,
+                       a.qflag, a.phi_int, a.partial, tw, M, T(hs), a.dt, cctl);
     rec(PROF_INV_ROWS);
   } else {
-    hipLaunchKernelGGL((k_inv_plane<T, NN, MODE>), dim3(planes), pblk, lp, st, spec, src, u, out, sig, q, a.qflag,
-                       a.phi_int, a.partial, tw, M, T(hs), a.dt, cctl);
+    hipLaunchKernelGGL((k_inv_plane<T, NN, MODE>), dim3(planes), pblk, lp, st, coupled, src, u, out, sig, q,
+                       a.qflag, a.phi_int, a.partial, tw, M, T(hs), a.dt, cctl);
     rec(PROF_INV_PLANE);
   }
 }
@@ -1169,7 +1210,8 @@ hipError_t enqueue_t(const StepArgs& a, const OpArgs& op, ProfRec* pr) {
       break;
     }
     case OP_EXPO:
-      return enqueue_expo<T, NN, N>(a, op, pr);
+      if constexpr (N <= kDenseOrder) return enqueue_expo<T, NN, N>(a, op, pr);
+      else return hipErrorInvalidValue;
     case OP_PSTEP: {
       // one step of the handle's scheme on op.u in place (op.y holds the
       // stage values); the source is the one in a (null: none)
@@ -1208,8 +1250,12 @@ hipError_t dispatch_tn(const StepArgs& a, Args... args) {
     case 5: return Fn<T, NN, 5>::call(a, args...);     \
     case 6: return Fn<T, NN, 6>::call(a, args...);     \
     case 7: return Fn<T, NN, 7>::call(a, args...);     \
-    default: return hipErrorInvalidValue;              \
-  }
+    default: break;                                    \
+  }                                                    \
+  if constexpr (NN <= kHighOrderMaxGrid) {             \
+    if (a.N == kHighOrder) return Fn<T, NN, kHighOrder>::call(a, args...); \
+  }                                                    \
+  return hipErrorInvalidValue;
   if (a.prec == 1) {
     RTE_CASE_N(double)
   } else {

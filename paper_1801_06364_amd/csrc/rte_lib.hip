@@ -22,14 +22,15 @@ constexpr size_t kAlign = 256;
 inline size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t u, v, spec, dspec, sig, q, qflag, tw, kv, coef, det, readings, resid, partial, phi_int, gin, ctl,
+  size_t u, v, spec, dspec, wspec, ctab, cval, sig, q, qflag, tw, kv, det, readings, resid, partial, phi_int,
+      gin, ctl,
       total;
 };
 
 inline bool config_ok(const rte_config* c) {
   if (!c) return false;
   if (!grid_supported(c->n)) return false;
-  if (c->order_N < 0 || c->order_N > kMaxOrder) return false;
+  if (!order_built(c->order_N, c->n)) return false;
   if (c->precision != RTE_FP32 && c->precision != RTE_FP64) return false;
   if (c->pml_width < 0 || 2 * c->pml_width >= c->n) return false;
   if (!(c->dx_mm > 0) || !(c->c_mm_ps > 0) || !std::isfinite(c->dx_mm) || !std::isfinite(c->c_mm_ps))
@@ -56,12 +57,16 @@ inline Layout layout_of(const rte_config* c, bool has_q) {
   L.v = o; o = up(o + M * V * s);
   L.spec = o; o = up(o + M * n * n * (n / 2) * 2 * s);
   L.dspec = o; o = up(o + M * n * n * (n / 2) * 2 * s);
+  // orders above kDenseOrder: coupled-spectrum buffer and slot table
+  const bool high = c->order_N > kDenseOrder;
+  L.wspec = o; o = up(o + (high ? M * n * n * (n / 2) * 2 * s : 0));
+  L.ctab = o; o = up(o + (high ? M * kMaxSlots * sizeof(int) : 0));
+  L.cval = o; o = up(o + (high ? M * kMaxSlots * s : 0));
   L.sig = o; o = up(o + size_t(c->order_N + 1) * V * s);
   L.q = o; o = up(o + (has_q ? M * V * s : 0));
   L.qflag = o; o = up(o + n * sizeof(int));
   L.tw = o; o = up(o + n * 2 * s);
   L.kv = o; o = up(o + n * s);
-  L.coef = o; o = up(o + M * kMaxSlots * 3 * s);
   L.det = o; o = up(o + size_t(c->n_det) * 8);
   L.readings = o; o = up(o + size_t(c->record_steps) * c->n_det * 8);
   L.resid = o; o = up(o + size_t(c->record_steps) * 8);
@@ -215,7 +220,7 @@ double growth_limit_of(const rte_handle* h, const double* psi0, const double* q,
 
 template <typename T>
 int upload_tables_t(rte_handle* h, const rte_medium* med, const std::vector<double>& sig,
-                    const std::vector<uint8_t>& inside, const std::vector<double>& coef) {
+                    const std::vector<uint8_t>& inside) {
   const int n = h->n;
   const size_t V = size_t(n) * n * n;
   const Layout& L = h->lay;
@@ -234,8 +239,6 @@ int upload_tables_t(rte_handle* h, const rte_medium* med, const std::vector<doub
   wavenumbers(n, h->cfg.dx_mm, kv);
   convert_upload(tmp, kv.data(), kv.size());
   put(L.kv, tmp.data(), tmp.size() * sizeof(T));
-  convert_upload(tmp, coef.data(), coef.size());
-  put(L.coef, tmp.data(), tmp.size() * sizeof(T));
   std::vector<int> qflag(n, 0);
   if (h->has_q) {
     std::vector<double> qm(size_t(h->M) * V);
@@ -257,6 +260,14 @@ int upload_tables_t(rte_handle* h, const rte_medium* med, const std::vector<doub
     put(L.gin, gin.data(), V * 8);
   }
   if (h->cfg.n_det > 0) put(L.det, h->cfg.det_index, size_t(h->cfg.n_det) * 8);
+  if (h->N > kDenseOrder) {
+    std::vector<int> code;
+    std::vector<double> val;
+    if (!coupling_table(h->N, code, val)) return RTE_EINVAL;
+    put(L.ctab, code.data(), code.size() * sizeof(int));
+    convert_upload(tmp, val.data(), val.size());
+    put(L.cval, tmp.data(), tmp.size() * sizeof(T));
+  }
   return to_code(e);
 }
 
@@ -354,8 +365,6 @@ int rte_create(const rte_config* cfg, const rte_medium* med, void* dev_ws, size_
   const Layout L = layout_of(cfg, has_q);
   if (!dev_ws || (reinterpret_cast<uintptr_t>(dev_ws) % kAlign) != 0 || ws_bytes < L.total) return RTE_ENOMEM;
 
-  std::vector<double> coef;
-  if (!coupling_slots(N, coef)) return RTE_EINVAL;
   std::vector<double> sig;
   std::vector<uint8_t> inside;
   potentials(n, N, cfg->pml_width, cfg->pml_mu0, cfg->pml_mu1, med->mu_a, med->mu_s, med->g, sig, inside);
@@ -390,9 +399,11 @@ int rte_create(const rte_config* cfg, const rte_medium* med, void* dev_ws, size_
   A.v = h->ws + L.v;
   A.spec = h->ws + L.spec;
   A.dspec = h->ws + L.dspec;
+  A.wspec = N > kDenseOrder ? h->ws + L.wspec : nullptr;
+  A.ctab = N > kDenseOrder ? h->at<int>(L.ctab) : nullptr;
+  A.cval = N > kDenseOrder ? h->ws + L.cval : nullptr;
   A.tw = h->ws + L.tw;
   A.kv = h->ws + L.kv;
-  A.coef = h->ws + L.coef;
   A.sig = h->ws + L.sig;
   A.q = has_q ? h->ws + L.q : nullptr;
   A.qflag = h->at<int>(L.qflag);
@@ -407,8 +418,8 @@ int rte_create(const rte_config* cfg, const rte_medium* med, void* dev_ws, size_
   A.c = cfg->c_mm_ps;
   A.dt = h->dt;
   int rc = to_code(hipError_t(launch_prepare(n, A)));
-  if (!rc) rc = h->prec == RTE_FP64 ? upload_tables_t<double>(h, med, sig, inside, coef)
-                                    : upload_tables_t<float>(h, med, sig, inside, coef);
+  if (!rc) rc = h->prec == RTE_FP64 ? upload_tables_t<double>(h, med, sig, inside)
+                                    : upload_tables_t<float>(h, med, sig, inside);
   const int pm = (med->psi0_moments > 0 && med->psi0_moments < M) ? med->psi0_moments : M;
   if (!rc)
     rc = h->prec == RTE_FP64 ? upload_state_t<double>(h, med->psi0, pm) : upload_state_t<float>(h, med->psi0, pm);
@@ -908,7 +919,7 @@ namespace {
 int expo_run(rte_handle* h, double t_ps, rte::ProfRec* pr) {
   using namespace rte;
   if (!h || !std::isfinite(t_ps) || t_ps < 0) return RTE_EINVAL;
-  if (!h->homogeneous) return RTE_EINVAL;
+  if (!h->homogeneous || h->N > kDenseOrder) return RTE_EINVAL;
   if (t_ps == 0) return RTE_OK;
   const bool f64 = h->prec == RTE_FP64;
   const double eps = f64 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24);

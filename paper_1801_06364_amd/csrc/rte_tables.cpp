@@ -86,30 +86,35 @@ void real_from_complex(int N, std::vector<cplx>& U) {
 
 bool coupling_dense(int N, std::vector<double>& bx, std::vector<double>& by,
                     std::vector<double>& bz) {
-  if (N < 0 || N > kMaxOrder) return false;
+  if (!order_built(N, 0)) return false;
   const int M = (N + 1) * (N + 1);
   std::vector<cplx> B[3];
   complex_streaming(N, B[0], B[1], B[2]);
   std::vector<cplx> U;
   real_from_complex(N, U);
+  // non-zeros of each row of U (at most two: the orders +-|m| of degree l)
+  std::vector<std::vector<int>> unz(M);
+  for (int a = 0; a < M; ++a)
+    for (int b = 0; b < M; ++b)
+      if (U[a * M + b] != 0.0) unz[a].push_back(b);
   // Moments transform as psi^R = conj(U) psi, psi = U^T psi^R, so the
-  // real-basis matrix is conj(U) B U^T.
+  // real-basis matrix is conj(U) B U^T (products over the non-zeros of U).
   std::vector<double>* out[3] = {&bx, &by, &bz};
   for (int j = 0; j < 3; ++j) {
-    std::vector<cplx> T(M * M, 0.0);
+    std::vector<cplx> T(size_t(M) * M, 0.0);
     for (int a = 0; a < M; ++a)
       for (int c = 0; c < M; ++c) {
         cplx s = 0.0;
-        for (int b = 0; b < M; ++b) s += std::conj(U[a * M + b]) * B[j][b * M + c];
-        T[a * M + c] = s;
+        for (int b : unz[a]) s += std::conj(U[a * M + b]) * B[j][size_t(b) * M + c];
+        T[size_t(a) * M + c] = s;
       }
-    out[j]->assign(M * M, 0.0);
+    out[j]->assign(size_t(M) * M, 0.0);
     for (int a = 0; a < M; ++a)
       for (int d = 0; d < M; ++d) {
         cplx s = 0.0;
-        for (int c = 0; c < M; ++c) s += T[a * M + c] * U[d * M + c];
+        for (int c : unz[d]) s += T[size_t(a) * M + c] * U[d * M + c];
         if (std::abs(s.imag()) > 1e-13) return false;   // must be real
-        (*out[j])[a * M + d] = std::abs(s.real()) < 1e-15 ? 0.0 : s.real();
+        (*out[j])[size_t(a) * M + d] = std::abs(s.real()) < 1e-15 ? 0.0 : s.real();
       }
   }
   // Every non-zero must sit in a slot of its row.
@@ -127,22 +132,26 @@ bool coupling_dense(int N, std::vector<double>& bx, std::vector<double>& by,
   return true;
 }
 
-bool coupling_slots(int N, std::vector<double>& tab) {
-  std::vector<double> bx, by, bz;
-  if (!coupling_dense(N, bx, by, bz)) return false;
+bool coupling_table(int N, std::vector<int>& code, std::vector<double>& val) {
+  std::vector<double> b[3];
+  if (!coupling_dense(N, b[0], b[1], b[2])) return false;
   const int M = (N + 1) * (N + 1);
-  tab.assign(size_t(M) * kMaxSlots * 3, 0.0);
+  code.assign(size_t(M) * kMaxSlots, -1);
+  val.assign(size_t(M) * kMaxSlots, 0.0);
   for (int l = 0; l <= N; ++l)
     for (int m = -l; m <= l; ++m) {
       const int a = idx(l, m);
       const SlotList sl = slots_of(N, l, m);
-      for (int s = 0; s < sl.count; ++s) {
-        const int b = sl.b[s];
-        double* t = &tab[(size_t(a) * kMaxSlots + s) * 3];
-        t[0] = bx[a * M + b];
-        t[1] = by[a * M + b];
-        t[2] = bz[a * M + b];
-      }
+      int k = 0;
+      for (int s = 0; s < sl.count; ++s)
+        for (int ax = 0; ax < 3; ++ax) {
+          const double v = b[ax][size_t(a) * M + sl.b[s]];
+          if (v == 0.0) continue;
+          if (k == kMaxSlots) return false;
+          code[size_t(a) * kMaxSlots + k] = (sl.b[s] << 2) | ax;
+          val[size_t(a) * kMaxSlots + k] = v;
+          ++k;
+        }
     }
   return true;
 }

@@ -263,10 +263,31 @@ def workload(name: str, n: Optional[int] = None, steps: Optional[int] = None,
         return Workload(name, n, 7, precision or "f32", dx, c, 0.04, W, 0.01, 1.0,
                         steps if steps is not None else 25000, mu_a, mu_s, g, None, q,
                         np.zeros(0, np.int64), scheme="euler")
+    if name == "paper_transient":  # P_21, 64^3, 50 mm cube, two regions, no layer, Euler
+        # transient without absorbing layer as in the paper's first
+        # experiment: 50 mm grid, mu_a 0.01, g 0.9, mu_s 1.0 except 5.0 in
+        # the slab x <= 15 mm (x measured from the low-x face), isotropic
+        # Gaussian initial fluence (1/e diameter 1.5 mm) at the centre,
+        # forward Euler with dt 0.1 ps, 400 steps; fluence read along the
+        # x axis through the centre
+        n = n or 64
+        L = 50.0
+        dx = L / n
+        mu_a, mu_s, g = homogeneous_maps(n, 0.01, 1.0, 0.9)
+        xs = np.arange(n) * dx
+        mu_s[:, :, xs <= 15.0] = 5.0
+        sigma = 0.75 / np.sqrt(2.0) / dx
+        psi0 = gaussian_ic(n, 0, sigma=sigma)
+        c0 = n // 2
+        det = np.array([(c0 * n + c0) * n + x for x in range(0, n, max(1, n // 16))], np.int64)
+        return Workload(name, n, 21, precision or "f32", dx, c, 0.1, 0, 0.01, 1.0,
+                        steps if steps is not None else 400, mu_a, mu_s, g, psi0, None, det,
+                        scheme="euler")
     raise KeyError(name)
 
 
-WORKLOADS = ("p1_gauss", "p7_spheres", "p5_steady", "p3_adjoint", "paper_pml_steady")
+WORKLOADS = ("p1_gauss", "p7_spheres", "p5_steady", "p3_adjoint", "paper_pml_steady",
+             "paper_transient")
 
 
 # ------------------------------------------------------------- serving ---

@@ -34,7 +34,8 @@ def test_strerror_codes():
 
 
 @pytest.mark.parametrize("n,N,prec", [(32, 1, rte.RTE_FP64), (128, 7, rte.RTE_FP32),
-                                      (96, 3, rte.RTE_FP32), (48, 5, rte.RTE_FP64)])
+                                      (96, 3, rte.RTE_FP32), (48, 5, rte.RTE_FP64),
+                                      (64, 21, rte.RTE_FP32)])
 def test_workspace_bytes_cover_state_and_spectrum(n, N, prec):
     cfg, _ = rte.make_config(n, N, prec, 0.25, 0.3, 0.0, n // 8, 0.01, 1.0,
                              det_index=[0, 5], record_steps=100)
@@ -42,12 +43,12 @@ def test_workspace_bytes_cover_state_and_spectrum(n, N, prec):
     s = 8 if prec == rte.RTE_FP64 else 4
     M = (N + 1) ** 2
     floor = 3 * M * n ** 3 * s + n ** 3 * 8
-    assert floor <= b <= floor * 2
+    assert floor <= b <= floor * 2.2
 
 
-@pytest.mark.parametrize("bad", [dict(n=100), dict(n=512), dict(N=8),
-                                 dict(N=-1), dict(W=16, n=32), dict(dx=0.0), dict(c=-1.0),
-                                 dict(precision=7)])
+@pytest.mark.parametrize("bad", [dict(n=100), dict(n=512), dict(N=8), dict(N=20), dict(N=22),
+                                 dict(N=21, n=96, W=8), dict(N=-1), dict(W=16, n=32), dict(dx=0.0),
+                                 dict(c=-1.0), dict(precision=7)])
 def test_invalid_configs_rejected(bad):
     a = dict(n=32, N=1, precision=rte.RTE_FP64, dx=0.5, c=0.3, W=4)
     a.update(bad)
@@ -56,7 +57,7 @@ def test_invalid_configs_rejected(bad):
     assert rte.rte_workspace_bytes(cfg) == 0
 
 
-@pytest.mark.parametrize("N", [0, 1, 2, 3, 5, 7])
+@pytest.mark.parametrize("N", [0, 1, 2, 3, 5, 7, 21])
 def test_real_basis_tables_match_oracle(N):
     """The library's FP64 real-basis streaming matrices (eq. 6 rotated
     analytically) equal the oracle's (eq. 6 rotated by a quadrature-built

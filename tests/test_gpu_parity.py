@@ -55,6 +55,8 @@ CASES = [
     ("p7_spheres", 16, 8),      # smallest grid
     ("p3_adjoint", 96, 3),      # radix-3, larger
     ("paper_pml_steady", 32, 15),   # forward Euler (eq. 11), source, layer
+    ("paper_transient", 16, 4),     # P_21 (484 moments), two regions, Euler
+    ("paper_transient", 32, 3),
 ]
 
 
@@ -84,6 +86,24 @@ def test_parity_against_oracle(torch_cuda, name, n, steps, prec):
     res = s.residuals()
     assert res.shape == (steps,)
     assert np.allclose(res, ref["residual"], rtol=1e-3 if prec == "f32" else 1e-9, atol=1e-7)
+    s.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_high_order_rk4_with_layer(torch_cuda, prec):
+    """P_21 on the inclusion recipe (16^3, absorbing layer, detectors), three
+    RK4 steps: the run-time coupling table path against the oracle."""
+    print(f"\n[parity] p7_spheres as P_21 n=16 {prec}", flush=True)
+    wl = ri.workload("p7_spheres", n=16, steps=3, precision=prec)
+    wl.N = 21
+    ref = pn.solve(wl.n, wl.N, wl.dx, wl.c, wl.dt, wl.mu_a, wl.mu_s, wl.g, wl.psi0, None, wl.W,
+                   wl.mu0, wl.mu1, wl.steps, det_index=wl.det_index)
+    s = _solver(wl)
+    s.step(wl.steps)
+    assert rel(s.get_state(), ref["state"]) <= TOL[prec]
+    assert rel(s.fluence(1), ref["phi_int"]) <= TOL[prec]
+    err = np.abs(s.readings() - ref["readings"])
+    assert np.all(err <= TOL[prec] * ref["peak"][:, None])
     s.close()
 
 
