@@ -20,4 +20,5 @@ from .pn import (  # noqa: F401
     solve, to_complex_basis, to_real_basis, mode_matrix, rk4_poly,
     hg_phase, hg_legendre_moments, real_coupling, operator_transpose,
     adjoint_gradient, full_moments, euler_step, steady_state, expo_advance,
+    source_profile, source_moments, rk4_source_step,
 )

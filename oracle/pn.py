@@ -307,9 +307,57 @@ def euler_step(psi, f, dt):
     return psi + dt * f(psi)
 
 
+def source_profile(samples, delta):
+    """Temporal profile s(t) of a source ``q(r) s(t)`` (eq. 4 lets q depend
+    on time): linear between ``samples[i]`` at ``t = i * delta`` (t from the
+    start of the run), the last value after the last sample."""
+    samples = np.asarray(samples, float)
+    knots = delta * np.arange(samples.size)
+    return lambda t: np.interp(t, knots, samples)
+
+
+def source_moments(s_of_t, t0, h, knots):
+    """``m_j = int_0^h (h - tau)^j / j! s(t0 + tau) dtau`` for j = 0..3, by
+    adaptive quadrature (SciPy ``quad``) split at the profile's knots."""
+    from scipy.integrate import quad
+    pts = [k - t0 for k in knots if 0.0 < k - t0 < h]
+    out = []
+    for j in range(4):
+        f = (lambda tau, j=j: (h - tau) ** j / math.factorial(j) * s_of_t(t0 + tau))
+        val, _ = quad(f, 0.0, h, points=pts or None, epsabs=0.0, epsrel=1e-13, limit=200)
+        out.append(val)
+    return out
+
+
+def rk4_source_step(psi, lin, cq, h, m):
+    """One fourth-order step of ``d psi/dt = L psi + c q s(t)``: the
+    variation-of-constants formula with ``exp(h L)`` truncated after
+    ``(hL)^4 / 4!`` and the source integral after ``L^3``,
+    ``sum_j (hL)^j psi / j! + sum_j L^j (c q) m_j``, m_j the source moments
+    of the step. For constant s it is the classic RK4 step of an affine
+    system."""
+    out = psi.copy()
+    term = psi
+    for j in range(1, 5):
+        term = (h / j) * lin(term)
+        out = out + term
+    v = cq
+    for j in range(4):
+        out = out + m[j] * v
+        if j < 3:
+            v = lin(v)
+    return out
+
+
 def solve(n, N, dx, c, dt, mu_a, mu_s, g, psi0_real, q_real, W, mu0, mu1,
-          steps, det_index=(), workers=None, return_state=True, scheme="rk4"):
+          steps, det_index=(), workers=None, return_state=True, scheme="rk4",
+          q_profile=None):
     """March ``steps`` RK4 steps from ``psi0_real`` (real-basis moments).
+
+    ``q_profile = (samples, delta)`` makes the source ``q(r) s(t)`` with s
+    from :func:`source_profile` (t = 0 at the start); RK4 then takes
+    :func:`rk4_source_step` with the step's source moments and forward Euler
+    uses ``s`` at the start of each step.
 
     Returns a dict with ``fluence`` (psi_0^0 after the last step),
     ``readings`` ``[steps][n_det]`` (psi_0^0 at the detector voxels after
@@ -342,6 +390,20 @@ def solve(n, N, dx, c, dt, mu_a, mu_s, g, psi0_real, q_real, W, mu0, mu1,
         return operator(y, Sig, q, B, k, c, workers)
 
     stepper = euler_step if scheme == "euler" else rk4_step
+    if q_profile is not None:
+        s_of_t = source_profile(*q_profile)
+        knots = q_profile[1] * np.arange(len(q_profile[0]))
+        cq = c * q if q is not None else np.zeros_like(psi)
+
+        def lin(y):
+            return operator(y, Sig, None, B, k, c, workers)
+
+        def stepper(y, _f, h, step=[0]):
+            t0 = step[0] * h
+            step[0] += 1
+            if scheme == "euler":
+                return y + h * (lin(y) + s_of_t(t0) * cq)
+            return rk4_source_step(y, lin, cq, h, source_moments(s_of_t, t0, h, knots))
     for s in range(steps):
         psi = stepper(psi, f, dt)
         phi = psi[0].real
