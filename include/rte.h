@@ -175,6 +175,29 @@ int rte_forward_checkpointed(rte_handle* h, int64_t steps, int64_t every, void* 
 int rte_adjoint(rte_handle* h, int64_t steps, int64_t every, void* adj_ws, size_t adj_bytes,
                 const double* dj_dr, double* grad_mu_a, double* grad_mu_s);
 
+/* ---- Time-dependent sources ------------------------------------------
+ * Eq. (4) lets the source depend on time. rte_set_source_profile makes the
+ * handle's source q(r) s(t): s is linear between samples[i] at
+ * t = i * delta_ps (t from step 0, i.e. creation or the last
+ * rte_set_state) and keeps its last value after the last sample.
+ * The library turns s into per-step source weights for `rows` steps and
+ * copies them (FP64) into dev_table, a caller-owned device buffer of at
+ * least rows * 4 * 8 bytes (RK4) or rows * 8 bytes (Euler), 8-byte aligned,
+ * that must stay allocated while the profile is set. Steps at or past
+ * `rows` use the last row. RK4 step r gives its four nested stages
+ * (coefficients 1/4, 1/3, 1/2, 1) the weights
+ * (j + 1) / h^(j + 1) int_0^h (h - tau)^j s(t_r + tau) dtau, j = 3, 2, 1, 0,
+ * which makes the step reproduce the source integral of the
+ * variation-of-constants formula through the L^3 term (fourth order for any
+ * s; exact moments for the piecewise-linear s); Euler step r uses s(t_r).
+ * samples = NULL or rows = 0 returns to a constant source. A profile is
+ * refused by rte_steady_gmres and rte_expo_advance (RTE_EINVAL); the adjoint
+ * uses it (the checkpointed run is taken to end at the current step).
+ * RTE_EINVAL for non-finite samples or delta_ps <= 0, RTE_ENOMEM for a
+ * missing, small or misaligned table. Synchronises. */
+int rte_set_source_profile(rte_handle* h, const double* samples, int64_t nsamples, double delta_ps,
+                           int64_t rows, void* dev_table, size_t table_bytes);
+
 /* ---- Steady state by a Krylov solve ---------------------------------
  * Instead of marching to steady state, solve for it with a Krylov method
  * (Sec. II.A: the time-integrated form gives an operator whose steady state

@@ -103,6 +103,12 @@ struct Ctl {
   double growth_limit;  // ||phi||^2 above this flags runaway growth
   double last_resid;
   double last_norm2;
+  // time profile of the source: per-step stage weights [qw_rows][qw_cols]
+  // (null: constant source, weight 1); steps past the table use its last row
+  const double* qw;
+  long long qw_rows;
+  int qw_cols;
+  int pad2;
 };
 
 // Everything one RK4 step needs, as plain device pointers (carved from the
@@ -186,6 +192,8 @@ struct OpArgs {
   double scale;      // OP_COMBINE; OP_EXPO: per-substep norm limit theta
   double eps;        // OP_EXPO: Taylor truncation target
   double sigl[kMaxOrder + 1];  // OP_EXPO: per-degree loss of the medium
+  long long step1;   // OP_STEP / OP_STAGE: 1 + the step index whose source
+                     // weights apply (0: the control block's step counter)
 };
 
 // Per-grid-size entry points (one translation unit per n). enqueue_op

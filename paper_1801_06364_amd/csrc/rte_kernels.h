@@ -476,7 +476,7 @@ enum { EPI_MID = 0, EPI_FIRST = 1, EPI_LAST = 2, EPI_ADJ = 3, EPI_EULER = 4, EPI
 template <typename V, typename T, int NN, int RB, int LP, int BLOCK, int MODE>
 __device__ __forceinline__ void epilogue(const V* pl, int y0, int b, int z, const T* vin, T* u,
                                          T* dst, const T* __restrict__ sig, const T* __restrict__ q,
-                                         bool hasq, double* __restrict__ phi_int, T h, double dt,
+                                         bool hasq, T qs, double* __restrict__ phi_int, T h, double dt,
                                          double& acc_d, double& acc_o) {
   constexpr int n = NN, H = NN / 2;
   const int l = isqrt_c(b);
@@ -498,8 +498,8 @@ __device__ __forceinline__ void epilogue(const V* pl, int y0, int b, int z, cons
     T src0 = -ss.x * vv.x, src1 = -ss.y * vv.y;
     if (MODE != EPI_ADJ && hasq) {
       const V qq = *reinterpret_cast<const V*>(q + poff + e);
-      src0 += qq.x;
-      src1 += qq.y;
+      src0 += qs * qq.x;
+      src1 += qs * qq.y;
     }
     if constexpr (MODE == EPI_APPLY) {
       *reinterpret_cast<V*>(dst + poff + e) = cmk<V>(-w.x + ss.x * vv.x, -w.y + ss.y * vv.y);
@@ -547,13 +547,23 @@ __device__ __forceinline__ void block_sum2(unsigned char* smem, double a, double
   }
 }
 
+// Weight of the source in stage `stage` of a step: 1 for a constant source,
+// else the step's row of the profile table (step1 - 1 if given, else the
+// control block's step counter; past the table, its last row).
+__device__ __forceinline__ double source_weight(const Ctl* __restrict__ ctl, int stage, long long step1) {
+  if (ctl->qw == nullptr) return 1.0;
+  long long r = step1 > 0 ? step1 - 1 : ctl->step;
+  if (r >= ctl->qw_rows) r = ctl->qw_rows - 1;
+  return ctl->qw[r * ctl->qw_cols + stage];
+}
+
 template <typename T, int NN, int MODE>
 __global__ void __launch_bounds__(kPBlock)
 k_inv_plane(const typename cplx_of<T>::type* __restrict__ spec, const T* vin, T* u, T* dst,
             const T* __restrict__ sig, const T* __restrict__ q, const int* __restrict__ qflag,
             double* __restrict__ phi_int, double* __restrict__ partial,
             const typename cplx_of<T>::type* __restrict__ twg, int M, T h, double dt,
-            const Ctl* __restrict__ ctl) {
+            const Ctl* __restrict__ ctl, int stage, long long step1) {
   using V = typename cplx_of<T>::type;
   using G = GridC<NN>;
   constexpr int n = NN, H = G::H, LP = H + 1;
@@ -579,7 +589,8 @@ k_inv_plane(const typename cplx_of<T>::type* __restrict__ spec, const T* vin, T*
   __syncthreads();
   double acc_d = 0.0, acc_o = 0.0;
   const bool hasq = (q != nullptr) && qflag[z];
-  epilogue<V, T, NN, n, LP, kPBlock, MODE>(pl, 0, b, z, vin, u, dst, sig, q, hasq, phi_int, h, dt, acc_d,
+  const T qs = hasq ? T(source_weight(ctl, stage, step1)) : T(0);
+  epilogue<V, T, NN, n, LP, kPBlock, MODE>(pl, 0, b, z, vin, u, dst, sig, q, hasq, qs, phi_int, h, dt, acc_d,
                                            acc_o);
   if ((MODE == EPI_LAST || MODE == EPI_EULER) && b == 0) block_sum2<kPBlock>(smem, acc_d, acc_o, partial + 2 * z);
 }
@@ -594,7 +605,7 @@ k_rows_inv(const typename cplx_of<T>::type* __restrict__ spec, const T* vin, T* 
            const T* __restrict__ sig, const T* __restrict__ q, const int* __restrict__ qflag,
            double* __restrict__ phi_int, double* __restrict__ partial,
            const typename cplx_of<T>::type* __restrict__ twg, int M, T h, double dt,
-           const Ctl* __restrict__ ctl) {
+           const Ctl* __restrict__ ctl, int stage, long long step1) {
   using V = typename cplx_of<T>::type;
   constexpr int n = NN, H = NN / 2, LP = H + 1, RB = RowShape<NN>::RB, NB = NN / RB;
   if (ctl->stop) return;
@@ -616,7 +627,8 @@ k_rows_inv(const typename cplx_of<T>::type* __restrict__ spec, const T* vin, T* 
   __syncthreads();
   double acc_d = 0.0, acc_o = 0.0;
   const bool hasq = (q != nullptr) && qflag[z];
-  epilogue<V, T, NN, RB, LP, kZBlock, MODE>(pl, y0, b, z, vin, u, dst, sig, q, hasq, phi_int, h, dt, acc_d,
+  const T qs = hasq ? T(source_weight(ctl, stage, step1)) : T(0);
+  epilogue<V, T, NN, RB, LP, kZBlock, MODE>(pl, y0, b, z, vin, u, dst, sig, q, hasq, qs, phi_int, h, dt, acc_d,
                                             acc_o);
   if ((MODE == EPI_LAST || MODE == EPI_EULER) && b == 0) block_sum2<kZBlock>(smem, acc_d, acc_o, partial + 2 * zy);
 }
@@ -981,7 +993,8 @@ template <int NN> constexpr int partial_count() {
 // One stage: out = MODE-epilogue of (u, src) with the streaming term
 // sgn * a h c (-B.grad src) (sgn = -1 gives the transposed streaming).
 template <typename T, int NN, int N, int MODE>
-void enqueue_stage(const StepArgs& a, ProfRec* pr, double hs, double sgn, const T* src, T* u, T* out) {
+void enqueue_stage(const StepArgs& a, ProfRec* pr, double hs, double sgn, const T* src, T* u, T* out,
+                   int stage = 0, long long step1 = 0) {
   using V = typename cplx_of<T>::type;
   using Z = ZdShape<T, NN>;
   constexpr int M = (N + 1) * (N + 1);
@@ -1033,11 +1046,11 @@ void enqueue_stage(const StepArgs& a, ProfRec* pr, double hs, double sgn, const 
                        cctl);
     rec(PROF_Y_INV);
     hipLaunchKernelGGL((k_rows_inv<T, NN, MODE>), dim3(rblocks), zblk, lr, st, coupled, src, u, out, sig, q,
-                       a.qflag, a.phi_int, a.partial, tw, M, T(hs), a.dt, cctl);
+                       a.qflag, a.phi_int, a.partial, tw, M, T(hs), a.dt, cctl, stage, step1);
     rec(PROF_INV_ROWS);
   } else {
     hipLaunchKernelGGL((k_inv_plane<T, NN, MODE>), dim3(planes), pblk, lp, st, coupled, src, u, out, sig, q,
-                       a.qflag, a.phi_int, a.partial, tw, M, T(hs), a.dt, cctl);
+                       a.qflag, a.phi_int, a.partial, tw, M, T(hs), a.dt, cctl, stage, step1);
     rec(PROF_INV_PLANE);
   }
 }
@@ -1111,11 +1124,13 @@ hipError_t enqueue_expo(const StepArgs& a, const OpArgs& op, ProfRec* pr) {
     hipLaunchKernelGGL((k_pencil<T, NN, PENCIL_YINV>), dim3(pencils), zblk, lz, st, spec, spec, tw, kv, cctl);
     rec(PROF_Y_INV);
     hipLaunchKernelGGL((k_rows_inv<T, NN, EPI_SET>), dim3(rblocks), zblk, lr, st, spec, u, u, u, sig,
-                       static_cast<const T*>(nullptr), a.qflag, a.phi_int, a.partial, tw, M, T(0), 0.0, cctl);
+                       static_cast<const T*>(nullptr), a.qflag, a.phi_int, a.partial, tw, M, T(0), 0.0, cctl, 0,
+                       0LL);
     rec(PROF_INV_ROWS);
   } else {
     hipLaunchKernelGGL((k_inv_plane<T, NN, EPI_SET>), dim3(planes), pblk, lp, st, spec, u, u, u, sig,
-                       static_cast<const T*>(nullptr), a.qflag, a.phi_int, a.partial, tw, M, T(0), 0.0, cctl);
+                       static_cast<const T*>(nullptr), a.qflag, a.phi_int, a.partial, tw, M, T(0), 0.0, cctl, 0,
+                       0LL);
     rec(PROF_INV_PLANE);
   }
   return hipGetLastError();
@@ -1137,14 +1152,15 @@ hipError_t enqueue_t(const StepArgs& a, const OpArgs& op, ProfRec* pr) {
         (void)hipEventRecord(static_cast<hipEvent_t>(pr->ev0), st);
         pr->count = 0;
       }
+      const long long s1 = op.step1;
       if (a.scheme == 1) {
         // forward Euler (eq. 11 with the sign reading): u <- u + dt f(u)
-        enqueue_stage<T, NN, N, EPI_EULER>(a, pr, hc, 1.0, u, u, u);
+        enqueue_stage<T, NN, N, EPI_EULER>(a, pr, hc, 1.0, u, u, u, 0, s1);
       } else {
-        enqueue_stage<T, NN, N, EPI_FIRST>(a, pr, kRkAlpha[0] * hc, 1.0, u, u, v);
-        enqueue_stage<T, NN, N, EPI_MID>(a, pr, kRkAlpha[1] * hc, 1.0, v, u, v);
-        enqueue_stage<T, NN, N, EPI_MID>(a, pr, kRkAlpha[2] * hc, 1.0, v, u, v);
-        enqueue_stage<T, NN, N, EPI_LAST>(a, pr, kRkAlpha[3] * hc, 1.0, v, u, u);
+        enqueue_stage<T, NN, N, EPI_FIRST>(a, pr, kRkAlpha[0] * hc, 1.0, u, u, v, 0, s1);
+        enqueue_stage<T, NN, N, EPI_MID>(a, pr, kRkAlpha[1] * hc, 1.0, v, u, v, 1, s1);
+        enqueue_stage<T, NN, N, EPI_MID>(a, pr, kRkAlpha[2] * hc, 1.0, v, u, v, 2, s1);
+        enqueue_stage<T, NN, N, EPI_LAST>(a, pr, kRkAlpha[3] * hc, 1.0, v, u, u, 3, s1);
       }
       hipLaunchKernelGGL((k_end_step<T>), dim3(1), dim3(kBlock), 0, st, u, a.det, a.ndet, a.readings, a.resid,
                          a.cap, a.partial, partial_count<NN>(), static_cast<Ctl*>(a.ctl));
@@ -1161,8 +1177,8 @@ hipError_t enqueue_t(const StepArgs& a, const OpArgs& op, ProfRec* pr) {
       const T* xin = static_cast<const T*>(op.x);
       T* u = static_cast<T*>(op.u);
       T* out = static_cast<T*>(op.y);
-      if (s == 0) enqueue_stage<T, NN, N, EPI_FIRST>(a, nullptr, kRkAlpha[0] * hc, 1.0, u, u, out);
-      else enqueue_stage<T, NN, N, EPI_MID>(a, nullptr, kRkAlpha[s] * hc, 1.0, xin, u, out);
+      if (s == 0) enqueue_stage<T, NN, N, EPI_FIRST>(a, nullptr, kRkAlpha[0] * hc, 1.0, u, u, out, 0, op.step1);
+      else enqueue_stage<T, NN, N, EPI_MID>(a, nullptr, kRkAlpha[s] * hc, 1.0, xin, u, out, s, op.step1);
       break;
     }
     case OP_ADJ_STAGE: {

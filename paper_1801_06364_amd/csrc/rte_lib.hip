@@ -135,6 +135,9 @@ struct rte_handle {
   hipGraphExec_t exec;
   bool graph_ready;
   bool use_graph;
+  const double* qw;                 // source time profile (device, caller-owned) or null
+  long long qw_rows;
+  int qw_cols;
   bool homogeneous;                 // constant maps, no boundary layer
   double sigl[rte::kMaxOrder + 1];  // per-degree loss (homogeneous media)
   template <typename P> P* at(size_t off) const { return reinterpret_cast<P*>(ws + off); }
@@ -194,6 +197,9 @@ int write_ctl(rte_handle* h, const Ctl* c) {
 int reset_run_state(rte_handle* h, double growth_limit) {
   Ctl c{};
   c.growth_limit = growth_limit;
+  c.qw = h->qw;
+  c.qw_rows = h->qw_rows;
+  c.qw_cols = h->qw_cols;
   int rc = write_ctl(h, &c);
   if (rc) return rc;
   hipError_t e = hipMemsetAsync(h->ws + h->lay.phi_int, 0, size_t(h->n) * h->n * h->n * 8, h->stream);
@@ -383,6 +389,9 @@ int rte_create(const rte_config* cfg, const rte_medium* med, void* dev_ws, size_
   h->ws = reinterpret_cast<unsigned char*>(dev_ws);
   h->lay = L;
   h->graph_ready = false;
+  h->qw = nullptr;
+  h->qw_rows = 0;
+  h->qw_cols = 0;
   h->homogeneous = cfg->pml_width == 0;
   for (size_t i = 1; i < V && h->homogeneous; ++i)
     h->homogeneous = med->mu_a[i] == med->mu_a[0] && med->mu_s[i] == med->mu_s[0] && med->g[i] == med->g[0];
@@ -536,6 +545,98 @@ int rte_set_state(rte_handle* h, const double* in, size_t len) {
   return rte::reset_run_state(h, c.growth_limit);
 }
 
+namespace {
+// Profile s(t): linear between samples[i] at t = i * delta, last value after.
+double profile_at(const double* sm, int64_t ns, double delta, double t) {
+  if (t <= 0.0 || ns == 1) return sm[0];
+  const double x = t / delta;
+  const int64_t i = int64_t(std::floor(x));
+  if (i >= ns - 1) return sm[ns - 1];
+  const double f = x - double(i);
+  return sm[i] + f * (sm[i + 1] - sm[i]);
+}
+
+// int_0^h (h - tau)^j s(t0 + tau) dtau, j = 0..3: the step is split at the
+// sample knots, where s is linear, and each piece integrated by 3-point
+// Gauss-Legendre (exact for the polynomial degree <= 4 of the integrand).
+void profile_moments(const double* sm, int64_t ns, double delta, double t0, double h, double out[4]) {
+  static const double gx[3] = {-0.7745966692414834, 0.0, 0.7745966692414834};
+  static const double gw[3] = {5.0 / 9.0, 8.0 / 9.0, 5.0 / 9.0};
+  for (int j = 0; j < 4; ++j) out[j] = 0.0;
+  double a = 0.0;
+  while (a < h) {
+    // next knot after t0 + a (or the end of the step); a knot within
+    // rounding of a counts as passed
+    double k = std::floor((t0 + a) / delta) + 1.0;
+    double tk = k * delta - t0;
+    while (tk <= a + 1e-12 * h) {
+      k += 1.0;
+      tk = k * delta - t0;
+    }
+    const double b = tk < h ? tk : h;
+    const double mid = 0.5 * (a + b), half = 0.5 * (b - a);
+    for (int g = 0; g < 3; ++g) {
+      const double tau = mid + half * gx[g];
+      const double sv = profile_at(sm, ns, delta, t0 + tau) * gw[g] * half;
+      double p = 1.0;
+      for (int j = 0; j < 4; ++j) {
+        out[j] += p * sv;
+        p *= (h - tau);
+      }
+    }
+    a = b;
+  }
+}
+}  // namespace
+
+int rte_set_source_profile(rte_handle* h, const double* samples, int64_t nsamples, double delta_ps,
+                           int64_t rows, void* dev_table, size_t table_bytes) {
+  using namespace rte;
+  if (!h) return RTE_EINVAL;
+  const int cols = h->cfg.scheme == RTE_EULER ? 1 : 4;
+  if (samples == nullptr || rows == 0) {
+    h->qw = nullptr;
+    h->qw_rows = 0;
+    h->qw_cols = 0;
+  } else {
+    if (nsamples < 1 || rows < 0 || !(delta_ps > 0) || !std::isfinite(delta_ps)) return RTE_EINVAL;
+    for (int64_t i = 0; i < nsamples; ++i)
+      if (!std::isfinite(samples[i])) return RTE_EINVAL;
+    const size_t need = size_t(rows) * cols * 8;
+    if (!dev_table || (reinterpret_cast<uintptr_t>(dev_table) % 8) != 0 || table_bytes < need) return RTE_ENOMEM;
+    std::vector<double> w(size_t(rows) * cols);
+    const double dt = h->dt;
+    for (int64_t r = 0; r < rows; ++r) {
+      const double t0 = double(r) * dt;
+      if (cols == 1) {
+        w[size_t(r)] = profile_at(samples, nsamples, delta_ps, t0);
+        continue;
+      }
+      double m[4];
+      profile_moments(samples, nsamples, delta_ps, t0, dt, m);
+      // stage k of the nested step (coefficients 1/4, 1/3, 1/2, 1) carries
+      // (j + 1) / h^(j + 1) int (h - tau)^j s, j = 3 - k
+      for (int k = 0; k < 4; ++k) {
+        const int j = 3 - k;
+        w[size_t(r) * 4 + k] = double(j + 1) * m[j] / std::pow(dt, j + 1);
+      }
+    }
+    hipError_t e = hipMemcpyAsync(dev_table, w.data(), need, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return RTE_EDEVICE;
+    h->qw = static_cast<const double*>(dev_table);
+    h->qw_rows = rows;
+    h->qw_cols = cols;
+  }
+  Ctl c;
+  int rc = read_ctl(h, &c);
+  if (rc) return rc;
+  c.qw = h->qw;
+  c.qw_rows = h->qw_rows;
+  c.qw_cols = h->qw_cols;
+  return write_ctl(h, &c);
+}
+
 int rte_coupling_dense(int32_t order_N, double* bx, double* by, double* bz) {
   if (!bx || !by || !bz) return RTE_EINVAL;
   std::vector<double> X, Y, Z;
@@ -593,8 +694,18 @@ int rte_adjoint(rte_handle* h, int64_t steps, int64_t every, void* adj_ws, size_
   ok(hipMemsetAsync(w + A.gmua, 0, V * 8, st));
   ok(hipMemsetAsync(w + A.gmus, 0, V * 8, st));
   ok(hipMemsetAsync(w + A.lam, 0, F, st));
+  Ctl hc{};
+  {
+    const int rc = read_ctl(h, &hc);
+    if (rc) return rc;
+  }
+  // the checkpointed run ended at the handle's current step
+  const long long s0 = hc.step - steps;
   Ctl c0{};
   c0.growth_limit = 1e300;
+  c0.qw = h->qw;
+  c0.qw_rows = h->qw_rows;
+  c0.qw_cols = h->qw_cols;
   ok(hipMemcpyAsync(w + A.ctl, &c0, sizeof(Ctl), hipMemcpyHostToDevice, st));
   ok(hipStreamSynchronize(st));
   if (e != hipSuccess) return RTE_EDEVICE;
@@ -641,10 +752,11 @@ int rte_adjoint(rte_handle* h, int64_t steps, int64_t every, void* adj_ws, size_
     o.coef = coef;
     op(R, o);
   };
-  auto fwd_stage = [&](int s, const void* un, const void* x, void* y) {
+  auto fwd_stage = [&](int s, int64_t nn, const void* un, const void* x, void* y) {
     OpArgs o{};
     o.kind = OP_STAGE;
     o.stage = s;
+    o.step1 = s0 + nn + 1;
     o.u = const_cast<void*>(un);
     o.x = x;
     o.y = y;
@@ -664,6 +776,7 @@ int rte_adjoint(rte_handle* h, int64_t steps, int64_t every, void* adj_ws, size_
       S.u = next;
       OpArgs o{};
       o.kind = OP_STEP;
+      o.step1 = s0 + nn + 1;
       op(S, o);
     }
     for (int64_t nn = n1 - 1; nn >= n0 && e == hipSuccess; --nn) {
@@ -675,9 +788,9 @@ int rte_adjoint(rte_handle* h, int64_t steps, int64_t every, void* adj_ws, size_
         if (nn >= 1) inject(nn - 1);
         continue;
       }
-      fwd_stage(0, un, un, w + A.v1);
-      fwd_stage(1, un, w + A.v1, w + A.v2);
-      fwd_stage(2, un, w + A.v2, w + A.v3);
+      fwd_stage(0, nn, un, un, w + A.v1);
+      fwd_stage(1, nn, un, w + A.v1, w + A.v2);
+      fwd_stage(2, nn, un, w + A.v2, w + A.v3);
       // transposed nested stages (coefficients 1, 1/2, 1/3, 1/4), each
       // preceded by the gradient term of its forward counterpart
       grad(w + A.lam, w + A.v3, 1.0);
@@ -713,6 +826,7 @@ int rte_steady_gmres(rte_handle* h, int32_t restart, int64_t max_iters, double t
   using namespace rte;
   if (!h || restart < 1 || restart + 1 > kMaxBasisVectors || max_iters < 1 || !(tol > 0) || steps_per_apply < 0)
     return RTE_EINVAL;
+  if (h->qw) return RTE_EINVAL;   // a steady state needs a constant source
   const size_t need = rte_krylov_workspace_bytes(&h->cfg, restart);
   if (!kws || (reinterpret_cast<uintptr_t>(kws) % kAlign) != 0 || kbytes < need) return RTE_ENOMEM;
   {
@@ -919,7 +1033,7 @@ namespace {
 int expo_run(rte_handle* h, double t_ps, rte::ProfRec* pr) {
   using namespace rte;
   if (!h || !std::isfinite(t_ps) || t_ps < 0) return RTE_EINVAL;
-  if (!h->homogeneous || h->N > kDenseOrder) return RTE_EINVAL;
+  if (!h->homogeneous || h->N > kDenseOrder || h->qw) return RTE_EINVAL;
   if (t_ps == 0) return RTE_OK;
   const bool f64 = h->prec == RTE_FP64;
   const double eps = f64 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24);

@@ -27,7 +27,7 @@ EXPORTS = (
     "rte_set_state", "rte_coupling_dense", "rte_profile_kernels", "rte_destroy",
     "rte_strerror", "rte_adjoint_workspace_bytes", "rte_forward_checkpointed",
     "rte_adjoint", "rte_krylov_workspace_bytes", "rte_steady_gmres", "rte_expo_advance",
-    "rte_profile_expo",
+    "rte_profile_expo", "rte_set_source_profile",
 )
 KERNEL_CLASSES = ("fwd_plane", "zderiv", "couple", "inv_plane", "end_step",
                   "fwd_rows", "y_fwd", "y_inv", "inv_rows", "z_fwd", "expo", "z_inv")
@@ -109,6 +109,8 @@ def lib():
         L.rte_steady_gmres.restype = C.c_int
         L.rte_expo_advance.argtypes = [vp, C.c_double]
         L.rte_expo_advance.restype = C.c_int
+        L.rte_set_source_profile.argtypes = [vp, dp, C.c_int64, C.c_double, C.c_int64, vp, C.c_size_t]
+        L.rte_set_source_profile.restype = C.c_int
         L.rte_profile_expo.argtypes = [vp, C.c_double, dp, C.POINTER(C.c_int64)]
         L.rte_profile_expo.restype = C.c_int
         L.rte_destroy.argtypes = [vp]
@@ -254,6 +256,25 @@ class Solver:
     def set_state(self, psi: np.ndarray):
         a = _f64(psi).ravel()
         _check(lib().rte_set_state(self.h, _dptr(a), a.size), "rte_set_state")
+
+    # -- time-dependent source ---------------------------------------------
+    def set_source_profile(self, samples, delta_ps: float, rows: int):
+        """Source q(r) s(t), s linear between samples spaced delta_ps apart
+        (t from step 0); the library tabulates per-step weights for `rows`
+        steps into a device table owned by this solver. samples=None
+        returns to a constant source."""
+        import torch
+        if samples is None:
+            _check(lib().rte_set_source_profile(self.h, None, 0, 1.0, 0, None, 0), "rte_set_source_profile")
+            self._qw = None
+            return
+        sm = _f64(samples).ravel()
+        cols = 1 if self.cfg.scheme == RTE_EULER else 4
+        table = torch.empty(max(1, int(rows)) * cols, dtype=torch.float64, device=self.workspace.device)
+        _check(lib().rte_set_source_profile(self.h, _dptr(sm), sm.size, float(delta_ps), int(rows),
+                                            C.c_void_p(table.data_ptr()), table.numel() * 8),
+               "rte_set_source_profile")
+        self._qw = table
 
     # -- exact propagation (homogeneous media) -----------------------------
     def expo_advance(self, t_ps: float):
