@@ -55,10 +55,13 @@ def algorithmic_bytes(kind: str, n: int, M: int, N: int, s: int) -> float:
     fwd_plane: read the stage input, write the spectrum.
     zderiv: read the spectrum, write its z derivative.
     couple: read the spectrum and the derivative, write the coupled spectrum.
-    inv_plane: read the coupled spectrum, the stage input, u and the
-    per-degree loss maps ((N+1) n^3), write the stage output; averaged over
-    the four RK stages (the first stage reads u once, the last one also
-    updates the FP64 integrated fluence, 16 bytes per voxel).
+    inv_plane (grids up to 128, fused with the next stage's forward
+    transform): read the coupled spectrum, the stage input, u and the
+    per-degree loss maps ((N+1) n^3), write the stage output and its xy
+    spectrum; averaged over the four RK stages (the first stage reads u
+    once, the last one also updates the FP64 integrated fluence, 16 bytes
+    per voxel).
+    inv_rows (larger grids, not fused): the same without the spectrum write.
     """
     F = M * n ** 3 * s
     if kind == "fwd_plane":
@@ -67,7 +70,9 @@ def algorithmic_bytes(kind: str, n: int, M: int, N: int, s: int) -> float:
         return 2 * F
     if kind == "couple":
         return 3 * F
-    if kind in ("inv_plane", "inv_rows"):
+    if kind == "inv_plane":
+        return 4.75 * F + (N + 1) * n ** 3 * s + 16 * n ** 3 / 4
+    if kind == "inv_rows":
         return 3.75 * F + (N + 1) * n ** 3 * s + 16 * n ** 3 / 4
     if kind in ("fwd_rows", "y_fwd", "y_inv"):
         return 2 * F

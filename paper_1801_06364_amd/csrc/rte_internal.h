@@ -174,7 +174,8 @@ enum {
   OP_SCALE = 8,      // y = x / djdr[0]
   OP_RHS_MINUS = 9,  // y = x - y (x may be null)
   OP_EXPO = 10,      // u <- exact propagation over time coef (homogeneous medium)
-  OP_PSTEP = 11      // u <- one time step of u (y: stage scratch), no bookkeeping
+  OP_PSTEP = 11,     // u <- one time step of u (y: stage scratch), no bookkeeping
+  OP_FWD = 12        // spectrum of u (the entry condition of a fused OP_STEP)
 };
 struct OpArgs {
   int kind;
@@ -192,6 +193,8 @@ struct OpArgs {
   double scale;      // OP_COMBINE; OP_EXPO: per-substep norm limit theta
   double eps;        // OP_EXPO: Taylor truncation target
   double sigl[kMaxOrder + 1];  // OP_EXPO: per-degree loss of the medium
+  int fused;         // OP_STEP: the spectrum of u is in place on entry and is
+                     // left in place for the next step (plane grids)
   long long step1;   // OP_STEP / OP_STAGE: 1 + the step index whose source
                      // weights apply (0: the control block's step counter)
 };

@@ -84,6 +84,45 @@ constexpr size_t plane_lds() {
 // later operator treats them alike and they travel packed as one complex
 // column kx = 0 holding (X_0, X_{n/2}). The half spectrum is therefore
 // exactly n/2 columns wide: [b][z][ky][kx], kx in [0, n/2).
+// Forward transform of one real plane held in LDS as n rows of H packed
+// complex values (pitch LP = H + 1): x real-to-complex FFT with the
+// kx = 0 / n/2 packing, then y FFT of the H columns. Callers synchronise
+// before (plane written) and read the spectrum after (ends synchronised).
+template <typename V, typename T, int NN, int BLOCK>
+__device__ __forceinline__ void forward_plane_lds(V* pl, const V* tw) {
+  constexpr int n = NN, H = NN / 2, LP = H + 1;
+  // x: n packed rows of length H (twiddle table of length n, stride 2)
+  fft_batch<V, H, 1, 2 * H, -1, n, BLOCK>(tw, [&](int f) { return pl + f * LP; });
+  __syncthreads();
+  // real-to-complex split: X_k from Z_k and Z_{H-k}
+  constexpr int half = H / 2;
+  for (int i = threadIdx.x; i < n * (half + 1); i += BLOCK) {
+    const int y = i / (half + 1), kk = i - y * (half + 1);
+    V* row = pl + y * LP;
+    if (kk == 0) {
+      const V z0 = row[0];
+      row[0] = cmk<V>(z0.x + z0.y, z0.x - z0.y);   // packed (X_0, X_{n/2})
+    } else {
+      const int m = H - kk;
+      const V zk = row[kk], zm = row[m];
+      const V zmc = cconj(zm), zkc = cconj(zk);
+      // X_k = (Z_k + conj Z_m)/2 - i w_k (Z_k - conj Z_m)/2,  w_k = exp(-2 pi i k / n)
+      const V ek = cscale(cadd(zk, zmc), T(0.5));
+      const V ok = cmul_i<V, -1>(cscale(csub(zk, zmc), T(0.5)));
+      row[kk] = cadd(ek, cmul(tw[kk], ok));
+      if (m != kk) {
+        const V em = cscale(cadd(zm, zkc), T(0.5));
+        const V om = cmul_i<V, -1>(cscale(csub(zm, zkc), T(0.5)));
+        row[m] = cadd(em, cmul(tw[m], om));
+      }
+    }
+  }
+  __syncthreads();
+  // y: H columns of length n, stride LP
+  fft_batch<V, n, LP, n, -1, H, BLOCK>(tw, [&](int f) { return pl + f; });
+  __syncthreads();
+}
+
 template <typename T, int NN>
 __global__ void __launch_bounds__(kPBlock)
 k_fwd_plane(const T* __restrict__ src, typename cplx_of<T>::type* __restrict__ spec,
@@ -122,36 +161,7 @@ k_fwd_plane(const T* __restrict__ src, typename cplx_of<T>::type* __restrict__ s
     }
     __syncthreads();
     if (k + 1 < kFwdPlanes && plane + 1 < nplanes) gload(plane + 1);
-    // x: n packed rows of length H (twiddle table of length n, stride 2)
-    fft_batch<V, H, 1, 2 * H, -1, n, kPBlock>(tw, [&](int f) { return pl + f * LP; });
-    __syncthreads();
-    // real-to-complex split: X_k from Z_k and Z_{H-k}
-    constexpr int half = H / 2;
-    for (int i = threadIdx.x; i < n * (half + 1); i += kPBlock) {
-      const int y = i / (half + 1), kk = i - y * (half + 1);
-      V* row = pl + y * LP;
-      if (kk == 0) {
-        const V z0 = row[0];
-        row[0] = cmk<V>(z0.x + z0.y, z0.x - z0.y);   // packed (X_0, X_{n/2})
-      } else {
-        const int m = H - kk;
-        const V zk = row[kk], zm = row[m];
-        const V zmc = cconj(zm), zkc = cconj(zk);
-        // X_k = (Z_k + conj Z_m)/2 - i w_k (Z_k - conj Z_m)/2,  w_k = exp(-2 pi i k / n)
-        const V ek = cscale(cadd(zk, zmc), T(0.5));
-        const V ok = cmul_i<V, -1>(cscale(csub(zk, zmc), T(0.5)));
-        row[kk] = cadd(ek, cmul(tw[kk], ok));
-        if (m != kk) {
-          const V em = cscale(cadd(zm, zkc), T(0.5));
-          const V om = cmul_i<V, -1>(cscale(csub(zm, zkc), T(0.5)));
-          row[m] = cadd(em, cmul(tw[m], om));
-        }
-      }
-    }
-    __syncthreads();
-    // y: H columns of length n, stride LP
-    fft_batch<V, n, LP, n, -1, H, kPBlock>(tw, [&](int f) { return pl + f; });
-    __syncthreads();
+    forward_plane_lds<V, T, NN, kPBlock>(pl, tw);
     V* dst = spec + size_t(plane) * n * H;
     staged_copy<n * H, kPBlock>([&](int i) { return pl[(i / H) * LP + (i % H)]; },
                                 [&](int i, V x) { dst[i] = x; });
@@ -473,8 +483,8 @@ enum { EPI_MID = 0, EPI_FIRST = 1, EPI_LAST = 2, EPI_ADJ = 3, EPI_EULER = 4, EPI
 //     steady-state operator A v = (S + Sigma) v, for which the steady state
 //     solves A u = q;
 //   EPI_SET         o = w -> dst (the transformed field itself).
-template <typename V, typename T, int NN, int RB, int LP, int BLOCK, int MODE>
-__device__ __forceinline__ void epilogue(const V* pl, int y0, int b, int z, const T* vin, T* u,
+template <typename V, typename T, int NN, int RB, int LP, int BLOCK, int MODE, bool KEEP = false>
+__device__ __forceinline__ void epilogue(V* pl, int y0, int b, int z, const T* vin, T* u,
                                          T* dst, const T* __restrict__ sig, const T* __restrict__ q,
                                          bool hasq, T qs, double* __restrict__ phi_int, T h, double dt,
                                          double& acc_d, double& acc_o) {
@@ -513,6 +523,7 @@ __device__ __forceinline__ void epilogue(const V* pl, int y0, int b, int z, cons
     }
     const V o = cmk<V>(uu.x + w.x + h * src0, uu.y + w.y + h * src1);
     *reinterpret_cast<V*>(dst + poff + e) = o;
+    if constexpr (KEEP) pl[y * LP + j] = o;   // the output plane, for the fused forward transform
     if ((MODE == EPI_LAST || MODE == EPI_EULER) && b == 0) {
       double2* pi = reinterpret_cast<double2*>(phi_int + voff + e);
       double2 acc = *pi;
@@ -557,13 +568,17 @@ __device__ __forceinline__ double source_weight(const Ctl* __restrict__ ctl, int
   return ctl->qw[r * ctl->qw_cols + stage];
 }
 
-template <typename T, int NN, int MODE>
+// FUSE: the stage output plane, still in LDS, is transformed forward at
+// once (x r2c + y FFT) and written as the next stage's xy spectrum to fspec
+// (which may be the spectrum just read: each workgroup owns its plane), so
+// the next stage needs no separate forward pass.
+template <typename T, int NN, int MODE, bool FUSE = false>
 __global__ void __launch_bounds__(kPBlock)
-k_inv_plane(const typename cplx_of<T>::type* __restrict__ spec, const T* vin, T* u, T* dst,
+k_inv_plane(const typename cplx_of<T>::type* spec, const T* vin, T* u, T* dst,
             const T* __restrict__ sig, const T* __restrict__ q, const int* __restrict__ qflag,
             double* __restrict__ phi_int, double* __restrict__ partial,
             const typename cplx_of<T>::type* __restrict__ twg, int M, T h, double dt,
-            const Ctl* __restrict__ ctl, int stage, long long step1) {
+            const Ctl* __restrict__ ctl, int stage, long long step1, typename cplx_of<T>::type* fspec) {
   using V = typename cplx_of<T>::type;
   using G = GridC<NN>;
   constexpr int n = NN, H = G::H, LP = H + 1;
@@ -590,8 +605,16 @@ k_inv_plane(const typename cplx_of<T>::type* __restrict__ spec, const T* vin, T*
   double acc_d = 0.0, acc_o = 0.0;
   const bool hasq = (q != nullptr) && qflag[z];
   const T qs = hasq ? T(source_weight(ctl, stage, step1)) : T(0);
-  epilogue<V, T, NN, n, LP, kPBlock, MODE>(pl, 0, b, z, vin, u, dst, sig, q, hasq, qs, phi_int, h, dt, acc_d,
-                                           acc_o);
+  epilogue<V, T, NN, n, LP, kPBlock, MODE, FUSE>(pl, 0, b, z, vin, u, dst, sig, q, hasq, qs, phi_int, h, dt,
+                                                 acc_d, acc_o);
+  if constexpr (FUSE) {
+    __syncthreads();
+    forward_plane_lds<V, T, NN, kPBlock>(pl, tw);
+    V* fd = fspec + size_t(plane) * n * H;
+    staged_copy<n * H, kPBlock>([&](int i) { return pl[(i / H) * LP + (i % H)]; },
+                                [&](int i, V x) { fd[i] = x; });
+  }
+  // (block_sum2 reuses the LDS: it synchronises first)
   if ((MODE == EPI_LAST || MODE == EPI_EULER) && b == 0) block_sum2<kPBlock>(smem, acc_d, acc_o, partial + 2 * z);
 }
 
@@ -977,6 +1000,10 @@ hipError_t prepare_t(const StepArgs& a) {
     set(reinterpret_cast<const void*>(&k_inv_plane<T, NN, EPI_EULER>), plane_lds<T, NN>());
     set(reinterpret_cast<const void*>(&k_inv_plane<T, NN, EPI_APPLY>), plane_lds<T, NN>());
     set(reinterpret_cast<const void*>(&k_inv_plane<T, NN, EPI_SET>), plane_lds<T, NN>());
+    set(reinterpret_cast<const void*>(&k_inv_plane<T, NN, EPI_FIRST, true>), plane_lds<T, NN>());
+    set(reinterpret_cast<const void*>(&k_inv_plane<T, NN, EPI_MID, true>), plane_lds<T, NN>());
+    set(reinterpret_cast<const void*>(&k_inv_plane<T, NN, EPI_LAST, true>), plane_lds<T, NN>());
+    set(reinterpret_cast<const void*>(&k_inv_plane<T, NN, EPI_EULER, true>), plane_lds<T, NN>());
   }
   set(reinterpret_cast<const void*>(&k_pencil<T, NN, PENCIL_ZDERIV>), zd_lds<T, NN>());
   set(reinterpret_cast<const void*>(&k_pencil<T, NN, PENCIL_ZFWD>), zd_lds<T, NN>());
@@ -992,9 +1019,10 @@ template <int NN> constexpr int partial_count() {
 
 // One stage: out = MODE-epilogue of (u, src) with the streaming term
 // sgn * a h c (-B.grad src) (sgn = -1 gives the transposed streaming).
-template <typename T, int NN, int N, int MODE>
+template <typename T, int NN, int N, int MODE, bool FUSE = false>
 void enqueue_stage(const StepArgs& a, ProfRec* pr, double hs, double sgn, const T* src, T* u, T* out,
                    int stage = 0, long long step1 = 0) {
+  static_assert(!FUSE || !split_planes<NN>(), "the fused forward transform needs a plane in LDS");
   using V = typename cplx_of<T>::type;
   using Z = ZdShape<T, NN>;
   constexpr int M = (N + 1) * (N + 1);
@@ -1024,7 +1052,9 @@ void enqueue_stage(const StepArgs& a, ProfRec* pr, double hs, double sgn, const 
     rec(PROF_FWD_ROWS);
     hipLaunchKernelGGL((k_pencil<T, NN, PENCIL_YFWD>), dim3(pencils), zblk, lz, st, spec, spec, tw, kv, cctl);
     rec(PROF_Y_FWD);
-  } else {
+  } else if constexpr (!FUSE) {
+    // (fused stages find the spectrum of src already written by the
+    // previous inverse pass)
     hipLaunchKernelGGL((k_fwd_plane<T, NN>), dim3((planes + kFwdPlanes - 1) / kFwdPlanes), pblk, lp, st, src,
                        spec, tw, cctl, planes);
     rec(PROF_FWD_PLANE);
@@ -1049,8 +1079,9 @@ void enqueue_stage(const StepArgs& a, ProfRec* pr, double hs, double sgn, const 
                        a.qflag, a.phi_int, a.partial, tw, M, T(hs), a.dt, cctl, stage, step1);
     rec(PROF_INV_ROWS);
   } else {
-    hipLaunchKernelGGL((k_inv_plane<T, NN, MODE>), dim3(planes), pblk, lp, st, coupled, src, u, out, sig, q,
-                       a.qflag, a.phi_int, a.partial, tw, M, T(hs), a.dt, cctl, stage, step1);
+    hipLaunchKernelGGL((k_inv_plane<T, NN, MODE, FUSE>), dim3(planes), pblk, lp, st, coupled, src, u, out, sig,
+                       q, a.qflag, a.phi_int, a.partial, tw, M, T(hs), a.dt, cctl, stage, step1,
+                       FUSE ? spec : static_cast<V*>(nullptr));
     rec(PROF_INV_PLANE);
   }
 }
@@ -1130,7 +1161,7 @@ hipError_t enqueue_expo(const StepArgs& a, const OpArgs& op, ProfRec* pr) {
   } else {
     hipLaunchKernelGGL((k_inv_plane<T, NN, EPI_SET>), dim3(planes), pblk, lp, st, spec, u, u, u, sig,
                        static_cast<const T*>(nullptr), a.qflag, a.phi_int, a.partial, tw, M, T(0), 0.0, cctl, 0,
-                       0LL);
+                       0LL, static_cast<V*>(nullptr));
     rec(PROF_INV_PLANE);
   }
   return hipGetLastError();
@@ -1153,7 +1184,25 @@ hipError_t enqueue_t(const StepArgs& a, const OpArgs& op, ProfRec* pr) {
         pr->count = 0;
       }
       const long long s1 = op.step1;
-      if (a.scheme == 1) {
+      bool done = false;
+      if constexpr (!split_planes<NN>()) {
+        if (op.fused) {
+          // the spectrum of u is in place on entry; every inverse pass
+          // leaves the spectrum of its output for the next stage (the last
+          // one that of the new u, for the next step)
+          if (a.scheme == 1) {
+            enqueue_stage<T, NN, N, EPI_EULER, true>(a, pr, hc, 1.0, u, u, u, 0, s1);
+          } else {
+            enqueue_stage<T, NN, N, EPI_FIRST, true>(a, pr, kRkAlpha[0] * hc, 1.0, u, u, v, 0, s1);
+            enqueue_stage<T, NN, N, EPI_MID, true>(a, pr, kRkAlpha[1] * hc, 1.0, v, u, v, 1, s1);
+            enqueue_stage<T, NN, N, EPI_MID, true>(a, pr, kRkAlpha[2] * hc, 1.0, v, u, v, 2, s1);
+            enqueue_stage<T, NN, N, EPI_LAST, true>(a, pr, kRkAlpha[3] * hc, 1.0, v, u, u, 3, s1);
+          }
+          done = true;
+        }
+      }
+      if (done) {
+      } else if (a.scheme == 1) {
         // forward Euler (eq. 11 with the sign reading): u <- u + dt f(u)
         enqueue_stage<T, NN, N, EPI_EULER>(a, pr, hc, 1.0, u, u, u, 0, s1);
       } else {
@@ -1223,6 +1272,21 @@ hipError_t enqueue_t(const StepArgs& a, const OpArgs& op, ProfRec* pr) {
       const long long len = (long long)M * nvox;
       hipLaunchKernelGGL((k_rhs_minus<T>), dim3(kDotBlocks), dim3(kBlock), 0, st, static_cast<T*>(op.y),
                          static_cast<const T*>(op.x), len);
+      break;
+    }
+    case OP_FWD: {
+      // spectrum of u for the fused step (plane grids only)
+      if constexpr (!split_planes<NN>()) {
+        using V = typename cplx_of<T>::type;
+        constexpr int planes = M * NN;
+        const size_t lds = plane_lds<T, NN>();
+        const T* src = static_cast<const T*>(a.u);
+        V* spec = static_cast<V*>(a.spec);
+        const V* tw = static_cast<const V*>(a.tw);
+        const Ctl* cctl = static_cast<const Ctl*>(a.ctl);
+        hipLaunchKernelGGL((k_fwd_plane<T, NN>), dim3((planes + kFwdPlanes - 1) / kFwdPlanes), dim3(kPBlock),
+                           lds, st, src, spec, tw, cctl, planes);
+      }
       break;
     }
     case OP_EXPO:

@@ -135,6 +135,7 @@ struct rte_handle {
   hipGraphExec_t exec;
   bool graph_ready;
   bool use_graph;
+  bool spec_valid;                  // spec holds the xy spectrum of u (fused steps' entry condition)
   const double* qw;                 // source time profile (device, caller-owned) or null
   long long qw_rows;
   int qw_cols;
@@ -150,6 +151,7 @@ int to_code(hipError_t e) { return e == hipSuccess ? RTE_OK : RTE_EDEVICE; }
 OpArgs step_op() {
   OpArgs op{};
   op.kind = OP_STEP;
+  op.fused = 1;
   return op;
 }
 
@@ -294,6 +296,12 @@ int enqueue_steps(rte_handle* h, int64_t k) {
       h->graph_ready = true;
     }
   }
+  if (!h->spec_valid) {
+    OpArgs f{};
+    f.kind = OP_FWD;
+    if (launch_enqueue_op(h->n, h->args, f, nullptr) != 0) return RTE_EDEVICE;
+    h->spec_valid = true;
+  }
   for (int64_t i = 0; i < k; ++i) {
     hipError_t e = h->graph_ready ? hipGraphLaunch(h->exec, h->stream)
                                   : hipError_t(launch_enqueue_op(h->n, h->args, step_op(), nullptr));
@@ -389,6 +397,7 @@ int rte_create(const rte_config* cfg, const rte_medium* med, void* dev_ws, size_
   h->ws = reinterpret_cast<unsigned char*>(dev_ws);
   h->lay = L;
   h->graph_ready = false;
+  h->spec_valid = false;
   h->qw = nullptr;
   h->qw_rows = 0;
   h->qw_cols = 0;
@@ -535,6 +544,7 @@ int rte_get_state(rte_handle* h, double* out, size_t len) {
 
 int rte_set_state(rte_handle* h, const double* in, size_t len) {
   if (!h || !in) return RTE_EINVAL;
+  h->spec_valid = false;
   const size_t cnt = size_t(h->M) * h->n * h->n * h->n;
   if (len < cnt) return RTE_EINVAL;
   rte::Ctl c;
@@ -679,6 +689,7 @@ int rte_adjoint(rte_handle* h, int64_t steps, int64_t every, void* adj_ws, size_
   using namespace rte;
   if (!h || steps <= 0 || every <= 0 || !grad_mu_a || !grad_mu_s) return RTE_EINVAL;
   if (h->cfg.n_det > 0 && !dj_dr) return RTE_EINVAL;
+  h->spec_valid = false;   // the recomputation and transposed stages reuse the spectrum buffers
   const AdjLayout A = adj_layout(&h->cfg, steps, every);
   if (!adj_ws || (reinterpret_cast<uintptr_t>(adj_ws) % kAlign) != 0 || adj_bytes < A.total) return RTE_ENOMEM;
   unsigned char* w = static_cast<unsigned char*>(adj_ws);
@@ -827,6 +838,7 @@ int rte_steady_gmres(rte_handle* h, int32_t restart, int64_t max_iters, double t
   if (!h || restart < 1 || restart + 1 > kMaxBasisVectors || max_iters < 1 || !(tol > 0) || steps_per_apply < 0)
     return RTE_EINVAL;
   if (h->qw) return RTE_EINVAL;   // a steady state needs a constant source
+  h->spec_valid = false;          // the operator applications reuse the spectrum buffers
   const size_t need = rte_krylov_workspace_bytes(&h->cfg, restart);
   if (!kws || (reinterpret_cast<uintptr_t>(kws) % kAlign) != 0 || kbytes < need) return RTE_ENOMEM;
   {
@@ -1035,6 +1047,7 @@ int expo_run(rte_handle* h, double t_ps, rte::ProfRec* pr) {
   if (!h || !std::isfinite(t_ps) || t_ps < 0) return RTE_EINVAL;
   if (!h->homogeneous || h->N > kDenseOrder || h->qw) return RTE_EINVAL;
   if (t_ps == 0) return RTE_OK;
+  h->spec_valid = false;
   const bool f64 = h->prec == RTE_FP64;
   const double eps = f64 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24);
   const double theta = taylor_theta(f64 ? kTaylorMaxF64 : kTaylorMaxF32, eps);
@@ -1120,6 +1133,12 @@ int rte_profile_kernels(rte_handle* h, int64_t nsteps, double* ms, int64_t* coun
     counts[c] = 0;
   }
   int rc = made == kMaxProfLaunches ? RTE_OK : RTE_EDEVICE;
+  if (rc == RTE_OK && !h->spec_valid) {
+    OpArgs f{};
+    f.kind = OP_FWD;
+    if (launch_enqueue_op(h->n, h->args, f, nullptr) != 0) rc = RTE_EDEVICE;
+    else h->spec_valid = true;
+  }
   for (int64_t s = 0; s < nsteps && rc == RTE_OK; ++s) {
     hipError_t e = hipError_t(launch_enqueue_op(h->n, h->args, step_op(), &pr));
     if (e == hipSuccess && pr.count > 0) e = hipEventSynchronize(ev[pr.count - 1]);
