@@ -119,7 +119,7 @@ def serving_bench(a):
     Poisson arrivals at 1.5 / (mean one-at-a-time service time)."""
     # one hardware queue per request stream (HIP's default is 4 per process),
     # set before the runtime initialises
-    os.environ.setdefault("GPU_MAX_HW_QUEUES", str(max(4, min(16, a.slots))))
+    os.environ["GPU_MAX_HW_QUEUES"] = str(max(4, min(16, a.slots)))
     import numpy as np
     import torch
 
