@@ -468,6 +468,15 @@ __device__ __forceinline__ void c2r_merge(V* pl, const V* tw) {
   }
 }
 
+#ifndef RTE_EPI_UNROLL
+#define RTE_EPI_UNROLL 16
+#endif
+#ifndef RTE_PWAVES
+#define RTE_PWAVES 1
+#endif
+constexpr int kEpiUnroll = RTE_EPI_UNROLL;   // epilogue elements per thread with loads in flight
+constexpr int kPWaves = RTE_PWAVES;          // minimum waves per SIMD asked of the plane passes
+
 // Epilogue modes of the inverse pass.
 enum { EPI_MID = 0, EPI_FIRST = 1, EPI_LAST = 2, EPI_ADJ = 3, EPI_EULER = 4, EPI_APPLY = 5, EPI_SET = 6 };
 
@@ -493,7 +502,7 @@ __device__ __forceinline__ void epilogue(V* pl, int y0, int b, int z, const T* v
   const size_t poff = (size_t(b) * n + z) * n * n + size_t(y0) * n;
   const size_t voff = size_t(z) * n * n + size_t(y0) * n;
   const T* sg = sig + size_t(l) * n * n * n + voff;
-#pragma unroll 4
+#pragma unroll (kEpiUnroll)
   for (int i = threadIdx.x; i < RB * H; i += BLOCK) {
     const int y = i / H, j = i - y * H;
     const int e = y * n + 2 * j;
@@ -573,7 +582,7 @@ __device__ __forceinline__ double source_weight(const Ctl* __restrict__ ctl, int
 // (which may be the spectrum just read: each workgroup owns its plane), so
 // the next stage needs no separate forward pass.
 template <typename T, int NN, int MODE, bool FUSE = false>
-__global__ void __launch_bounds__(kPBlock)
+__global__ void __launch_bounds__(kPBlock, kPWaves)
 k_inv_plane(const typename cplx_of<T>::type* spec, const T* vin, T* u, T* dst,
             const T* __restrict__ sig, const T* __restrict__ q, const int* __restrict__ qflag,
             double* __restrict__ phi_int, double* __restrict__ partial,
