@@ -115,3 +115,16 @@ int main() {
                     str(cs / "rte_tables.cpp"), "-o", str(exe)], check=True)
     r = subprocess.run([str(exe)], capture_output=True, text=True)
     assert r.returncode == 0, (r.returncode, r.stdout)
+
+
+def test_krylov_workspace_bytes_bounds():
+    """Restart lengths outside 1..31 are refused (0 bytes); inside, the
+    workspace holds restart + 3 state vectors."""
+    cfg, _ = rte.make_config(32, 3, rte.RTE_FP32, 0.25, 0.3, 0.0, 4, 0.01, 1.0)
+    lib = rte.lib()
+    assert lib.rte_krylov_workspace_bytes(cfg, 0) == 0
+    assert lib.rte_krylov_workspace_bytes(cfg, 32) == 0
+    F = 16 * 32 ** 3 * 4
+    for m in (1, 16, 31):
+        b = lib.rte_krylov_workspace_bytes(cfg, m)
+        assert (m + 3) * F <= b <= (m + 3) * F + (1 << 20)
