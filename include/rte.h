@@ -21,8 +21,10 @@
  *    to d psi/dt = c (-[s.grad psi] - Sigma_l psi + q) (the sign form that
  *    eqs. 1 and 6 give), evaluated in the equivalent nested form
  *    v <- u + dt/4 f(u); v <- u + dt/3 f(v); v <- u + dt/2 f(v);
- *    u <- u + dt f(v), exact for this autonomous affine right-hand side;
- *    or, on request, the paper's first-order explicit step (eq. 11).
+ *    u <- u + dt f(v), exact for this autonomous affine right-hand side
+ *    (a time-dependent source gives each stage its own source weight, see
+ *    rte_set_source_profile); or, on request, the paper's first-order
+ *    explicit step (eq. 11).
  *
  * Grid: n^3 voxels, voxel (z, y, x) at r = (x, y, z) * dx; every field is
  * stored [z][y][x] with x fastest; moment fields are [a][z][y][x]. The real

@@ -8,15 +8,22 @@
 // moments are mixed, which keeps every sweep over HBM coalesced:
 //   F  k_fwd_plane  per (moment, z-plane): x real-to-complex FFT and y FFT of
 //                   the plane in LDS -> xy spectrum S [b][z][ky][kx];
-//   D  k_zderiv     per (moment, ky, 16 kx columns): z FFT, times i k_z,
+//   D  k_pencil     per (moment, ky, 16 kx columns): z FFT, times i k_z,
 //                   inverse z FFT -> D = d/dz S (xy spectral, z physical);
 //   C  k_couple     per spectral point, all moments in registers:
-//                   W = -i (kx Bx + ky By) S - Bz D, written over S;
+//                   W = -i (kx Bx + ky By) S - Bz D, written over S
+//                   (k_couple_rt for orders beyond registers: a run-time
+//                   slot table, W to a separate buffer);
 //   P  k_inv_plane  per (moment, z-plane): inverse y FFT, complex-to-real x
 //                   FFT and the fused pointwise epilogue (loss, in-scatter,
 //                   boundary layer, source, RK combine; after the last stage
-//                   also the integrated fluence and fluence-change partials).
+//                   also the integrated fluence and fluence-change partials);
+//                   in a time step it also transforms its output plane
+//                   forward (F of the next stage, fused).
 // k_end_step closes each step (detector readings, residual, stop flags).
+// Grids of 256 points split F and P into row and y-pencil passes. Also
+// here: the exact propagation in homogeneous media (k_expo on the full 3D
+// spectrum) and the vector kernels of the Krylov steady-state solver.
 //
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
 // L2. Tiles that share data (neighbouring kx tiles in D, the moments of one
