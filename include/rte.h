@@ -252,17 +252,19 @@ int rte_expo_advance(rte_handle* h, double t_ps);
 
 /* Run nsteps steps with plain launches, timing every kernel with HIP
  * events on the handle's stream, and store the summed milliseconds of each
- * kernel class in ms[0..11] and the launch counts in counts[0..11]. Classes:
+ * kernel class in ms[0..12] and the launch counts in counts[0..12]. Classes:
  * 0 forward plane pass, 1 z-derivative pass, 2 moment coupling pass,
  * 3 inverse plane pass with epilogue, 4 end-of-step bookkeeping; on grids
  * split into row and pencil passes (n = 256): 5 forward row pass,
  * 6 forward y pencil pass, 7 inverse y pencil pass, 8 inverse row pass with
  * epilogue; of the exact propagation: 9 forward z pass, 10 per-point
- * exponential, 11 inverse z pass. Synchronises the stream. */
+ * propagation (frame rotations and block products, or the per-point
+ * series), 11 inverse z pass, 12 block-exponential table. Synchronises the
+ * stream. */
 int rte_profile_kernels(rte_handle* h, int64_t nsteps, double* ms, int64_t* counts);
 
-/* rte_expo_advance with the same per-class event timing (ms[0..11],
- * counts[0..11] as for rte_profile_kernels). */
+/* rte_expo_advance with the same per-class event timing (ms[0..12],
+ * counts[0..12] as for rte_profile_kernels). */
 int rte_profile_expo(rte_handle* h, double t_ps, double* ms, int64_t* counts);
 
 /* Release the handle (and its captured graph). The workspace stays the

@@ -65,6 +65,12 @@ constexpr SlotList slots_of(int N, int l, int m) {
 bool coupling_dense(int N, std::vector<double>& bx, std::vector<double>& by,
                     std::vector<double>& bz);
 
+// Real-harmonic representation of the rotation by +90 degrees about x
+// (y -> z): one (2l+1)^2 block per degree l <= N, row-major, concatenated.
+// Computed by exact quadrature and checked against the streaming matrices
+// (D (k.B) D^T = (X k).B); false if the check fails or N is out of range.
+bool rotation_x90(int N, std::vector<double>& D);
+
 // Coupling slot table of the high-order pass: per row a, the non-zeros of
 // the real-basis streaming matrices as codes (b << 2 | axis) in slot order,
 // -1 after the last, and their FP64 values. Returns false for an order that
@@ -148,7 +154,7 @@ struct StepArgs {
 enum {
   PROF_FWD_PLANE = 0, PROF_ZDERIV, PROF_COUPLE, PROF_INV_PLANE, PROF_END,
   PROF_FWD_ROWS, PROF_Y_FWD, PROF_Y_INV, PROF_INV_ROWS,
-  PROF_Z_FWD, PROF_EXPO, PROF_Z_INV, PROF_CLASSES
+  PROF_Z_FWD, PROF_EXPO, PROF_Z_INV, PROF_EXPO_TABLE, PROF_CLASSES
 };
 constexpr int kMaxProfLaunches = 32;
 
@@ -189,10 +195,13 @@ struct OpArgs {
   double* gmus;
   const double* djdr;// adjoint sources of one step's readings (ndet); device
                      // coefficients of OP_COMBINE / OP_SCALE
-  int count;         // OP_WDOTS / OP_COMBINE: number of basis vectors
+  int count;         // OP_WDOTS / OP_COMBINE: number of basis vectors; OP_EXPO: 1 =
+                     // rotation path
   double scale;      // OP_COMBINE; OP_EXPO: per-substep norm limit theta
   double eps;        // OP_EXPO: Taylor truncation target
   double sigl[kMaxOrder + 1];  // OP_EXPO: per-degree loss of the medium
+  double kunit;      // OP_EXPO: 2 pi / (n dx); with count = 1 the rotation
+                     // data sit in the stage buffer v
   int fused;         // OP_STEP: the spectrum of u is in place on entry and is
                      // left in place for the next step (plane grids)
   long long step1;   // OP_STEP / OP_STAGE: 1 + the step index whose source

@@ -984,6 +984,326 @@ k_expo(typename cplx_of<T>::type* __restrict__ spec, const typename cplx_of<T>::
   for (int i = 0; i < M; ++i) spec[i * MS + pt] = a[i];
 }
 
+// ----------------------------- E': exact propagation by rotation to k = z ---
+
+// Rotation covariance of the streaming matrices: for the rotation R taking
+// khat to z, D(R) (k.B) D(R)^T = |k| B_z, with D(R) the real-harmonic
+// representation of R (block diagonal per degree, orthogonal; it commutes
+// with the per-degree loss). So exp(T M(k)) = D^T exp(T M_z(|k|)) D, and
+// M_z(|k|) = -c (i |k| B_z + Sigma) couples only equal orders m: blocks of
+// size N + 1 - |m| (degrees |m|..N). The block exponentials depend on |k|
+// only, i.e. on the integer f^2 = fx^2 + fy^2 + fz^2 of the grid frequencies:
+// k_expo_table builds, for every f^2 and m, E_m = exp(T M_z) and
+// Phi_m = int_0^T exp(s M_z) ds c (column by column, truncated Taylor series
+// with the same bounded remainder as k_expo), and k_expo_rot rotates each
+// point's moments and source to the k = z frame, applies the blocks and
+// rotates back. D(R) = X^T Rz(-theta) X Rz(-phi): Rz rotates the (m, -m)
+// pairs by m times the angle, X (rotation by 90 degrees about x, y -> z) is
+// a constant per-degree matrix computed once on the host.
+
+constexpr int expo_block(int N, int m) { return N + 1 - (m < 0 ? -m : m); }
+// number of f^2 values: kx index < n/2, ky and kz frequencies |f| < n/2
+constexpr int expo_nf2(int n) { return (n / 2 - 1) * (n / 2 - 1) * 3 + 1; }
+// offset (in complex entries) of the E block of order |m| in one f^2 row;
+// the Phi block follows it. Orders m and -m have the same B_z block, hence
+// the same exponentials: one pair of blocks per m >= 0.
+constexpr int expo_block_offset(int N, int m) {
+  int o = 0;
+  for (int mm = 0; mm < m; ++mm) o += 2 * expo_block(N, mm) * expo_block(N, mm);
+  return o;
+}
+constexpr int expo_row_size(int N) { return expo_block_offset(N, N + 1); }
+constexpr int expo_row_columns(int N) {   // sum over m >= 0 of 2 d
+  int c = 0;
+  for (int m = 0; m <= N; ++m) c += 2 * expo_block(N, m);
+  return c;
+}
+constexpr int xrot_size(int N) {
+  int o = 0;
+  for (int l = 0; l <= N; ++l) o += (2 * l + 1) * (2 * l + 1);
+  return o;
+}
+// real-valued offset of the table behind X and the B_z couplings (even, so
+// that complex entries stay aligned)
+constexpr int expo_table_offset(int N) {
+  const int o = xrot_size(N) + 2 * (N + 1) * (N + 1);
+  return o + (o & 1);
+}
+
+// One thread per (f^2, m, column): column j < d of E_m, or column j - d of
+// Phi_m, as the result of propagating the unit vector (with a unit source in
+// the Phi case) over time T. bz[2a], bz[2a+1]: B_z couplings of row a to
+// (l-1, m) and (l+1, m).
+template <typename T, int N>
+__global__ void __launch_bounds__(kEBlock)
+k_expo_table(typename cplx_of<T>::type* __restrict__ tab, const T* __restrict__ bz, ExpoParams<T> p,
+             double kunit, int nf2) {
+  using V = typename cplx_of<T>::type;
+  constexpr int M = (N + 1) * (N + 1);
+  constexpr int D = N + 1;
+  constexpr int JMAX = TaylorMax<T>::value;
+  constexpr int C = expo_row_columns(N);
+  const long long gid = (long long)blockIdx.x * kEBlock + threadIdx.x;
+  if (gid >= (long long)nf2 * C) return;
+  const int f2 = int(gid / C);
+  int col = int(gid - (long long)f2 * C);
+  int m = 0;
+  while (col >= 2 * expo_block(N, m)) {
+    col -= 2 * expo_block(N, m);
+    ++m;
+  }
+  const int am = m < 0 ? -m : m;
+  const int d = N + 1 - am;
+  const bool phi = col >= d;
+  const int j = phi ? col - d : col;
+  const double kk = kunit * std::sqrt(double(f2));
+  const double nu = p.ct * (kk + p.sigmax);
+  const int s = nu > p.theta ? int(std::ceil(nu / p.theta)) : 1;
+  const double nus = nu / s;
+  int J = 1;
+  double bound = 0.5 * nus * nus * std::exp(nus);
+  while (bound > p.eps && J < JMAX) {
+    ++J;
+    bound *= nus / (J + 1);
+  }
+  const T h = T(p.ct / s), k = T(kk);
+  // rows i = l - |m|; coupling of row i to rows i -+ 1
+  T lo[D], hi[D], sg[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const int l = am + i;
+    const int a = l * l + l + m;
+    lo[i] = i < d ? bz[2 * a] : T(0);
+    hi[i] = i + 1 < d ? bz[2 * a + 1] : T(0);
+    sg[i] = i < d ? p.sig[l] : T(0);
+  }
+  V x[D], t[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) x[i] = cmk<V>(T(!phi && i == j ? 1 : 0), T(0));
+  for (int sub = 0; sub < s; ++sub) {
+#pragma unroll
+    for (int i = 0; i < D; ++i) t[i] = x[i];
+    for (int jj = 1; jj <= J; ++jj) {
+      const T hj = h / T(jj);
+      V nt[D];
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        // (M t / c)_i = -i |k| (lo t_{i-1} + hi t_{i+1}) - sigma t_i
+        T re = T(0), im = T(0);
+        if (i > 0) {
+          re += lo[i] * t[i - 1].x;
+          im += lo[i] * t[i - 1].y;
+        }
+        if (i + 1 < D) {
+          re += hi[i] * t[i + 1].x;
+          im += hi[i] * t[i + 1].y;
+        }
+        T ox = k * im - sg[i] * t[i].x;
+        T oy = -k * re - sg[i] * t[i].y;
+        if (phi && jj == 1 && i == j) ox += T(1);   // unit source in the first term
+        nt[i] = cmk<V>(hj * ox, hj * oy);
+      }
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        t[i] = nt[i];
+        x[i] = cmk<V>(x[i].x + nt[i].x, x[i].y + nt[i].y);
+      }
+    }
+  }
+  V* out = tab + (size_t)f2 * expo_row_size(N);
+  // block of order m (m is a run-time value here)
+  int off = 0;
+  for (int mm = 0; mm < m; ++mm) off += 2 * expo_block(N, mm) * expo_block(N, mm);
+  out += off + (phi ? d * d : 0);
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+    if (i < d) out[i * d + j] = x[i];
+}
+
+// Rotation of one degree shell L (2L+1 moments in registers): z-rotation
+// of the (m, -m) pairs by m times an angle given as (cos m a, sin m a).
+template <typename V, typename T, int L>
+__device__ __forceinline__ void shell_rot_z(V* v, const T* cm, const T* sm) {
+#pragma unroll
+  for (int m = 1; m <= L; ++m) {
+    const V xp = v[L + m], xq = v[L - m];
+    v[L + m] = cmk<V>(cm[m] * xp.x - sm[m] * xq.x, cm[m] * xp.y - sm[m] * xq.y);
+    v[L - m] = cmk<V>(sm[m] * xp.x + cm[m] * xq.x, sm[m] * xp.y + cm[m] * xq.y);
+  }
+}
+
+// v <- X_L v (TRANS: X_L^T v), the degree-L block of X from LDS
+template <typename V, typename T, int L, bool TRANS>
+__device__ __forceinline__ void shell_rot_x(V* v, const T* xs) {
+  constexpr int d = 2 * L + 1;
+  constexpr int o = L * (2 * L - 1) * (2 * L + 1) / 3;   // sum_{l<L} (2l+1)^2
+  V w[d];
+#pragma unroll
+  for (int i = 0; i < d; ++i) {
+    T re = T(0), im = T(0);
+#pragma unroll
+    for (int j = 0; j < d; ++j) {
+      const T c = TRANS ? xs[o + j * d + i] : xs[o + i * d + j];
+      re += c * v[j].x;
+      im += c * v[j].y;
+    }
+    w[i] = cmk<V>(re, im);
+  }
+#pragma unroll
+  for (int i = 0; i < d; ++i) v[i] = w[i];
+}
+
+// (cos, sin) of m phi and m theta, m = 0..N, for the direction of k
+// (k = 0: no rotation)
+template <typename T, int N>
+__device__ __forceinline__ void k_angles(T kx, T ky, T kz, T* cp, T* sp, T* ct, T* st) {
+  const T kxy = std::sqrt(kx * kx + ky * ky);
+  const T kr = std::sqrt(kxy * kxy + kz * kz);
+  T cph = T(1), sph = T(0), cth = T(1), sth = T(0);
+  if (kr > T(0)) {
+    cth = kz / kr;
+    sth = kxy / kr;
+  }
+  if (kxy > T(0)) {
+    cph = kx / kxy;
+    sph = ky / kxy;
+  }
+  cp[0] = ct[0] = T(1);
+  sp[0] = st[0] = T(0);
+#pragma unroll
+  for (int m = 1; m <= N; ++m) {
+    cp[m] = cp[m - 1] * cph - sp[m - 1] * sph;
+    sp[m] = sp[m - 1] * cph + cp[m - 1] * sph;
+    ct[m] = ct[m - 1] * cth - st[m - 1] * sth;
+    st[m] = st[m - 1] * cth + ct[m - 1] * sth;
+  }
+}
+
+// Shells L..N of one point: to the k = z frame, D(R) = X^T Rz(-theta) X
+// Rz(-phi) (BACK: D(R)^T = Rz(phi) X^T Rz(theta) X), scaled by sc; one shell
+// in registers at a time.
+template <typename V, typename T, int N, bool BACK, int L = 0>
+__device__ __forceinline__ void frame_shells(V* v, size_t ms, const T* xs, const T* cp, const T* sp,
+                                             const T* ct, const T* st, T sc) {
+  if constexpr (L <= N) {
+    constexpr int d = 2 * L + 1, a0 = L * L;
+    V w[d];
+#pragma unroll
+    for (int i = 0; i < d; ++i) {
+      const V x = v[(a0 + i) * ms];
+      w[i] = cmk<V>(sc * x.x, sc * x.y);
+    }
+    if constexpr (L > 0) {
+      T ns[L + 1];
+      if constexpr (!BACK) {
+#pragma unroll
+        for (int m = 0; m <= L; ++m) ns[m] = -sp[m];
+        shell_rot_z<V, T, L>(w, cp, ns);
+        shell_rot_x<V, T, L, false>(w, xs);
+#pragma unroll
+        for (int m = 0; m <= L; ++m) ns[m] = -st[m];
+        shell_rot_z<V, T, L>(w, ct, ns);
+        shell_rot_x<V, T, L, true>(w, xs);
+      } else {
+        shell_rot_x<V, T, L, false>(w, xs);
+        shell_rot_z<V, T, L>(w, ct, st);
+        shell_rot_x<V, T, L, true>(w, xs);
+        shell_rot_z<V, T, L>(w, cp, sp);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < d; ++i) v[(a0 + i) * ms] = w[i];
+    frame_shells<V, T, N, BACK, L + 1>(v, ms, xs, cp, sp, ct, st, sc);
+  }
+}
+
+// Every point's moments (scaled by sc) to (BACK: from) its k = z frame, in
+// place in the full spectrum [b][kz][ky][kx].
+template <typename T, int NN, int N, bool BACK>
+__global__ void __launch_bounds__(kEBlock)
+k_expo_frame(typename cplx_of<T>::type* __restrict__ v, const T* __restrict__ kv, const T* __restrict__ xrot,
+             T sc) {
+  using V = typename cplx_of<T>::type;
+  constexpr int n = NN, H = NN / 2;
+  constexpr size_t MS = size_t(n) * n * H;
+  constexpr int XS = xrot_size(N);
+  __shared__ T xs[XS];
+  for (int i = threadIdx.x; i < XS; i += kEBlock) xs[i] = xrot[i];
+  __syncthreads();
+  const int pt = blockIdx.x * kEBlock + threadIdx.x;
+  if (pt >= n * n * H) return;
+  const int xi = pt % H, yi = (pt / H) % n, zi = pt / (n * H);
+  T cp[N + 1], sp[N + 1], ct[N + 1], st[N + 1];
+  k_angles<T, N>(kv[xi], kv[yi], kv[zi], cp, sp, ct, st);
+  frame_shells<V, T, N, BACK>(v + pt, MS, xs, cp, sp, ct, st, sc);
+}
+
+// a <- E_m a + Phi_m q on the degrees m..N of orders m and -m (same
+// blocks), for m = MM..N, with a and q (both in the k = z frame) read from
+// and a written to the spectrum
+template <typename V, typename T, int N, int MM = 0>
+__device__ __forceinline__ void expo_blocks(V* a, const V* q, size_t ms, const V* row) {
+  if constexpr (MM <= N) {
+    constexpr int d = N + 1 - MM;
+    constexpr int NS = MM == 0 ? 1 : 2;   // the orders m and -m
+    const V* E = row + expo_block_offset(N, MM);
+    const V* P = E + d * d;
+    V x[NS][d], y[NS][d];
+#pragma unroll
+    for (int sgn = 0; sgn < NS; ++sgn)
+#pragma unroll
+      for (int j = 0; j < d; ++j) {
+        const int m = sgn ? -MM : MM;
+        const int bj = (MM + j) * (MM + j) + (MM + j) + m;
+        x[sgn][j] = a[bj * ms];
+        y[sgn][j] = q ? q[bj * ms] : cmk<V>(T(0), T(0));
+      }
+    V w[NS][d];
+#pragma unroll
+    for (int i = 0; i < d; ++i) {
+      T re[NS], im[NS];
+#pragma unroll
+      for (int sgn = 0; sgn < NS; ++sgn) re[sgn] = im[sgn] = T(0);
+#pragma unroll
+      for (int j = 0; j < d; ++j) {
+        const V e = E[i * d + j];
+        const V f = q ? P[i * d + j] : cmk<V>(T(0), T(0));
+#pragma unroll
+        for (int sgn = 0; sgn < NS; ++sgn) {
+          re[sgn] += e.x * x[sgn][j].x - e.y * x[sgn][j].y + f.x * y[sgn][j].x - f.y * y[sgn][j].y;
+          im[sgn] += e.x * x[sgn][j].y + e.y * x[sgn][j].x + f.x * y[sgn][j].y + f.y * y[sgn][j].x;
+        }
+      }
+#pragma unroll
+      for (int sgn = 0; sgn < NS; ++sgn) w[sgn][i] = cmk<V>(re[sgn], im[sgn]);
+    }
+#pragma unroll
+    for (int sgn = 0; sgn < NS; ++sgn)
+#pragma unroll
+      for (int i = 0; i < d; ++i) {
+        const int m = sgn ? -MM : MM;
+        a[((MM + i) * (MM + i) + (MM + i) + m) * ms] = w[sgn][i];
+      }
+    expo_blocks<V, T, N, MM + 1>(a, q, ms, row);
+  }
+}
+
+template <typename T, int NN, int N>
+__global__ void __launch_bounds__(kEBlock)
+k_expo_blocks(typename cplx_of<T>::type* __restrict__ spec, const typename cplx_of<T>::type* __restrict__ qs,
+              const typename cplx_of<T>::type* __restrict__ tab) {
+  using V = typename cplx_of<T>::type;
+  constexpr int n = NN, H = NN / 2;
+  constexpr size_t MS = size_t(n) * n * H;
+  const int pt = blockIdx.x * kEBlock + threadIdx.x;
+  if (pt >= n * n * H) return;
+  const int xi = pt % H, yi = (pt / H) % n, zi = pt / (n * H);
+  auto freq = [](int i) { return i < n / 2 ? i : (i == n / 2 ? 0 : i - n); };
+  const int fy = freq(yi), fz = freq(zi);
+  const int f2 = xi * xi + fy * fy + fz * fz;
+  expo_blocks<V, T, N>(spec + pt, qs ? qs + pt : nullptr, MS, tab + (size_t)f2 * expo_row_size(N));
+}
+
 // ---------------------------------------------------------------- launch ---
 
 // Grids up to 128 points per axis keep a whole plane in LDS (plane passes);
@@ -1163,7 +1483,28 @@ hipError_t enqueue_expo(const StepArgs& a, const OpArgs& op, ProfRec* pr) {
   p.eps = op.eps;
   p.inv_n3 = T(1.0 / (double(n) * n * n));
   const int eblocks = (n * n * H + kEBlock - 1) / kEBlock;
-  hipLaunchKernelGGL((k_expo<T, NN, N>), dim3(eblocks), dim3(kEBlock), 0, st, spec, q ? dspec : nullptr, kv, p);
+  if (op.count == 1) {
+    // rotation data in the stage buffer v: X blocks, B_z couplings, then the
+    // block-exponential table (layout checked on the host)
+    const T* xrot = static_cast<const T*>(a.v);
+    const T* bz = xrot + xrot_size(N);
+    V* tab = reinterpret_cast<V*>(static_cast<T*>(a.v) + expo_table_offset(N));
+    const int nf2 = expo_nf2(NN);
+    const long long tthreads = (long long)nf2 * expo_row_columns(N);
+    hipLaunchKernelGGL((k_expo_table<T, N>), dim3(unsigned((tthreads + kEBlock - 1) / kEBlock)), dim3(kEBlock), 0,
+                       st, tab, bz, p, op.kunit, nf2);
+    rec(PROF_EXPO_TABLE);
+    if (q)
+      hipLaunchKernelGGL((k_expo_frame<T, NN, N, false>), dim3(eblocks), dim3(kEBlock), 0, st, dspec, kv, xrot,
+                         p.inv_n3);
+    hipLaunchKernelGGL((k_expo_frame<T, NN, N, false>), dim3(eblocks), dim3(kEBlock), 0, st, spec, kv, xrot,
+                       p.inv_n3);
+    hipLaunchKernelGGL((k_expo_blocks<T, NN, N>), dim3(eblocks), dim3(kEBlock), 0, st, spec, q ? dspec : nullptr,
+                       tab);
+    hipLaunchKernelGGL((k_expo_frame<T, NN, N, true>), dim3(eblocks), dim3(kEBlock), 0, st, spec, kv, xrot, T(1));
+  } else {
+    hipLaunchKernelGGL((k_expo<T, NN, N>), dim3(eblocks), dim3(kEBlock), 0, st, spec, q ? dspec : nullptr, kv, p);
+  }
   rec(PROF_EXPO);
   hipLaunchKernelGGL((k_pencil<T, NN, PENCIL_ZINV>), dim3(pencils), zblk, lz, st, spec, spec, tw, kv, cctl);
   rec(PROF_Z_INV);

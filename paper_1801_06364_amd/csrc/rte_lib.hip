@@ -140,6 +140,8 @@ struct rte_handle {
   long long qw_rows;
   int qw_cols;
   bool homogeneous;                 // constant maps, no boundary layer
+  bool expo_taylor;                 // exact propagation by the per-point series only
+  std::vector<double> rot_data;     // X blocks and B_z couplings of the rotation path
   double sigl[rte::kMaxOrder + 1];  // per-degree loss (homogeneous media)
   template <typename P> P* at(size_t off) const { return reinterpret_cast<P*>(ws + off); }
 };
@@ -401,6 +403,10 @@ int rte_create(const rte_config* cfg, const rte_medium* med, void* dev_ws, size_
   h->qw = nullptr;
   h->qw_rows = 0;
   h->qw_cols = 0;
+  {
+    const char* et = std::getenv("RTE_EXPO_SERIES");
+    h->expo_taylor = et && et[0] == '1';
+  }
   h->homogeneous = cfg->pml_width == 0;
   for (size_t i = 1; i < V && h->homogeneous; ++i)
     h->homogeneous = med->mu_a[i] == med->mu_a[0] && med->mu_s[i] == med->mu_s[0] && med->g[i] == med->g[0];
@@ -1070,8 +1076,57 @@ int expo_run(rte_handle* h, double t_ps, rte::ProfRec* pr) {
   o.coef = t_ps;
   o.scale = theta;
   o.eps = eps;
+  o.kunit = 2.0 * M_PI / (double(h->n) * h->cfg.dx_mm);
   for (int l = 0; l <= kMaxOrder; ++l) o.sigl[l] = h->sigl[l];
-  hipError_t e = hipError_t(launch_enqueue_op(h->n, h->args, o, pr));
+  hipError_t e = hipSuccess;
+  if (!h->expo_taylor) {
+    // rotation path: X blocks, B_z couplings and the block-exponential table
+    // go to the stage buffer v if they fit (else the per-point series)
+    const int N = h->N, M = h->M, n = h->n;
+    const size_t s = f64 ? 8 : 4;
+    size_t xs = 0;
+    for (int l = 0; l <= N; ++l) xs += size_t(2 * l + 1) * (2 * l + 1);
+    size_t toff = xs + 2 * size_t(M);
+    toff += toff & 1;
+    size_t row = 0;   // one pair of blocks per m >= 0 (m and -m share them)
+    for (int m = 0; m <= N; ++m) {
+      const size_t d = size_t(N + 1 - m);
+      row += 2 * d * d;
+    }
+    const size_t nf2 = size_t(n / 2 - 1) * (n / 2 - 1) * 3 + 1;
+    const size_t need = (toff + nf2 * row * 2) * s;
+    const size_t have = size_t(M) * n * n * n * s;
+    if (need <= have && h->rot_data.empty()) {
+      // X blocks and B_z couplings, built (and self-checked) once per handle
+      std::vector<double> X;
+      std::vector<double> b[3];
+      if (rotation_x90(N, X) && coupling_dense(N, b[0], b[1], b[2])) {
+        std::vector<double>& data = h->rot_data;
+        data = X;
+        data.resize(toff, 0.0);
+        for (int l = 0; l <= N; ++l)
+          for (int m = -l; m <= l; ++m) {
+            const int a = l * l + l + m;
+            if (l >= 1 && std::abs(m) <= l - 1)
+              data[xs + 2 * a] = b[2][size_t(a) * M + (l - 1) * (l - 1) + (l - 1) + m];
+            if (l + 1 <= N) data[xs + 2 * a + 1] = b[2][size_t(a) * M + (l + 1) * (l + 1) + (l + 1) + m];
+          }
+      }
+    }
+    if (need <= have && !h->rot_data.empty()) {
+      const std::vector<double>& data = h->rot_data;
+      if (f64) {
+        e = hipMemcpyAsync(h->ws + h->lay.v, data.data(), data.size() * 8, hipMemcpyHostToDevice, h->stream);
+      } else {
+        std::vector<float> df(data.begin(), data.end());
+        e = hipMemcpyAsync(h->ws + h->lay.v, df.data(), df.size() * 4, hipMemcpyHostToDevice, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);   // df is freed at scope end
+      }
+      if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+      o.count = 1;
+    }
+  }
+  if (e == hipSuccess) e = hipError_t(launch_enqueue_op(h->n, h->args, o, pr));
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   return to_code(e);
 }

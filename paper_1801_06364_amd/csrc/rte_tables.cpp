@@ -1,6 +1,7 @@
 // Host-side FP64 tables for the P_N stepper: streaming coefficients of
 // eq. (6) rotated to the real harmonic basis, FFT twiddles, wavenumbers and
 // the per-degree losses with the absorbing layer of eq. (12).
+#include <algorithm>
 #include <cmath>
 #include <complex>
 
@@ -129,6 +130,125 @@ bool coupling_dense(int N, std::vector<double>& bx, std::vector<double>& by,
         if (nz && !in) return false;
       }
     }
+  return true;
+}
+
+namespace {
+// Real harmonic Y^R_{l,m}(theta, phi) of the basis above (no Condon-Shortley
+// phase, orthonormal on the sphere): N_lm P_l^|m|(cos theta) times
+// sqrt2 cos(m phi) (m > 0), 1 (m = 0) or sqrt2 sin(|m| phi) (m < 0).
+double real_sh(int l, int m, double ct, double phi) {
+  const int am = m < 0 ? -m : m;
+  // P_am^am = (2 am - 1)!! (1 - x^2)^(am/2), then upward in l
+  const double st = std::sqrt(std::max(0.0, 1.0 - ct * ct));
+  double pmm = 1.0;
+  for (int i = 1; i <= am; ++i) pmm *= double(2 * i - 1) * st;
+  double p = pmm;
+  if (l > am) {
+    double pm1 = ct * double(2 * am + 1) * pmm;
+    double pm0 = pmm;
+    for (int ll = am + 2; ll <= l; ++ll) {
+      const double pn = (double(2 * ll - 1) * ct * pm1 - double(ll + am - 1) * pm0) / double(ll - am);
+      pm0 = pm1;
+      pm1 = pn;
+    }
+    p = pm1;
+  }
+  double ratio = 1.0;   // (l - am)! / (l + am)!
+  for (int i = l - am + 1; i <= l + am; ++i) ratio /= double(i);
+  const double nlm = std::sqrt(double(2 * l + 1) / (4.0 * M_PI) * ratio);
+  if (m > 0) return std::sqrt(2.0) * nlm * p * std::cos(m * phi);
+  if (m < 0) return std::sqrt(2.0) * nlm * p * std::sin(am * phi);
+  return nlm * p;
+}
+
+// Gauss-Legendre nodes and weights on [-1, 1] (Newton on P_q).
+void gauss_legendre(int q, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(q, 0.0);
+  w.assign(q, 0.0);
+  for (int i = 0; i < q; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (q + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= q; ++k) {
+        const double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      const double dp = q * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) {
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+        break;
+      }
+      x[i] = z;
+      w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+  }
+}
+}  // namespace
+
+bool rotation_x90(int N, std::vector<double>& D) {
+  if (N < 0 || N > kDenseOrder) return false;
+  // D_ab = int Y_a(s) Y_b(X^-1 s) ds for X the rotation by +90 degrees
+  // about x (y -> z, z -> -y), so X^-1 s = (s_x, s_z, -s_y); block per
+  // degree, exact quadrature (degree <= 2N in cos theta and in phi)
+  std::vector<double> gx, gw;
+  const int q = N + 2, P = 2 * N + 2;
+  gauss_legendre(q, gx, gw);
+  size_t off = 0;
+  D.clear();
+  for (int l = 0; l <= N; ++l) {
+    const int d = 2 * l + 1;
+    std::vector<double> blk(size_t(d) * d, 0.0);
+    for (int i = 0; i < q; ++i)
+      for (int j = 0; j < P; ++j) {
+        const double ct = gx[i], st = std::sqrt(std::max(0.0, 1.0 - ct * ct));
+        const double phi = 2.0 * M_PI * (j + 0.5) / P;
+        const double wq = gw[i] * 2.0 * M_PI / P;
+        const double sx = st * std::cos(phi), sy = st * std::sin(phi), sz = ct;
+        // X^-1 s
+        const double rx = sx, ry = sz, rz = -sy;
+        const double rct = rz, rphi = std::atan2(ry, rx);
+        for (int ma = -l; ma <= l; ++ma) {
+          const double ya = real_sh(l, ma, ct, phi) * wq;
+          for (int mb = -l; mb <= l; ++mb) blk[size_t(ma + l) * d + (mb + l)] += ya * real_sh(l, mb, rct, rphi);
+        }
+      }
+    for (int a = 0; a < d * d; ++a) D.push_back(std::fabs(blk[a]) < 1e-15 ? 0.0 : blk[a]);
+    off += size_t(d) * d;
+  }
+  // self-check of the representation against the streaming matrices:
+  // D (k.B) D^T = (X k).B for k = x, y, z
+  std::vector<double> b[3];
+  if (!coupling_dense(N, b[0], b[1], b[2])) return false;
+  const int M = (N + 1) * (N + 1);
+  std::vector<double> Dd(size_t(M) * M, 0.0);
+  size_t o = 0;
+  for (int l = 0; l <= N; ++l) {
+    const int d = 2 * l + 1, a0 = l * l;
+    for (int i = 0; i < d; ++i)
+      for (int j = 0; j < d; ++j) Dd[size_t(a0 + i) * M + a0 + j] = D[o + size_t(i) * d + j];
+    o += size_t(d) * d;
+  }
+  // X e_x = e_x, X e_y = e_z, X e_z = -e_y
+  const double Xc[3][3] = {{1, 0, 0}, {0, 0, -1}, {0, 1, 0}};   // columns are X e_j
+  for (int jx = 0; jx < 3; ++jx) {
+    for (int a = 0; a < M; ++a)
+      for (int c = 0; c < M; ++c) {
+        double lhs = 0.0;
+        for (int p = 0; p < M; ++p) {
+          const double dap = Dd[size_t(a) * M + p];
+          if (dap == 0.0) continue;
+          for (int r = 0; r < M; ++r) lhs += dap * b[jx][size_t(p) * M + r] * Dd[size_t(c) * M + r];
+        }
+        double rhs = 0.0;
+        for (int i = 0; i < 3; ++i) rhs += Xc[i][jx] * b[i][size_t(a) * M + c];
+        if (std::fabs(lhs - rhs) > 1e-11) return false;
+      }
+  }
   return true;
 }
 

@@ -30,7 +30,7 @@ EXPORTS = (
     "rte_profile_expo", "rte_set_source_profile",
 )
 KERNEL_CLASSES = ("fwd_plane", "zderiv", "couple", "inv_plane", "end_step",
-                  "fwd_rows", "y_fwd", "y_inv", "inv_rows", "z_fwd", "expo", "z_inv")
+                  "fwd_rows", "y_fwd", "y_inv", "inv_rows", "z_fwd", "expo", "z_inv", "expo_table")
 
 
 class RteError(RuntimeError):
