@@ -291,7 +291,8 @@ def expo_bench(a):
         if t_tab >= t_app:
             achieved = table_flops / (t_tab / 1e3) / 1e12
             roof = {"bound": "alu", "kernel": "expo_table", "achieved": achieved, "peak": FP32_VALU_PEAK,
-                    "unit": "TFLOP/s", "frac": achieved / FP32_VALU_PEAK, "traffic": None,
+                    "unit": "TFLOP/s", "frac": achieved / FP32_VALU_PEAK,
+                    "traffic": traffic_for("expo_table", "expo_homogeneous_128"),
                     "algorithmic_flops": table_flops, "avg_launch_ms": t_tab,
                     "peak_without_packed_fp32": FP32_VALU_PEAK / 2}
         else:
