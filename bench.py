@@ -80,8 +80,8 @@ def algorithmic_bytes(kind: str, n: int, M: int, N: int, s: int) -> float:
 
 
 def cpu_baseline(wl, workers: int):
-    """Time the FP64 oracle on a bounded sample: one RK stage (one full
-    operator evaluation plus the stage update) of the same workload."""
+    """Time the FP64 oracle on a bounded sample: one full RK4 step (four
+    operator evaluations and the stage combinations) of the same workload."""
     import numpy as np
     from oracle import pn
     pn.WORKERS = workers
@@ -90,15 +90,18 @@ def cpu_baseline(wl, workers: int):
     k = pn.wavenumbers(wl.n, wl.dx)
     Sig, _ = pn.potentials(wl.mu_a, wl.mu_s, wl.g, wl.N, wl.W, wl.mu0, wl.mu1)
     psi = pn.to_complex_basis(pn.full_moments(wl.psi0, wl.M), U).astype(complex)
+
+    def f(y):
+        return pn.operator(y, Sig, None, B, k, wl.c, workers)
+
     t0 = time.perf_counter()
-    f = pn.operator(psi, Sig, None, B, k, wl.c, workers)
-    psi = psi + (0.5 * wl.dt) * f
+    psi = pn.rk4_step(psi, f, wl.dt)
     el = time.perf_counter() - t0
-    del f, psi
-    upd = wl.n ** 3 * wl.M
+    del psi
+    upd = wl.n ** 3 * wl.M * 4
     return {"value": upd / el, "unit": "updates/s", "cores": workers, "kind": "oracle",
-            "sample": f"one RK stage (operator + stage update) of the full {wl.n}^3 P_{wl.N} "
-                      f"workload in FP64, complex SH basis; {upd} updates in {el:.1f} s; "
+            "sample": f"one RK4 step (four operator evaluations and the stage combinations) of the full "
+                      f"{wl.n}^3 P_{wl.N} workload in FP64, complex SH basis; {upd} updates in {el:.1f} s; "
                       f"scipy.fft workers={workers}, NumPy elementwise single-threaded"}
 
 
