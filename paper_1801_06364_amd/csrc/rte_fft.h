@@ -137,12 +137,12 @@ template <typename V, int DIR> struct Bfly<V, 8, DIR> {
   }
 };
 
-// One Stockham stage of radix R on an FFT of length L stored at
-// buf[i * S]. Lane p (of P = L/E) performs butterflies j = p + i P,
-// i < E / R, after the previous stages have combined spans of NS.
-// tw holds exp(-2 pi i t / NTAB), t < NTAB.
-template <typename V, int L, int R, int NS, int S, int NTAB, int DIR>
-__device__ __forceinline__ void fft_stage(V* buf, int p, const V* tw, bool act) {
+// One Stockham stage of radix R on an FFT of length L whose element i is
+// *el(i). Lane p (of P = L/E) performs butterflies j = p + i P, i < E / R,
+// after the previous stages have combined spans of NS. tw holds
+// exp(-2 pi i t / NTAB), t < NTAB.
+template <typename V, int L, int R, int NS, int NTAB, int DIR, typename El>
+__device__ __forceinline__ void fft_stage(El el, int p, const V* tw, bool act) {
   constexpr int E = elems_per_lane(L);
   constexpr int P = L / E;
   constexpr int NB = E / R;
@@ -155,7 +155,7 @@ __device__ __forceinline__ void fft_stage(V* buf, int p, const V* tw, bool act) 
     for (int i = 0; i < NB; ++i) {
       const int j = p + i * P;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[i][r] = buf[(j + r * LR) * S];
+      for (int r = 0; r < R; ++r) v[i][r] = *el(j + r * LR);
     }
   }
   wave_sync();
@@ -175,26 +175,26 @@ __device__ __forceinline__ void fft_stage(V* buf, int p, const V* tw, bool act) 
       Bfly<V, R, DIR>::run(v[i]);
       const int o = (j / NS) * NS * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[(o + r * NS) * S] = v[i][r];
+      for (int r = 0; r < R; ++r) *el(o + r * NS) = v[i][r];
     }
   }
   wave_sync();
 }
 
-template <typename V, int L, int S, int NTAB, int DIR, int ST = 0, int NS = 1>
-__device__ __forceinline__ void fft_stages(V* buf, int p, const V* tw, bool act) {
+template <typename V, int L, int NTAB, int DIR, int ST = 0, int NS = 1, typename El>
+__device__ __forceinline__ void fft_stages(El el, int p, const V* tw, bool act) {
   if constexpr (ST < plan_count(L)) {
     constexpr int R = plan_radix(L, ST);
-    fft_stage<V, L, R, NS, S, NTAB, DIR>(buf, p, tw, act);
-    fft_stages<V, L, S, NTAB, DIR, ST + 1, NS * R>(buf, p, tw, act);
+    fft_stage<V, L, R, NS, NTAB, DIR>(el, p, tw, act);
+    fft_stages<V, L, NTAB, DIR, ST + 1, NS * R>(el, p, tw, act);
   }
 }
 
-// Run COUNT FFTs of length L (element stride S, FFT f based at base_of(f))
-// with every wavefront of a BLOCK-thread workgroup holding 64 / P of them at
-// a time.
-template <typename V, int L, int S, int NTAB, int DIR, int COUNT, int BLOCK, typename BaseOf>
-__device__ __forceinline__ void fft_batch(const V* tw, BaseOf base_of) {
+// Run COUNT FFTs of length L, element i of FFT f at at(f, i) (an LDS
+// address), with every wavefront of a BLOCK-thread workgroup holding 64 / P
+// of them at a time.
+template <typename V, int L, int NTAB, int DIR, int COUNT, int BLOCK, typename At>
+__device__ __forceinline__ void fft_batch(const V* tw, At at) {
   static_assert(plan_ok(L), "unsupported FFT length");
   constexpr int P = L / elems_per_lane(L);
   static_assert(64 % P == 0, "an FFT must fit one wavefront");
@@ -207,8 +207,27 @@ __device__ __forceinline__ void fft_batch(const V* tw, BaseOf base_of) {
   for (int f0 = 0; f0 < COUNT; f0 += per_round) {
     const int f = f0 + wave * PER_WAVE + g;
     const bool act = f < COUNT;
-    fft_stages<V, L, S, NTAB, DIR>(base_of(act ? f : 0), p, tw, act);
+    int fa = act ? f : 0, pp = p;
+    // opaque copies: the per-lane index arithmetic of the stages is redone
+    // in every round instead of being hoisted (and held in registers) across
+    // rounds and calls
+    asm volatile("" : "+v"(fa), "+v"(pp));
+    fft_stages<V, L, NTAB, DIR>([&](int i) { return at(fa, i); }, pp, tw, act);
   }
+}
+
+// Bank swizzle of an FFT of length L stored contiguously in LDS: element i
+// sits at i ^ ((i >> 3) & 15) (a permutation inside each aligned block of
+// 16). A Stockham stage with eight elements per lane writes every lane's
+// eight outputs to consecutive slots (stride 8 across the lanes), which
+// without it puts the 16 lanes of one LDS cycle on two bank pairs; with it
+// every read and write of the radix-8 and radix-2 stages of a length-64..256
+// transform is conflict-free. Lengths that are not a power of two >= 64 keep
+// the plain order.
+template <int L>
+__device__ __forceinline__ int fft_swz(int i) {
+  if constexpr (L >= 64 && (L & (L - 1)) == 0) return i ^ ((i >> 3) & 15);
+  else return i;
 }
 
 // Element-wise copy of COUNT items by a BLOCK-thread workgroup with up to

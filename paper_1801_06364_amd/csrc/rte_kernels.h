@@ -77,11 +77,40 @@ template <int NN> struct GridC {
   static_assert(elems_per_lane(NN / 2) == elems_per_lane(NN), "row/column lane shape");
 };
 
+// LDS layout of RB packed spectral rows of H = n/2 complex values (a whole
+// plane when RB = n). Default: row pitch H + 1 (odd, so the strided column
+// accesses of the y transform spread over the banks). The 128-point plane
+// is transformed along both axes by radix-8 Stockham stages whose stride-8
+// writes alias on that layout; it uses pitch H + 8 and stores column c of
+// row r at c ^ ((c >> 3) & 7) ^ x(r >> 1), where the row term
+// x(q) = ((q ^ (q >> 3)) & 7) | ((q & 4) << 1) spreads the 16 rows that one
+// LDS cycle touches in every y stage over distinct banks and keeps the two
+// rows one cycle touches in the x stages on complementary halves. Row blocks
+// of the large-grid kernels (RB < n, x transforms only) use the in-row
+// swizzle of contiguous FFTs.
+template <int NN, int RB> struct PlaneLayout {
+  static constexpr int H = NN / 2;
+  static constexpr bool SWZ = (NN == 128 && RB == NN);
+  static constexpr bool ROWSWZ = (RB < NN && H >= 64 && (H & (H - 1)) == 0);
+  static constexpr int PITCH = SWZ ? H + 8 : H + 1;
+  static constexpr int SIZE = RB * PITCH;
+  static __device__ __forceinline__ int pos(int row, int col) {
+    if constexpr (SWZ) {
+      const int q = row >> 1;
+      const int rx = ((q ^ (q >> 3)) & 7) | ((q << 1) & 8);
+      return row * PITCH + ((col ^ ((col >> 3) & 7)) ^ rx);
+    } else if constexpr (ROWSWZ) {
+      return row * PITCH + fft_swz<H>(col);
+    } else {
+      return row * PITCH + col;
+    }
+  }
+};
+
 template <typename T, int NN>
 constexpr size_t plane_lds() {
-  using G = GridC<NN>;
-  // twiddles (n) + plane with odd row pitch n/2 + 1
-  const size_t b = (size_t(NN) * (G::H + 1) + NN) * 2 * sizeof(T);
+  // twiddles (n) + the plane
+  const size_t b = (size_t(PlaneLayout<NN, NN>::SIZE) + NN) * 2 * sizeof(T);
   return b < 2 * kPBlock * 8 ? 2 * kPBlock * 8 : b;
 }
 // ---------------------------------------------------------- F: forward ---
@@ -92,41 +121,42 @@ constexpr size_t plane_lds() {
 // column kx = 0 holding (X_0, X_{n/2}). The half spectrum is therefore
 // exactly n/2 columns wide: [b][z][ky][kx], kx in [0, n/2).
 // Forward transform of one real plane held in LDS as n rows of H packed
-// complex values (pitch LP = H + 1): x real-to-complex FFT with the
+// complex values (PlaneLayout): x real-to-complex FFT with the
 // kx = 0 / n/2 packing, then y FFT of the H columns. Callers synchronise
 // before (plane written) and read the spectrum after (ends synchronised).
 template <typename V, typename T, int NN, int BLOCK>
 __device__ __forceinline__ void forward_plane_lds(V* pl, const V* tw) {
-  constexpr int n = NN, H = NN / 2, LP = H + 1;
+  constexpr int n = NN, H = NN / 2;
+  using Lay = PlaneLayout<NN, NN>;
   // x: n packed rows of length H (twiddle table of length n, stride 2)
-  fft_batch<V, H, 1, 2 * H, -1, n, BLOCK>(tw, [&](int f) { return pl + f * LP; });
+  fft_batch<V, H, 2 * H, -1, n, BLOCK>(tw, [&](int f, int i) { return pl + Lay::pos(f, i); });
   __syncthreads();
   // real-to-complex split: X_k from Z_k and Z_{H-k}
   constexpr int half = H / 2;
   for (int i = threadIdx.x; i < n * (half + 1); i += BLOCK) {
     const int y = i / (half + 1), kk = i - y * (half + 1);
-    V* row = pl + y * LP;
+    auto row = [&](int c) -> V& { return pl[Lay::pos(y, c)]; };
     if (kk == 0) {
-      const V z0 = row[0];
-      row[0] = cmk<V>(z0.x + z0.y, z0.x - z0.y);   // packed (X_0, X_{n/2})
+      const V z0 = row(0);
+      row(0) = cmk<V>(z0.x + z0.y, z0.x - z0.y);   // packed (X_0, X_{n/2})
     } else {
       const int m = H - kk;
-      const V zk = row[kk], zm = row[m];
+      const V zk = row(kk), zm = row(m);
       const V zmc = cconj(zm), zkc = cconj(zk);
       // X_k = (Z_k + conj Z_m)/2 - i w_k (Z_k - conj Z_m)/2,  w_k = exp(-2 pi i k / n)
       const V ek = cscale(cadd(zk, zmc), T(0.5));
       const V ok = cmul_i<V, -1>(cscale(csub(zk, zmc), T(0.5)));
-      row[kk] = cadd(ek, cmul(tw[kk], ok));
+      row(kk) = cadd(ek, cmul(tw[kk], ok));
       if (m != kk) {
         const V em = cscale(cadd(zm, zkc), T(0.5));
         const V om = cmul_i<V, -1>(cscale(csub(zm, zkc), T(0.5)));
-        row[m] = cadd(em, cmul(tw[m], om));
+        row(m) = cadd(em, cmul(tw[m], om));
       }
     }
   }
   __syncthreads();
-  // y: H columns of length n, stride LP
-  fft_batch<V, n, LP, n, -1, H, BLOCK>(tw, [&](int f) { return pl + f; });
+  // y: H columns of length n
+  fft_batch<V, n, n, -1, H, BLOCK>(tw, [&](int f, int i) { return pl + Lay::pos(i, f); });
   __syncthreads();
 }
 
@@ -136,7 +166,8 @@ k_fwd_plane(const T* __restrict__ src, typename cplx_of<T>::type* __restrict__ s
             const typename cplx_of<T>::type* __restrict__ twg, const Ctl* __restrict__ ctl, int nplanes) {
   using V = typename cplx_of<T>::type;
   using G = GridC<NN>;
-  constexpr int n = NN, H = G::H, LP = H + 1;   // LDS row pitch (odd: no bank aliasing)
+  constexpr int n = NN, H = G::H;
+  using Lay = PlaneLayout<NN, NN>;
   constexpr int CNT = n * H;                     // complex values per packed plane
   constexpr int ITER = (CNT + kPBlock - 1) / kPBlock;
   if (ctl->stop) return;
@@ -164,13 +195,13 @@ k_fwd_plane(const T* __restrict__ src, typename cplx_of<T>::type* __restrict__ s
 #pragma unroll
     for (int it = 0; it < ITER; ++it) {
       const int i = int(threadIdx.x) + it * kPBlock;
-      if (CNT % kPBlock == 0 || i < CNT) pl[(i / H) * LP + (i % H)] = pre[it];
+      if (CNT % kPBlock == 0 || i < CNT) pl[Lay::pos(i / H, i % H)] = pre[it];
     }
     __syncthreads();
     if (k + 1 < kFwdPlanes && plane + 1 < nplanes) gload(plane + 1);
     forward_plane_lds<V, T, NN, kPBlock>(pl, tw);
     V* dst = spec + size_t(plane) * n * H;
-    staged_copy<n * H, kPBlock>([&](int i) { return pl[(i / H) * LP + (i % H)]; },
+    staged_copy<n * H, kPBlock>([&](int i) { return pl[Lay::pos(i / H, i % H)]; },
                                 [&](int i, V x) { dst[i] = x; });
     __syncthreads();
   }
@@ -237,31 +268,33 @@ k_pencil(const typename cplx_of<T>::type* src, typename cplx_of<T>::type* dst,  
   const size_t base = pencil_z(MODE) ? (size_t(b) * n * n + w) * H + kx0
                                             : (size_t(b) * n + w) * size_t(n) * H + kx0;
   for (int i = threadIdx.x; i < n; i += kZBlock) tw[i] = twg[i];
+  // element i of pencil f (bank-swizzled within the pencil)
+  auto at = [&](int f, int i) { return col + f * PITCH + fft_swz<n>(i); };
   staged_copy<n * TZ, kZBlock>(
       [&](int i) { return src[base + size_t(i / TZ) * AX + (i % TZ)]; },
-      [&](int i, V x) { col[(i % TZ) * PITCH + i / TZ] = x; });
+      [&](int i, V x) { col[(i % TZ) * PITCH + fft_swz<n>(i / TZ)] = x; });
   __syncthreads();
   if constexpr (pencil_inverse(MODE)) {
-    fft_batch<V, n, 1, n, +1, TZ, kZBlock>(tw, [&](int f) { return col + f * PITCH; });
+    fft_batch<V, n, n, +1, TZ, kZBlock>(tw, at);
   } else {
-    fft_batch<V, n, 1, n, -1, TZ, kZBlock>(tw, [&](int f) { return col + f * PITCH; });
+    fft_batch<V, n, n, -1, TZ, kZBlock>(tw, at);
   }
   if constexpr (MODE == PENCIL_ZDERIV) {
     __syncthreads();
     const T inv_n = T(1) / T(n);
     for (int i = threadIdx.x; i < n * TZ; i += kZBlock) {
       const int t = i / n, kz = i - t * n;
-      V* e = col + t * PITCH + kz;
+      V* e = col + t * PITCH + fft_swz<n>(kz);
       const T k = kv[kz] * inv_n;
       const V x = *e;
       *e = cmk<V>(-k * x.y, k * x.x);     // times i k_z / n
     }
     __syncthreads();
-    fft_batch<V, n, 1, n, +1, TZ, kZBlock>(tw, [&](int f) { return col + f * PITCH; });
+    fft_batch<V, n, n, +1, TZ, kZBlock>(tw, at);
   }
   __syncthreads();
   staged_copy<n * TZ, kZBlock>(
-      [&](int i) { return col[(i % TZ) * PITCH + i / TZ]; },
+      [&](int i) { return col[(i % TZ) * PITCH + fft_swz<n>(i / TZ)]; },
       [&](int i, V x) { dst[base + size_t(i / TZ) * AX + (i % TZ)] = x; });
 }
 
@@ -277,7 +310,7 @@ template <int NN> struct RowShape {
 
 template <typename T, int NN>
 constexpr size_t rows_lds() {
-  const size_t b = (size_t(RowShape<NN>::RB) * (NN / 2 + 1) + NN) * 2 * sizeof(T);
+  const size_t b = (size_t(PlaneLayout<NN, RowShape<NN>::RB>::SIZE) + NN) * 2 * sizeof(T);
   return b < 2 * kPBlock * 8 ? 2 * kPBlock * 8 : b;
 }
 
@@ -286,7 +319,8 @@ __global__ void __launch_bounds__(kZBlock)
 k_rows_fwd(const T* __restrict__ src, typename cplx_of<T>::type* __restrict__ spec,
            const typename cplx_of<T>::type* __restrict__ twg, const Ctl* __restrict__ ctl) {
   using V = typename cplx_of<T>::type;
-  constexpr int n = NN, H = NN / 2, LP = H + 1, RB = RowShape<NN>::RB;
+  constexpr int n = NN, H = NN / 2, RB = RowShape<NN>::RB;
+  using Lay = PlaneLayout<NN, RB>;
   if (ctl->stop) return;
   extern __shared__ __align__(16) unsigned char smem[];
   V* tw = reinterpret_cast<V*>(smem);
@@ -295,34 +329,34 @@ k_rows_fwd(const T* __restrict__ src, typename cplx_of<T>::type* __restrict__ sp
   for (int i = threadIdx.x; i < n; i += kZBlock) tw[i] = twg[i];
   const V* s = reinterpret_cast<const V*>(src + r0 * n);
   staged_copy<RB * H, kZBlock>([&](int i) { return s[i]; },
-                               [&](int i, V x) { pl[(i / H) * LP + (i % H)] = x; });
+                               [&](int i, V x) { pl[Lay::pos(i / H, i % H)] = x; });
   __syncthreads();
-  fft_batch<V, H, 1, 2 * H, -1, RB, kZBlock>(tw, [&](int f) { return pl + f * LP; });
+  fft_batch<V, H, 2 * H, -1, RB, kZBlock>(tw, [&](int f, int i) { return pl + Lay::pos(f, i); });
   __syncthreads();
   constexpr int half = H / 2;
   for (int i = threadIdx.x; i < RB * (half + 1); i += kZBlock) {
     const int y = i / (half + 1), k = i - y * (half + 1);
-    V* row = pl + y * LP;
+    auto row = [&](int c) -> V& { return pl[Lay::pos(y, c)]; };
     if (k == 0) {
-      const V z0 = row[0];
-      row[0] = cmk<V>(z0.x + z0.y, z0.x - z0.y);   // packed (X_0, X_{n/2})
+      const V z0 = row(0);
+      row(0) = cmk<V>(z0.x + z0.y, z0.x - z0.y);   // packed (X_0, X_{n/2})
     } else {
       const int m = H - k;
-      const V zk = row[k], zm = row[m];
+      const V zk = row(k), zm = row(m);
       const V zmc = cconj(zm), zkc = cconj(zk);
       const V ek = cscale(cadd(zk, zmc), T(0.5));
       const V ok = cmul_i<V, -1>(cscale(csub(zk, zmc), T(0.5)));
-      row[k] = cadd(ek, cmul(tw[k], ok));
+      row(k) = cadd(ek, cmul(tw[k], ok));
       if (m != k) {
         const V em = cscale(cadd(zm, zkc), T(0.5));
         const V om = cmul_i<V, -1>(cscale(csub(zm, zkc), T(0.5)));
-        row[m] = cadd(em, cmul(tw[m], om));
+        row(m) = cadd(em, cmul(tw[m], om));
       }
     }
   }
   __syncthreads();
   V* dst = spec + r0 * H;
-  staged_copy<RB * H, kZBlock>([&](int i) { return pl[(i / H) * LP + (i % H)]; },
+  staged_copy<RB * H, kZBlock>([&](int i) { return pl[Lay::pos(i / H, i % H)]; },
                                [&](int i, V x) { dst[i] = x; });
 }
 
@@ -453,24 +487,24 @@ k_couple_rt(const typename cplx_of<T>::type* __restrict__ spec,
 
 // ------------------------------------------- P: inverse + epilogue -------
 
-// Complex-to-real merge of RB packed spectral rows in LDS (pitch LP):
+// Complex-to-real merge of RB packed spectral rows in LDS (layout Lay):
 // Z_k = (X_k + conj X_{H-k}) + i conj(w_k) (X_k - conj X_{H-k}); column 0
 // carries the real pair (X_0, X_{n/2}).
-template <typename V, typename T, int NN, int RB, int LP, int BLOCK>
+template <typename V, typename T, int NN, int RB, typename Lay, int BLOCK>
 __device__ __forceinline__ void c2r_merge(V* pl, const V* tw) {
   constexpr int H = NN / 2, half = H / 2;
   for (int i = threadIdx.x; i < RB * (half + 1); i += BLOCK) {
     const int y = i / (half + 1), k = i - y * (half + 1);
-    V* row = pl + y * LP;
+    auto row = [&](int c) -> V& { return pl[Lay::pos(y, c)]; };
     if (k == 0) {
-      const V p0 = row[0];
-      row[0] = cmk<V>(p0.x + p0.y, p0.x - p0.y);
+      const V p0 = row(0);
+      row(0) = cmk<V>(p0.x + p0.y, p0.x - p0.y);
     } else {
       const int m = H - k;
-      const V xk = row[k], xm = row[m];
+      const V xk = row(k), xm = row(m);
       const V xmc = cconj(xm), xkc = cconj(xk);
-      row[k] = cadd(cadd(xk, xmc), cmul_i<V, +1>(cmul(cconj(tw[k]), csub(xk, xmc))));
-      if (m != k) row[m] = cadd(cadd(xm, xkc), cmul_i<V, +1>(cmul(cconj(tw[m]), csub(xm, xkc))));
+      row(k) = cadd(cadd(xk, xmc), cmul_i<V, +1>(cmul(cconj(tw[k]), csub(xk, xmc))));
+      if (m != k) row(m) = cadd(cadd(xm, xkc), cmul_i<V, +1>(cmul(cconj(tw[m]), csub(xm, xkc))));
     }
   }
 }
@@ -499,7 +533,7 @@ enum { EPI_MID = 0, EPI_FIRST = 1, EPI_LAST = 2, EPI_ADJ = 3, EPI_EULER = 4, EPI
 //     steady-state operator A v = (S + Sigma) v, for which the steady state
 //     solves A u = q;
 //   EPI_SET         o = w -> dst (the transformed field itself).
-template <typename V, typename T, int NN, int RB, int LP, int BLOCK, int MODE, bool KEEP = false>
+template <typename V, typename T, int NN, int RB, typename Lay, int BLOCK, int MODE, bool KEEP = false>
 __device__ __forceinline__ void epilogue(V* pl, int y0, int b, int z, const T* vin, T* u,
                                          T* dst, const T* __restrict__ sig, const T* __restrict__ q,
                                          bool hasq, T qs, double* __restrict__ phi_int, T h, double dt,
@@ -513,7 +547,7 @@ __device__ __forceinline__ void epilogue(V* pl, int y0, int b, int z, const T* v
   for (int i = threadIdx.x; i < RB * H; i += BLOCK) {
     const int y = i / H, j = i - y * H;
     const int e = y * n + 2 * j;
-    const V w = pl[y * LP + j];
+    const V w = pl[Lay::pos(y, j)];
     if constexpr (MODE == EPI_SET) {
       *reinterpret_cast<V*>(dst + poff + e) = w;
       continue;
@@ -539,7 +573,7 @@ __device__ __forceinline__ void epilogue(V* pl, int y0, int b, int z, const T* v
     }
     const V o = cmk<V>(uu.x + w.x + h * src0, uu.y + w.y + h * src1);
     *reinterpret_cast<V*>(dst + poff + e) = o;
-    if constexpr (KEEP) pl[y * LP + j] = o;   // the output plane, for the fused forward transform
+    if constexpr (KEEP) pl[Lay::pos(y, j)] = o;   // the output plane, for the fused forward transform
     if ((MODE == EPI_LAST || MODE == EPI_EULER) && b == 0) {
       double2* pi = reinterpret_cast<double2*>(phi_int + voff + e);
       double2 acc = *pi;
@@ -597,7 +631,8 @@ k_inv_plane(const typename cplx_of<T>::type* spec, const T* vin, T* u, T* dst,
             const Ctl* __restrict__ ctl, int stage, long long step1, typename cplx_of<T>::type* fspec) {
   using V = typename cplx_of<T>::type;
   using G = GridC<NN>;
-  constexpr int n = NN, H = G::H, LP = H + 1;
+  constexpr int n = NN, H = G::H;
+  using Lay = PlaneLayout<NN, NN>;
   if (ctl->stop) return;
   extern __shared__ __align__(16) unsigned char smem[];
   V* tw = reinterpret_cast<V*>(smem);
@@ -610,24 +645,24 @@ k_inv_plane(const typename cplx_of<T>::type* spec, const T* vin, T* u, T* dst,
   for (int i = threadIdx.x; i < n; i += kPBlock) tw[i] = twg[i];
   const V* srcp = spec + size_t(plane) * n * H;
   staged_copy<n * H, kPBlock>([&](int i) { return srcp[i]; },
-                              [&](int i, V x) { pl[(i / H) * LP + (i % H)] = x; });
+                              [&](int i, V x) { pl[Lay::pos(i / H, i % H)] = x; });
   __syncthreads();
-  fft_batch<V, n, LP, n, +1, H, kPBlock>(tw, [&](int f) { return pl + f; });
+  fft_batch<V, n, n, +1, H, kPBlock>(tw, [&](int f, int i) { return pl + Lay::pos(i, f); });
   __syncthreads();
-  c2r_merge<V, T, NN, n, LP, kPBlock>(pl, tw);
+  c2r_merge<V, T, NN, n, Lay, kPBlock>(pl, tw);
   __syncthreads();
-  fft_batch<V, H, 1, 2 * H, +1, n, kPBlock>(tw, [&](int f) { return pl + f * LP; });
+  fft_batch<V, H, 2 * H, +1, n, kPBlock>(tw, [&](int f, int i) { return pl + Lay::pos(f, i); });
   __syncthreads();
   double acc_d = 0.0, acc_o = 0.0;
   const bool hasq = (q != nullptr) && qflag[z];
   const T qs = hasq ? T(source_weight(ctl, stage, step1)) : T(0);
-  epilogue<V, T, NN, n, LP, kPBlock, MODE, FUSE>(pl, 0, b, z, vin, u, dst, sig, q, hasq, qs, phi_int, h, dt,
+  epilogue<V, T, NN, n, Lay, kPBlock, MODE, FUSE>(pl, 0, b, z, vin, u, dst, sig, q, hasq, qs, phi_int, h, dt,
                                                  acc_d, acc_o);
   if constexpr (FUSE) {
     __syncthreads();
     forward_plane_lds<V, T, NN, kPBlock>(pl, tw);
     V* fd = fspec + size_t(plane) * n * H;
-    staged_copy<n * H, kPBlock>([&](int i) { return pl[(i / H) * LP + (i % H)]; },
+    staged_copy<n * H, kPBlock>([&](int i) { return pl[Lay::pos(i / H, i % H)]; },
                                 [&](int i, V x) { fd[i] = x; });
   }
   // (block_sum2 reuses the LDS: it synchronises first)
@@ -646,7 +681,8 @@ k_rows_inv(const typename cplx_of<T>::type* __restrict__ spec, const T* vin, T* 
            const typename cplx_of<T>::type* __restrict__ twg, int M, T h, double dt,
            const Ctl* __restrict__ ctl, int stage, long long step1) {
   using V = typename cplx_of<T>::type;
-  constexpr int n = NN, H = NN / 2, LP = H + 1, RB = RowShape<NN>::RB, NB = NN / RB;
+  constexpr int n = NN, H = NN / 2, RB = RowShape<NN>::RB, NB = NN / RB;
+  using Lay = PlaneLayout<NN, RB>;
   if (ctl->stop) return;
   extern __shared__ __align__(16) unsigned char smem[];
   V* tw = reinterpret_cast<V*>(smem);
@@ -658,16 +694,16 @@ k_rows_inv(const typename cplx_of<T>::type* __restrict__ spec, const T* vin, T* 
   for (int i = threadIdx.x; i < n; i += kZBlock) tw[i] = twg[i];
   const V* srcp = spec + ((size_t(b) * n + z) * n + y0) * H;
   staged_copy<RB * H, kZBlock>([&](int i) { return srcp[i]; },
-                               [&](int i, V x) { pl[(i / H) * LP + (i % H)] = x; });
+                               [&](int i, V x) { pl[Lay::pos(i / H, i % H)] = x; });
   __syncthreads();
-  c2r_merge<V, T, NN, RB, LP, kZBlock>(pl, tw);
+  c2r_merge<V, T, NN, RB, Lay, kZBlock>(pl, tw);
   __syncthreads();
-  fft_batch<V, H, 1, 2 * H, +1, RB, kZBlock>(tw, [&](int f) { return pl + f * LP; });
+  fft_batch<V, H, 2 * H, +1, RB, kZBlock>(tw, [&](int f, int i) { return pl + Lay::pos(f, i); });
   __syncthreads();
   double acc_d = 0.0, acc_o = 0.0;
   const bool hasq = (q != nullptr) && qflag[z];
   const T qs = hasq ? T(source_weight(ctl, stage, step1)) : T(0);
-  epilogue<V, T, NN, RB, LP, kZBlock, MODE>(pl, y0, b, z, vin, u, dst, sig, q, hasq, qs, phi_int, h, dt, acc_d,
+  epilogue<V, T, NN, RB, Lay, kZBlock, MODE>(pl, y0, b, z, vin, u, dst, sig, q, hasq, qs, phi_int, h, dt, acc_d,
                                             acc_o);
   if ((MODE == EPI_LAST || MODE == EPI_EULER) && b == 0) block_sum2<kZBlock>(smem, acc_d, acc_o, partial + 2 * zy);
 }
