@@ -137,29 +137,58 @@ template <typename V, int DIR> struct Bfly<V, 8, DIR> {
   }
 };
 
-// One Stockham stage of radix R on an FFT of length L whose element i is
-// *el(i). Lane p (of P = L/E) performs butterflies j = p + i P, i < E / R,
-// after the previous stages have combined spans of NS. tw holds
-// exp(-2 pi i t / NTAB), t < NTAB.
-template <typename V, int L, int R, int NS, int NTAB, int DIR, typename El>
-__device__ __forceinline__ void fft_stage(El el, int p, const V* tw, bool act) {
+// Element accessors. An FFT pass addresses element i of FFT f through an
+// accessor `at` with i split as i = a + b: `a` holds the lane-dependent
+// part and `b` a compile-time part whose bits are disjoint from those of a
+// (for power-of-two lengths). at.lane(f, a) returns the per-lane state of
+// one access pattern and at.elem(lane, b) the element's LDS address, so a
+// swizzled layout costs one XOR per access (kXor: the layout needs the
+// disjoint split; otherwise it is affine and any split works).
+//
+// Affine layout: element i of FFT f at p0 + f FS + i IS.
+template <typename V, int FS, int IS>
+struct AffineAt {
+  static constexpr bool kXor = false;
+  V* p0;
+  struct Lane { V* q; };
+  __device__ __forceinline__ Lane lane(int f, int a) const { return {p0 + f * FS + a * IS}; }
+  __device__ __forceinline__ V* elem(Lane l, int b) const { return l.q + b * IS; }
+};
+
+// One Stockham stage of radix R on an FFT of length L. Lane p (of
+// P = L/E) performs butterflies j = p + i P, i < E / R, after the previous
+// stages have combined spans of NS; butterfly j reads elements j + r L/R and
+// writes o + r NS, o = (j / NS) NS R + j % NS. tw holds exp(-2 pi i t / NTAB),
+// t < NTAB.
+template <typename V, int L, int R, int NS, int NTAB, int DIR, typename At>
+__device__ __forceinline__ void fft_stage(const At& at, int f, int p, const V* tw, bool act) {
   constexpr int E = elems_per_lane(L);
   constexpr int P = L / E;
   constexpr int NB = E / R;
   constexpr int LR = L / R;
   constexpr int SPAN = (NTAB / (NS * R));
   static_assert(E % R == 0, "radix must divide elements per lane");
+  static_assert(!At::kXor || (L & (L - 1)) == 0, "swizzled layouts need power-of-two lengths");
   V v[NB][R];
   if (act) {
+    // reads: j + r LR = p + (i P + r LR), the constant part a multiple of P
+    const auto lr = at.lane(f, p);
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
-      const int j = p + i * P;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[i][r] = *el(j + r * LR);
+      for (int r = 0; r < R; ++r) v[i][r] = *at.elem(lr, i * P + r * LR);
     }
   }
   wave_sync();
   if (act) {
+    // writes: o + r NS split into a lane part and a constant part (power-of-two
+    // lengths: NS and P are powers of two, so one divides the other)
+    constexpr bool kSplit = (L & (L - 1)) == 0;
+    int aw = 0;
+    if constexpr (!kSplit) aw = 0;
+    else if constexpr (NS <= P) aw = (p / NS) * NS * R + p % NS;
+    else aw = p;
+    const auto lw = at.lane(f, aw);
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
       const int j = p + i * P;
@@ -173,31 +202,33 @@ __device__ __forceinline__ void fft_stage(El el, int p, const V* tw, bool act) {
         }
       }
       Bfly<V, R, DIR>::run(v[i]);
-      const int o = (j / NS) * NS * R + k;
+      int ob;
+      if constexpr (!kSplit) ob = (j / NS) * NS * R + k;
+      else if constexpr (NS <= P) ob = i * P * R;
+      else ob = ((i * P) / NS) * NS * R + (i * P) % NS;
 #pragma unroll
-      for (int r = 0; r < R; ++r) *el(o + r * NS) = v[i][r];
+      for (int r = 0; r < R; ++r) *at.elem(lw, ob + r * NS) = v[i][r];
     }
   }
   wave_sync();
 }
 
-template <typename V, int L, int NTAB, int DIR, int ST = 0, int NS = 1, typename El>
-__device__ __forceinline__ void fft_stages(El el, int p, const V* tw, bool act) {
+template <typename V, int L, int NTAB, int DIR, int ST = 0, int NS = 1, typename At>
+__device__ __forceinline__ void fft_stages(const At& at, int f, int p, const V* tw, bool act) {
   if constexpr (ST < plan_count(L)) {
     constexpr int R = plan_radix(L, ST);
-    fft_stage<V, L, R, NS, NTAB, DIR>(el, p, tw, act);
-    fft_stages<V, L, NTAB, DIR, ST + 1, NS * R>(el, p, tw, act);
+    fft_stage<V, L, R, NS, NTAB, DIR>(at, f, p, tw, act);
+    fft_stages<V, L, NTAB, DIR, ST + 1, NS * R>(at, f, p, tw, act);
   }
 }
 
-// Run COUNT FFTs of length L, element i of FFT f at at(f, i) (an LDS
-// address), with every wavefront of a BLOCK-thread workgroup holding 64 / P
-// of them at a time.
+// Run COUNT FFTs of length L through accessor `at` with every wavefront of a
+// BLOCK-thread workgroup holding 64 / P of them at a time.
 template <typename V, int L, int NTAB, int DIR, int COUNT, int BLOCK, typename At>
-__device__ __forceinline__ void fft_batch(const V* tw, At at) {
+__device__ __forceinline__ void fft_batch(const V* tw, const At& at) {
   static_assert(plan_ok(L), "unsupported FFT length");
   constexpr int P = L / elems_per_lane(L);
-  static_assert(64 % P == 0, "an FFT must fit one wavefront");
+  static_assert(64 % P == 0 && (P & (P - 1)) == 0, "an FFT must fit one wavefront");
   constexpr int PER_WAVE = 64 / P;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -210,9 +241,10 @@ __device__ __forceinline__ void fft_batch(const V* tw, At at) {
     int fa = act ? f : 0, pp = p;
     // opaque copies: the per-lane index arithmetic of the stages is redone
     // in every round instead of being hoisted (and held in registers) across
-    // rounds and calls
+    // rounds and calls; the mask restores what is known of the lane index
     asm volatile("" : "+v"(fa), "+v"(pp));
-    fft_stages<V, L, NTAB, DIR>([&](int i) { return at(fa, i); }, pp, tw, act);
+    pp &= P - 1;
+    fft_stages<V, L, NTAB, DIR>(at, fa, pp, tw, act);
   }
 }
 
@@ -229,6 +261,21 @@ __device__ __forceinline__ int fft_swz(int i) {
   if constexpr (L >= 64 && (L & (L - 1)) == 0) return i ^ ((i >> 3) & 15);
   else return i;
 }
+
+// Contiguous FFTs of length L with the swizzle above: element i of FFT f at
+// p0 + f PITCH + fft_swz<L>(i) (the swizzle is linear over GF(2), so it
+// splits over the disjoint parts a and b).
+template <typename V, int L, int PITCH>
+struct SwzAt {
+  static constexpr bool kXor = (L >= 64 && (L & (L - 1)) == 0);
+  V* p0;
+  struct Lane { V* q; int x; };
+  __device__ __forceinline__ Lane lane(int f, int a) const { return {p0 + f * PITCH, fft_swz<L>(a)}; }
+  __device__ __forceinline__ V* elem(Lane l, int b) const {
+    if constexpr (kXor) return l.q + (l.x ^ fft_swz<L>(b));
+    else return l.q + l.x + b;
+  }
+};
 
 // Element-wise copy of COUNT items by a BLOCK-thread workgroup with up to
 // 16 loads per thread in flight before the matching stores, so global

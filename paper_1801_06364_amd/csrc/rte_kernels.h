@@ -94,16 +94,43 @@ template <int NN, int RB> struct PlaneLayout {
   static constexpr bool ROWSWZ = (RB < NN && H >= 64 && (H & (H - 1)) == 0);
   static constexpr int PITCH = SWZ ? H + 8 : H + 1;
   static constexpr int SIZE = RB * PITCH;
+  // column swizzle and row-pair term of the 128-point plane (both linear
+  // over GF(2), so they split over disjoint index parts)
+  static __device__ __forceinline__ int cs(int c) { return c ^ ((c >> 3) & 7); }
+  static __device__ __forceinline__ int rx(int r) {
+    const int q = r >> 1;
+    return ((q ^ (q >> 3)) & 7) | ((q << 1) & 8);
+  }
   static __device__ __forceinline__ int pos(int row, int col) {
-    if constexpr (SWZ) {
-      const int q = row >> 1;
-      const int rx = ((q ^ (q >> 3)) & 7) | ((q << 1) & 8);
-      return row * PITCH + ((col ^ ((col >> 3) & 7)) ^ rx);
-    } else if constexpr (ROWSWZ) {
-      return row * PITCH + fft_swz<H>(col);
-    } else {
-      return row * PITCH + col;
-    }
+    if constexpr (SWZ) return row * PITCH + (cs(col) ^ rx(row));
+    else if constexpr (ROWSWZ) return row * PITCH + fft_swz<H>(col);
+    else return row * PITCH + col;
+  }
+  // x transforms of the 128-point plane: FFT f = row f, element i = column i
+  template <typename V> struct XSwz {
+    static constexpr bool kXor = true;
+    V* p0;
+    struct Lane { V* q; int x; };
+    __device__ __forceinline__ Lane lane(int f, int a) const { return {p0 + f * PITCH, cs(a) ^ rx(f)}; }
+    __device__ __forceinline__ V* elem(Lane l, int b) const { return l.q + (l.x ^ cs(b)); }
+  };
+  // y transforms of the 128-point plane: FFT f = column f, element i = row i
+  template <typename V> struct YSwz {
+    static constexpr bool kXor = true;
+    V* p0;
+    struct Lane { V* q; int x; };
+    __device__ __forceinline__ Lane lane(int f, int a) const { return {p0 + a * PITCH, cs(f) ^ rx(a)}; }
+    __device__ __forceinline__ V* elem(Lane l, int b) const { return l.q + b * PITCH + (l.x ^ rx(b)); }
+  };
+  // accessors of the row (x) and column (y) transforms
+  template <typename V> static __device__ __forceinline__ auto xat(V* pl) {
+    if constexpr (SWZ) return XSwz<V>{pl};
+    else if constexpr (ROWSWZ) return SwzAt<V, H, PITCH>{pl};
+    else return AffineAt<V, PITCH, 1>{pl};
+  }
+  template <typename V> static __device__ __forceinline__ auto yat(V* pl) {
+    if constexpr (SWZ) return YSwz<V>{pl};
+    else return AffineAt<V, 1, PITCH>{pl};
   }
 };
 
@@ -129,7 +156,7 @@ __device__ __forceinline__ void forward_plane_lds(V* pl, const V* tw) {
   constexpr int n = NN, H = NN / 2;
   using Lay = PlaneLayout<NN, NN>;
   // x: n packed rows of length H (twiddle table of length n, stride 2)
-  fft_batch<V, H, 2 * H, -1, n, BLOCK>(tw, [&](int f, int i) { return pl + Lay::pos(f, i); });
+  fft_batch<V, H, 2 * H, -1, n, BLOCK>(tw, Lay::xat(pl));
   __syncthreads();
   // real-to-complex split: X_k from Z_k and Z_{H-k}
   constexpr int half = H / 2;
@@ -156,7 +183,7 @@ __device__ __forceinline__ void forward_plane_lds(V* pl, const V* tw) {
   }
   __syncthreads();
   // y: H columns of length n
-  fft_batch<V, n, n, -1, H, BLOCK>(tw, [&](int f, int i) { return pl + Lay::pos(i, f); });
+  fft_batch<V, n, n, -1, H, BLOCK>(tw, Lay::yat(pl));
   __syncthreads();
 }
 
@@ -269,7 +296,7 @@ k_pencil(const typename cplx_of<T>::type* src, typename cplx_of<T>::type* dst,  
                                             : (size_t(b) * n + w) * size_t(n) * H + kx0;
   for (int i = threadIdx.x; i < n; i += kZBlock) tw[i] = twg[i];
   // element i of pencil f (bank-swizzled within the pencil)
-  auto at = [&](int f, int i) { return col + f * PITCH + fft_swz<n>(i); };
+  const SwzAt<V, n, PITCH> at{col};
   staged_copy<n * TZ, kZBlock>(
       [&](int i) { return src[base + size_t(i / TZ) * AX + (i % TZ)]; },
       [&](int i, V x) { col[(i % TZ) * PITCH + fft_swz<n>(i / TZ)] = x; });
@@ -331,7 +358,7 @@ k_rows_fwd(const T* __restrict__ src, typename cplx_of<T>::type* __restrict__ sp
   staged_copy<RB * H, kZBlock>([&](int i) { return s[i]; },
                                [&](int i, V x) { pl[Lay::pos(i / H, i % H)] = x; });
   __syncthreads();
-  fft_batch<V, H, 2 * H, -1, RB, kZBlock>(tw, [&](int f, int i) { return pl + Lay::pos(f, i); });
+  fft_batch<V, H, 2 * H, -1, RB, kZBlock>(tw, Lay::xat(pl));
   __syncthreads();
   constexpr int half = H / 2;
   for (int i = threadIdx.x; i < RB * (half + 1); i += kZBlock) {
@@ -647,11 +674,11 @@ k_inv_plane(const typename cplx_of<T>::type* spec, const T* vin, T* u, T* dst,
   staged_copy<n * H, kPBlock>([&](int i) { return srcp[i]; },
                               [&](int i, V x) { pl[Lay::pos(i / H, i % H)] = x; });
   __syncthreads();
-  fft_batch<V, n, n, +1, H, kPBlock>(tw, [&](int f, int i) { return pl + Lay::pos(i, f); });
+  fft_batch<V, n, n, +1, H, kPBlock>(tw, Lay::yat(pl));
   __syncthreads();
   c2r_merge<V, T, NN, n, Lay, kPBlock>(pl, tw);
   __syncthreads();
-  fft_batch<V, H, 2 * H, +1, n, kPBlock>(tw, [&](int f, int i) { return pl + Lay::pos(f, i); });
+  fft_batch<V, H, 2 * H, +1, n, kPBlock>(tw, Lay::xat(pl));
   __syncthreads();
   double acc_d = 0.0, acc_o = 0.0;
   const bool hasq = (q != nullptr) && qflag[z];
@@ -698,7 +725,7 @@ k_rows_inv(const typename cplx_of<T>::type* __restrict__ spec, const T* vin, T* 
   __syncthreads();
   c2r_merge<V, T, NN, RB, Lay, kZBlock>(pl, tw);
   __syncthreads();
-  fft_batch<V, H, 2 * H, +1, RB, kZBlock>(tw, [&](int f, int i) { return pl + Lay::pos(f, i); });
+  fft_batch<V, H, 2 * H, +1, RB, kZBlock>(tw, Lay::xat(pl));
   __syncthreads();
   double acc_d = 0.0, acc_o = 0.0;
   const bool hasq = (q != nullptr) && qflag[z];
