@@ -142,6 +142,40 @@ constexpr size_t plane_lds() {
 }
 // ---------------------------------------------------------- F: forward ---
 
+// Real-to-complex split of RB rows of packed x transforms Z (layout Lay):
+// X_k = (Z_k + conj Z_m)/2 - i w_k (Z_k - conj Z_m)/2, m = H - k,
+// w_k = exp(-2 pi i k / n); column 0 becomes the real pair (X_0, X_{n/2}).
+// H/2 lanes per row: lane k > 0 does the pair (k, H - k), lane 0 column 0
+// and the self-paired column H/2.
+template <typename V, typename T, int NN, int RB, typename Lay, int BLOCK>
+__device__ __forceinline__ void r2c_split(V* pl, const V* tw) {
+  constexpr int H = NN / 2, half = H / 2;
+  for (int i = threadIdx.x; i < RB * half; i += BLOCK) {
+    const int y = i / half, kk = i - y * half;
+    auto row = [&](int c) -> V& { return pl[Lay::pos(y, c)]; };
+    auto pair = [&](int k) {
+      const int m = H - k;
+      const V zk = row(k), zm = row(m);
+      const V zmc = cconj(zm), zkc = cconj(zk);
+      const V ek = cscale(cadd(zk, zmc), T(0.5));
+      const V ok = cmul_i<V, -1>(cscale(csub(zk, zmc), T(0.5)));
+      row(k) = cadd(ek, cmul(tw[k], ok));
+      if (m != k) {
+        const V em = cscale(cadd(zm, zkc), T(0.5));
+        const V om = cmul_i<V, -1>(cscale(csub(zm, zkc), T(0.5)));
+        row(m) = cadd(em, cmul(tw[m], om));
+      }
+    };
+    if (kk == 0) {
+      const V z0 = row(0);
+      row(0) = cmk<V>(z0.x + z0.y, z0.x - z0.y);   // packed (X_0, X_{n/2})
+      pair(half);
+    } else {
+      pair(kk);
+    }
+  }
+}
+
 // The x transform of a real row has real kx = 0 and kx = n/2 entries; both
 // have zero x wavenumber (the Nyquist one by the Nyquist rule), so every
 // later operator treats them alike and they travel packed as one complex
@@ -158,29 +192,7 @@ __device__ __forceinline__ void forward_plane_lds(V* pl, const V* tw) {
   // x: n packed rows of length H (twiddle table of length n, stride 2)
   fft_batch<V, H, 2 * H, -1, n, BLOCK>(tw, Lay::xat(pl));
   __syncthreads();
-  // real-to-complex split: X_k from Z_k and Z_{H-k}
-  constexpr int half = H / 2;
-  for (int i = threadIdx.x; i < n * (half + 1); i += BLOCK) {
-    const int y = i / (half + 1), kk = i - y * (half + 1);
-    auto row = [&](int c) -> V& { return pl[Lay::pos(y, c)]; };
-    if (kk == 0) {
-      const V z0 = row(0);
-      row(0) = cmk<V>(z0.x + z0.y, z0.x - z0.y);   // packed (X_0, X_{n/2})
-    } else {
-      const int m = H - kk;
-      const V zk = row(kk), zm = row(m);
-      const V zmc = cconj(zm), zkc = cconj(zk);
-      // X_k = (Z_k + conj Z_m)/2 - i w_k (Z_k - conj Z_m)/2,  w_k = exp(-2 pi i k / n)
-      const V ek = cscale(cadd(zk, zmc), T(0.5));
-      const V ok = cmul_i<V, -1>(cscale(csub(zk, zmc), T(0.5)));
-      row(kk) = cadd(ek, cmul(tw[kk], ok));
-      if (m != kk) {
-        const V em = cscale(cadd(zm, zkc), T(0.5));
-        const V om = cmul_i<V, -1>(cscale(csub(zm, zkc), T(0.5)));
-        row(m) = cadd(em, cmul(tw[m], om));
-      }
-    }
-  }
+  r2c_split<V, T, NN, n, Lay, BLOCK>(pl, tw);
   __syncthreads();
   // y: H columns of length n
   fft_batch<V, n, n, -1, H, BLOCK>(tw, Lay::yat(pl));
@@ -360,27 +372,7 @@ k_rows_fwd(const T* __restrict__ src, typename cplx_of<T>::type* __restrict__ sp
   __syncthreads();
   fft_batch<V, H, 2 * H, -1, RB, kZBlock>(tw, Lay::xat(pl));
   __syncthreads();
-  constexpr int half = H / 2;
-  for (int i = threadIdx.x; i < RB * (half + 1); i += kZBlock) {
-    const int y = i / (half + 1), k = i - y * (half + 1);
-    auto row = [&](int c) -> V& { return pl[Lay::pos(y, c)]; };
-    if (k == 0) {
-      const V z0 = row(0);
-      row(0) = cmk<V>(z0.x + z0.y, z0.x - z0.y);   // packed (X_0, X_{n/2})
-    } else {
-      const int m = H - k;
-      const V zk = row(k), zm = row(m);
-      const V zmc = cconj(zm), zkc = cconj(zk);
-      const V ek = cscale(cadd(zk, zmc), T(0.5));
-      const V ok = cmul_i<V, -1>(cscale(csub(zk, zmc), T(0.5)));
-      row(k) = cadd(ek, cmul(tw[k], ok));
-      if (m != k) {
-        const V em = cscale(cadd(zm, zkc), T(0.5));
-        const V om = cmul_i<V, -1>(cscale(csub(zm, zkc), T(0.5)));
-        row(m) = cadd(em, cmul(tw[m], om));
-      }
-    }
-  }
+  r2c_split<V, T, NN, RB, Lay, kZBlock>(pl, tw);
   __syncthreads();
   V* dst = spec + r0 * H;
   staged_copy<RB * H, kZBlock>([&](int i) { return pl[Lay::pos(i / H, i % H)]; },
@@ -520,18 +512,24 @@ k_couple_rt(const typename cplx_of<T>::type* __restrict__ spec,
 template <typename V, typename T, int NN, int RB, typename Lay, int BLOCK>
 __device__ __forceinline__ void c2r_merge(V* pl, const V* tw) {
   constexpr int H = NN / 2, half = H / 2;
-  for (int i = threadIdx.x; i < RB * (half + 1); i += BLOCK) {
-    const int y = i / (half + 1), k = i - y * (half + 1);
+  // H/2 lanes per row: lane k > 0 does the pair (k, H - k), lane 0 column 0
+  // and the self-paired column H/2
+  for (int i = threadIdx.x; i < RB * half; i += BLOCK) {
+    const int y = i / half, kk = i - y * half;
     auto row = [&](int c) -> V& { return pl[Lay::pos(y, c)]; };
-    if (k == 0) {
-      const V p0 = row(0);
-      row(0) = cmk<V>(p0.x + p0.y, p0.x - p0.y);
-    } else {
+    auto pair = [&](int k) {
       const int m = H - k;
       const V xk = row(k), xm = row(m);
       const V xmc = cconj(xm), xkc = cconj(xk);
       row(k) = cadd(cadd(xk, xmc), cmul_i<V, +1>(cmul(cconj(tw[k]), csub(xk, xmc))));
       if (m != k) row(m) = cadd(cadd(xm, xkc), cmul_i<V, +1>(cmul(cconj(tw[m]), csub(xm, xkc))));
+    };
+    if (kk == 0) {
+      const V p0 = row(0);
+      row(0) = cmk<V>(p0.x + p0.y, p0.x - p0.y);
+      pair(half);
+    } else {
+      pair(kk);
     }
   }
 }
