@@ -57,6 +57,8 @@ CASES = [
     ("paper_pml_steady", 32, 15),   # forward Euler (eq. 11), source, layer
     ("paper_transient", 16, 4),     # P_21 (484 moments), two regions, Euler
     ("paper_transient", 32, 3),
+    ("p7_spheres", 64, 4),      # 64-point plane passes (bank-swizzled LDS layout)
+    ("paper_pml_steady", 64, 5),
     ("p1_gauss", 128, 4),       # 128-point plane passes (bank-swizzled LDS layout)
     ("p7_spheres", 128, 1),     # the full 128^3 / P_7 workload, one step
 ]
