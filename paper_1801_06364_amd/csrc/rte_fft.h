@@ -7,8 +7,10 @@
 // each lane holds E elements in registers per stage (E = 8 for powers of
 // two, 24 when L has a factor 3). Every stage only exchanges data among
 // lanes of the same wavefront, so stages synchronise with a wavefront
-// barrier instead of a workgroup barrier. Lengths, radices, strides and
-// twiddle spans are template constants, so all index arithmetic folds.
+// barrier instead of a workgroup barrier. Lengths, radices and twiddle
+// spans are template constants; the LDS layout enters through an element
+// accessor (affine, or bank-swizzled by a GF(2)-linear map), so each access
+// costs at most one XOR beyond a per-lane base.
 #pragma once
 
 #include <hip/hip_runtime.h>

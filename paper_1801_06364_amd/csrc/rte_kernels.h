@@ -28,7 +28,9 @@
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
 // L2. Tiles that share data (neighbouring kx tiles in D, the moments of one
 // z-plane that read the same loss map in P) are remapped so that
-// consecutive logical tiles run on the same XCD.
+// consecutive logical tiles run on the same XCD. Planes and pencils sit in
+// LDS in bank-swizzled layouts (PlaneLayout, fft_swz) so that the Stockham
+// stages run without bank conflicts.
 #pragma once
 
 #include <hip/hip_runtime.h>
