@@ -39,9 +39,6 @@
 #include "rte_fft.h"
 #include "rte_internal.h"
 
-#ifndef RTE_ZBUDGET
-#define RTE_ZBUDGET (64 * 1024)
-#endif
 #ifndef RTE_PBLOCK
 #define RTE_PBLOCK 512
 #endif
