@@ -648,8 +648,9 @@ def main():
     ap.add_argument("--steady-march-limit", type=float, default=60.0)
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: the hot path is a single-GPU solve; "
-              "multi-GPU runs are not part of this build", file=sys.stderr)
+        print("bench.py measures one GPU only: the hot path is a single-GPU solve "
+              "and no multi-GPU path is implemented (independent solves shard one "
+              "per GPU without exchange)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
