@@ -81,7 +81,8 @@ typedef struct {
   int32_t scheme;          /* RTE_RK4 (classic four-stage, default) or
                               RTE_EULER (the first-order explicit step of
                               eq. 11: u <- u + dt f(u), one stage per step)  */
-  const int64_t* det_index;/* n_det linear voxel indices (z*n+y)*n+x, host    */
+  const int64_t* det_index;/* n_det distinct linear voxel indices (z*n+y)*n+x,
+                              host, copied at create                         */
   int64_t record_steps;    /* capacity of the per-step record (readings,
                               residuals); later steps run unrecorded         */
 } rte_config;
@@ -105,19 +106,30 @@ size_t rte_workspace_bytes(const rte_config* cfg);
 /* Validate, build the FP64 tables (streaming coefficients of eq. 6 in the
  * real basis, twiddles, wavenumbers, per-degree losses with the absorbing
  * layer of eq. 12), carve the workspace and upload the medium and state.
- * hip_stream is a hipStream_t (NULL = the default stream). On success
- * *out receives a handle owned by the library until rte_destroy. */
+ * The problem statement is that of Sec. II: medium (eqs. 1-2, 5), source
+ * and initial radiance as moments (eqs. 3-4), order N of the truncation
+ * (Sec. II.A), real domain inside the computational domain with an
+ * absorbing layer (Sec. II.B, eq. 12). hip_stream is a hipStream_t (NULL =
+ * the default stream). On success *out receives a handle owned by the
+ * library until rte_destroy. RTE_EINVAL for an invalid configuration or
+ * medium, a detector index outside the grid or one listed twice;
+ * RTE_ENOMEM for a missing, misaligned or too small workspace; nothing is
+ * written to the device before these checks pass. */
 int rte_create(const rte_config* cfg, const rte_medium* med, void* dev_ws,
                size_t ws_bytes, void* hip_stream, rte_handle** out);
 
-/* Queue nsteps >= 0 full RK4 steps (asynchronous). After each step the
- * fluence psi_{0,0} at the detectors, the FP64 time-integrated fluence
- * (+= dt * psi_{0,0}) and the relative fluence change
+/* Queue nsteps >= 0 full time steps (asynchronous): the transient
+ * solution of Sec. II.A (the paper's first-order step is eq. 11; the
+ * operator of each stage is the three-part application of Sec. III). After
+ * each step the fluence psi_{0,0} at the detectors (time-resolved readings,
+ * as with the TCSPC measurements of Sec. II.A), the FP64 time-integrated
+ * fluence (+= dt * psi_{0,0}) and the relative fluence change
  * ||phi_n - phi_{n-1}||_2 / ||phi_n||_2 are updated on the device. Once a
  * non-finite value is seen the remaining queued steps do nothing. */
 int rte_step(rte_handle* h, int64_t nsteps);
 
-/* March until the relative fluence change of a step drops below steady_tol
+/* Steady state by marching the transient solution (Sec. II.A, Sec. III.B):
+ * march until the relative fluence change of a step drops below steady_tol
  * (> 0) or max_steps steps have run. The step that meets the tolerance is
  * the last one applied (later queued steps are skipped on the device).
  * *steps_taken receives the number of steps applied by this call.
@@ -125,27 +137,49 @@ int rte_step(rte_handle* h, int64_t nsteps);
 int rte_run(rte_handle* h, int64_t max_steps, double steady_tol,
             int64_t* steps_taken);
 
-/* Copy the fluence psi_{0,0} (which = RTE_FLUENCE_NOW) or the integrated
- * fluence (RTE_FLUENCE_INTEGRATED) to a caller-owned FP64 host buffer of
+/* Copy the fluence psi_{0,0} (which = RTE_FLUENCE_NOW; the internal fluence
+ * of Sec. III.A and III.B, the l = 0 moment of eq. 3) or the time-integrated
+ * fluence (RTE_FLUENCE_INTEGRATED; the steady-state fluence of a pulse by
+ * time integration, Sec. II.A) to a caller-owned FP64 host buffer of
  * len >= n^3 elements. Synchronises the stream. */
 int rte_fluence(rte_handle* h, int which, double* out, size_t len);
 
 /* Copy min(steps recorded, len / n_det) rows of detector readings
- * [step][det] (FP64) into out; *rows receives the row count. */
+ * [step][det] (FP64; fluence at the detector voxels after each step, the
+ * time-domain measurements of Sec. II.A) into out; *rows receives the row
+ * count. */
 int rte_readings(rte_handle* h, double* out, size_t len, int64_t* rows);
 
-/* Copy the per-step relative fluence change (FP64) into out (len entries
- * max); *rows receives the number written. */
+/* Copy the per-step relative fluence change (FP64; the convergence measure
+ * of the marched steady state, Sec. II.A) into out (len entries max); *rows
+ * receives the number written. */
 int rte_residuals(rte_handle* h, double* out, size_t len, int64_t* rows);
 
 /* Steps applied since creation (synchronises the stream). */
 int rte_steps_done(rte_handle* h, int64_t* steps);
 
 /* Read or overwrite the full real-basis moment state u (M*n^3, FP64 on the
- * host, converted to/from the working precision). rte_set_state also
- * resets the step count, the record and the integrated fluence. */
+ * host, converted to/from the working precision): the truncated moment
+ * vector psi_{l,m}, l <= N, of Sec. II.A. rte_set_state starts a new run
+ * from that state: it resets the step count, the record and the integrated
+ * fluence, and derives the runaway-growth threshold from the new state. */
 int rte_get_state(rte_handle* h, double* out, size_t len);
 int rte_set_state(rte_handle* h, const double* in, size_t len);
+
+/* Checkpoint / resume of a run (the transient solution of Sec. II.A).
+ * rte_snapshot_bytes: host bytes of a snapshot of this handle (0 for NULL).
+ * rte_snapshot: copy into the caller's host buffer (len >= that size) the
+ * state u in the working precision (bitwise), the step count, the FP64
+ * integrated fluence, the whole record of readings and residuals and the
+ * run flags. Synchronises the stream.
+ * rte_restore: load such a snapshot into a handle created with the same
+ * configuration, detectors, maps and source (checked by a hash stored in
+ * the snapshot; RTE_EINVAL on mismatch, short or corrupt input). Stepping
+ * on afterwards gives bitwise the results of the uninterrupted run.
+ * Synchronises the stream. */
+size_t rte_snapshot_bytes(const rte_handle* h);
+int rte_snapshot(rte_handle* h, void* out, size_t len);
+int rte_restore(rte_handle* h, const void* in, size_t len);
 
 /* Dense real-basis streaming matrices B_x, B_y, B_z (each M*M, row-major,
  * FP64) exactly as the library tabulates them from eq. (6). Host only, no
@@ -266,6 +300,59 @@ int rte_profile_kernels(rte_handle* h, int64_t nsteps, double* ms, int64_t* coun
 /* rte_expo_advance with the same per-class event timing (ms[0..12],
  * counts[0..12] as for rte_profile_kernels). */
 int rte_profile_expo(rte_handle* h, double t_ps, double* ms, int64_t* counts);
+
+/* ---- Batched serving ---------------------------------------------------
+ * Many independent solves of one configuration (grid, order, precision,
+ * scheme, spacing, time step, layer, detector count, record length) advance
+ * together: a batch holds `slots` solves in one caller-owned workspace of
+ * slots * rte_batch_slot_bytes(cfg) bytes (256-byte aligned), slot s at
+ * offset s * rte_batch_slot_bytes(cfg). Every kernel of a time step is
+ * launched once for all resident slots (the slot is a grid coordinate), from
+ * one captured graph per number of slot rows; slots that are free, finished
+ * or failed return at once. Each slot is an ordinary solve (the same
+ * kernels in the same order as rte_step on a single handle, so its results
+ * are bitwise those of that solve), with its own maps, source, initial state,
+ * detectors and step count. Grids up to 128 points per axis, orders N <= 7.
+ *
+ * rte_batch_slot_bytes: device bytes of one slot (0 for an unsupported
+ *   configuration).
+ * rte_batch_create: hip_stream (required) is the compute stream; the
+ *   library creates two more streams of its own (staging and reads) and a
+ *   small pinned host ring for control-block copies. cfg->det_index is
+ *   ignored (each request brings its own).
+ * rte_batch_admit: stage a request into a free slot: validate and build its
+ *   tables and state as rte_create does (same errors), upload them on the
+ *   staging stream; det_index: cfg->n_det distinct voxel indices (NULL if
+ *   n_det = 0); steps >= 1 time steps to run. May be called from another
+ *   thread than the one stepping the batch. The slot starts at the next
+ *   rte_batch_step.
+ * rte_batch_step: start the staged slots (in stream order), then queue
+ *   nsteps time steps of every running slot (a slot stops by itself after
+ *   its own step count) followed by an asynchronous copy of the slot control
+ *   blocks. At most 4 such chunks are in flight (the call waits for the
+ *   oldest otherwise).
+ * rte_batch_poll: non-blocking; from the newest chunk that has completed,
+ *   status[s] (RTE_SLOT_*) and steps_done[s] for every slot (arrays of
+ *   `slots` entries), and the number of queued chunks not yet completed
+ *   (any of the three may be NULL).
+ * rte_batch_handle: the handle of a finished or failed slot, for the
+ *   read-only calls (rte_fluence, rte_readings, rte_residuals,
+ *   rte_get_state, rte_steps_done, rte_snapshot; stepping calls and
+ *   rte_destroy refuse or ignore it); valid until the slot is released.
+ * rte_batch_release: free a finished, failed or staged slot.
+ * rte_batch_destroy: synchronise, release every slot and the batch. */
+enum { RTE_SLOT_FREE = 0, RTE_SLOT_STAGING = 1, RTE_SLOT_STAGED = 2, RTE_SLOT_RUNNING = 3,
+       RTE_SLOT_DONE = 4, RTE_SLOT_FAILED = 5 };
+typedef struct rte_batch rte_batch;
+size_t rte_batch_slot_bytes(const rte_config* cfg);
+int rte_batch_create(const rte_config* cfg, int32_t slots, void* dev_ws, size_t ws_bytes, void* hip_stream,
+                     rte_batch** out);
+int rte_batch_admit(rte_batch* b, int32_t slot, const rte_medium* med, const int64_t* det_index, int64_t steps);
+int rte_batch_step(rte_batch* b, int64_t nsteps);
+int rte_batch_poll(rte_batch* b, int64_t* steps_done, int32_t* status, int32_t* in_flight);
+int rte_batch_handle(rte_batch* b, int32_t slot, rte_handle** out);
+int rte_batch_release(rte_batch* b, int32_t slot);
+void rte_batch_destroy(rte_batch* b);
 
 /* Release the handle (and its captured graph). The workspace stays the
  * caller's. Safe on NULL. */

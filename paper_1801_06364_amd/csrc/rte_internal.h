@@ -103,7 +103,8 @@ constexpr int kDotPartials = 1024 * kMaxBasisVectors;
 // kernel of a step (kernels return at once when stop != 0).
 struct Ctl {
   long long step;       // steps applied since creation / last set_state
-  int stop;             // 0 run, 1 converged (tol met), 2 unstable
+  int stop;             // 0 run, 1 converged (tol met), 2 unstable, 3 step limit
+                        // reached or slot idle (batched serving)
   int pad;
   double tol;           // relative fluence change that stops a run (0: off)
   double growth_limit;  // ||phi||^2 above this flags runaway growth
@@ -115,6 +116,9 @@ struct Ctl {
   long long qw_rows;
   int qw_cols;
   int pad2;
+  // batched serving: the slot's run ends (stop = 3) once step reaches
+  // limit (0: no limit)
+  long long limit;
 };
 
 // Everything one RK4 step needs, as plain device pointers (carved from the
@@ -148,6 +152,11 @@ struct StepArgs {
   long long cap;
   void* ctl;                // device control block
   double c, dt;
+  // batched launches (serving): nslot solves of one configuration whose
+  // workspaces lie sstride bytes apart, the pointers above being those of
+  // slot 0; grid row blockIdx.y selects the slot (0 / 1: a single solve)
+  int nslot;
+  long long sstride;
 };
 
 // Kernel classes timed by the profiling entry point.

@@ -35,6 +35,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "rte_coupling_ct.h"
 #include "rte_fft.h"
 #include "rte_internal.h"
@@ -67,6 +69,16 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblocks) {
   const int per = nblocks / kXcds, rem = nblocks % kXcds;
   const int x = bid % kXcds, local = bid / kXcds;
   return x * per + (x < rem ? x : rem) + local;
+}
+
+// Batched launches: grid row blockIdx.y is a slot whose workspace lies
+// bs bytes after the previous slot's; every pointer of the launch moves by
+// blockIdx.y * bs (null pointers stay null). bs = 0: a single solve.
+template <typename P>
+__device__ __forceinline__ P* slot_ptr(P* p, long long bs) {
+  using B = typename std::conditional<std::is_const<P>::value, const char, char>::type;
+  if (bs == 0 || p == nullptr) return p;
+  return reinterpret_cast<P*>(reinterpret_cast<B*>(p) + (long long)blockIdx.y * bs);
 }
 
 template <int NN> struct GridC {
@@ -287,12 +299,17 @@ template <typename T, int NN, int MODE>
 __global__ void __launch_bounds__(kZBlock)
 k_pencil(const typename cplx_of<T>::type* src, typename cplx_of<T>::type* dst,   // may alias (in place)
          const typename cplx_of<T>::type* __restrict__ twg, const T* __restrict__ kv,
-         const Ctl* __restrict__ ctl) {
+         const Ctl* __restrict__ ctl, long long bs = 0) {
   using V = typename cplx_of<T>::type;
   using Z = ZdShape<T, NN>;
   constexpr int n = NN, H = NN / 2, TZ = Z::TZ, PITCH = Z::PITCH;
   // element stride along the pencil axis in the [b][z][ky][kx] spectrum
   constexpr size_t AX = pencil_z(MODE) ? size_t(n) * H : size_t(H);
+  src = slot_ptr(src, bs);
+  dst = slot_ptr(dst, bs);
+  twg = slot_ptr(twg, bs);
+  kv = slot_ptr(kv, bs);
+  ctl = slot_ptr(ctl, bs);
   if (ctl->stop) return;
   extern __shared__ __align__(16) unsigned char smem[];
   V* tw = reinterpret_cast<V*>(smem);
@@ -454,11 +471,15 @@ struct Rows {
 template <typename T, int NN, int N>
 __global__ void __launch_bounds__(kCBlock)
 k_couple(typename cplx_of<T>::type* __restrict__ spec, const typename cplx_of<T>::type* __restrict__ dspec,
-         const T* __restrict__ kv, T sc, const Ctl* __restrict__ ctl) {
+         const T* __restrict__ kv, T sc, const Ctl* __restrict__ ctl, long long bs = 0) {
   using V = typename cplx_of<T>::type;
   constexpr int n = NN, H = NN / 2;
   constexpr int M = (N + 1) * (N + 1);
   constexpr size_t MS = size_t(n) * n * H;      // moment stride
+  spec = slot_ptr(spec, bs);
+  dspec = slot_ptr(dspec, bs);
+  kv = slot_ptr(kv, bs);
+  ctl = slot_ptr(ctl, bs);
   if (ctl->stop) return;
   const int pt = blockIdx.x * kCBlock + threadIdx.x;   // (z * n + ky) * H + kx
   if (pt >= n * n * H) return;
@@ -652,11 +673,24 @@ k_inv_plane(const typename cplx_of<T>::type* spec, const T* vin, T* u, T* dst,
             const T* __restrict__ sig, const T* __restrict__ q, const int* __restrict__ qflag,
             double* __restrict__ phi_int, double* __restrict__ partial,
             const typename cplx_of<T>::type* __restrict__ twg, int M, T h, double dt,
-            const Ctl* __restrict__ ctl, int stage, long long step1, typename cplx_of<T>::type* fspec) {
+            const Ctl* __restrict__ ctl, int stage, long long step1, typename cplx_of<T>::type* fspec,
+            long long bs = 0) {
   using V = typename cplx_of<T>::type;
   using G = GridC<NN>;
   constexpr int n = NN, H = G::H;
   using Lay = PlaneLayout<NN, NN>;
+  spec = slot_ptr(spec, bs);
+  vin = slot_ptr(vin, bs);
+  u = slot_ptr(u, bs);
+  dst = slot_ptr(dst, bs);
+  sig = slot_ptr(sig, bs);
+  q = slot_ptr(q, bs);
+  qflag = slot_ptr(qflag, bs);
+  phi_int = slot_ptr(phi_int, bs);
+  partial = slot_ptr(partial, bs);
+  twg = slot_ptr(twg, bs);
+  ctl = slot_ptr(ctl, bs);
+  fspec = slot_ptr(fspec, bs);
   if (ctl->stop) return;
   extern __shared__ __align__(16) unsigned char smem[];
   V* tw = reinterpret_cast<V*>(smem);
@@ -738,8 +772,14 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_end_step(const T* __restrict__ u, const long long* __restrict__ det, int ndet,
            double* __restrict__ readings, double* __restrict__ resid, long long cap,
-           const double* __restrict__ partial, int npart, Ctl* ctl) {
+           const double* __restrict__ partial, int npart, Ctl* ctl, long long bs = 0) {
   __shared__ double red[2 * kBlock];
+  u = slot_ptr(u, bs);
+  det = slot_ptr(det, bs);
+  readings = slot_ptr(readings, bs);
+  resid = slot_ptr(resid, bs);
+  partial = slot_ptr(partial, bs);
+  ctl = slot_ptr(ctl, bs);
   if (ctl->stop) return;
   const long long s = ctl->step;
   if (s < cap)
@@ -769,6 +809,7 @@ k_end_step(const T* __restrict__ u, const long long* __restrict__ det, int ndet,
     ctl->step = s + 1;
     if (!isfinite(d2) || !isfinite(o2) || o2 > ctl->growth_limit) ctl->stop = 2;
     else if (ctl->tol > 0.0 && r < ctl->tol) ctl->stop = 1;
+    else if (ctl->limit > 0 && s + 1 >= ctl->limit) ctl->stop = 3;
   }
 }
 
@@ -1437,6 +1478,9 @@ void enqueue_stage(const StepArgs& a, ProfRec* pr, double hs, double sgn, const 
   const int cblocks = (NN * NN * (NN / 2) + kCBlock - 1) / kCBlock;
   const int rblocks = M * NN * (NN / RowShape<NN>::RB);
   const size_t lp = plane_lds<T, NN>(), lz = zd_lds<T, NN>(), lr = rows_lds<T, NN>();
+  // batched launches (plane grids, register coupling): grid rows = slots
+  const unsigned ns = a.nslot > 1 ? unsigned(a.nslot) : 1u;
+  const long long bs = ns > 1 ? a.sstride : 0;
   auto rec = [&](int cls) {
     if (pr && pr->count < kMaxProfLaunches) {
       (void)hipEventRecord(static_cast<hipEvent_t>(pr->ev[pr->count]), st);
@@ -1455,12 +1499,13 @@ void enqueue_stage(const StepArgs& a, ProfRec* pr, double hs, double sgn, const 
                        spec, tw, cctl, planes);
     rec(PROF_FWD_PLANE);
   }
-  hipLaunchKernelGGL((k_pencil<T, NN, PENCIL_ZDERIV>), dim3(pencils), zblk, lz, st, spec, dspec, tw, kv, cctl);
+  hipLaunchKernelGGL((k_pencil<T, NN, PENCIL_ZDERIV>), dim3(pencils, ns), zblk, lz, st, spec, dspec, tw, kv, cctl,
+                     bs);
   rec(PROF_ZDERIV);
   V* coupled = spec;   // the inverse passes read the coupled spectrum from here
   if constexpr (N <= kDenseOrder) {
-    hipLaunchKernelGGL((k_couple<T, NN, N>), dim3(cblocks), cblk, 0, st, spec, dspec, kv, T(sgn * hs / n2),
-                       cctl);
+    hipLaunchKernelGGL((k_couple<T, NN, N>), dim3(cblocks, ns), cblk, 0, st, spec, dspec, kv, T(sgn * hs / n2),
+                       cctl, bs);
   } else {
     coupled = static_cast<V*>(a.wspec);
     hipLaunchKernelGGL((k_couple_rt<T, NN>), dim3(cblocks), cblk, 0, st, spec, dspec, coupled, kv, a.ctab,
@@ -1475,9 +1520,9 @@ void enqueue_stage(const StepArgs& a, ProfRec* pr, double hs, double sgn, const 
                        a.qflag, a.phi_int, a.partial, tw, M, T(hs), a.dt, cctl, stage, step1);
     rec(PROF_INV_ROWS);
   } else {
-    hipLaunchKernelGGL((k_inv_plane<T, NN, MODE, FUSE>), dim3(planes), pblk, lp, st, coupled, src, u, out, sig,
-                       q, a.qflag, a.phi_int, a.partial, tw, M, T(hs), a.dt, cctl, stage, step1,
-                       FUSE ? spec : static_cast<V*>(nullptr));
+    hipLaunchKernelGGL((k_inv_plane<T, NN, MODE, FUSE>), dim3(planes, ns), pblk, lp, st, coupled, src, u, out,
+                       sig, q, a.qflag, a.phi_int, a.partial, tw, M, T(hs), a.dt, cctl, stage, step1,
+                       FUSE ? spec : static_cast<V*>(nullptr), bs);
     rec(PROF_INV_PLANE);
   }
 }
@@ -1628,8 +1673,10 @@ hipError_t enqueue_t(const StepArgs& a, const OpArgs& op, ProfRec* pr) {
         enqueue_stage<T, NN, N, EPI_MID>(a, pr, kRkAlpha[2] * hc, 1.0, v, u, v, 2, s1);
         enqueue_stage<T, NN, N, EPI_LAST>(a, pr, kRkAlpha[3] * hc, 1.0, v, u, u, 3, s1);
       }
-      hipLaunchKernelGGL((k_end_step<T>), dim3(1), dim3(kBlock), 0, st, u, a.det, a.ndet, a.readings, a.resid,
-                         a.cap, a.partial, partial_count<NN>(), static_cast<Ctl*>(a.ctl));
+      const unsigned ns = a.nslot > 1 ? unsigned(a.nslot) : 1u;
+      hipLaunchKernelGGL((k_end_step<T>), dim3(1, ns), dim3(kBlock), 0, st, u, a.det, a.ndet, a.readings, a.resid,
+                         a.cap, a.partial, partial_count<NN>(), static_cast<Ctl*>(a.ctl),
+                         ns > 1 ? a.sstride : 0LL);
       if (pr && pr->count < kMaxProfLaunches) {
         (void)hipEventRecord(static_cast<hipEvent_t>(pr->ev[pr->count]), st);
         pr->cls[pr->count++] = PROF_END;

@@ -8,7 +8,9 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/rte.h"
@@ -142,6 +144,9 @@ struct rte_handle {
   bool homogeneous;                 // constant maps, no boundary layer
   bool expo_taylor;                 // exact propagation by the per-point series only
   std::vector<double> rot_data;     // X blocks and B_z couplings of the rotation path
+  bool batch_owned;                 // a slot of a batch: stepped by the batch, read-only here
+  double source_term;               // weighted source energy / (smallest loss)^2 (growth limit)
+  uint64_t medium_hash;             // FNV-1a of the maps and source (snapshot compatibility)
   double sigl[rte::kMaxOrder + 1];  // per-degree loss (homogeneous media)
   template <typename P> P* at(size_t off) const { return reinterpret_cast<P*>(ws + off); }
 };
@@ -163,15 +168,22 @@ void convert_upload(std::vector<T>& tmp, const double* src, size_t count) {
   for (size_t i = 0; i < count; ++i) tmp[i] = T(src[i]);
 }
 
+// State upload: the given leading moments converted to the working
+// precision, the remaining moments cleared on the device.
 template <typename T>
 int upload_state_t(rte_handle* h, const double* psi, int moments) {
   const size_t V = size_t(h->n) * h->n * h->n;
   const size_t cnt = size_t(h->M) * V;
-  std::vector<T> tmp(cnt, T(0));
-  if (psi)
-    for (size_t i = 0; i < size_t(moments) * V; ++i) tmp[i] = T(psi[i]);
-  hipError_t e = hipMemcpyAsync(h->at<T>(h->lay.u), tmp.data(), cnt * sizeof(T), hipMemcpyHostToDevice,
-                                h->stream);
+  const size_t given = psi ? size_t(moments) * V : 0;
+  hipError_t e = hipSuccess;
+  std::vector<T> tmp;
+  if (given) {
+    tmp.resize(given);
+    for (size_t i = 0; i < given; ++i) tmp[i] = T(psi[i]);
+    e = hipMemcpyAsync(h->at<T>(h->lay.u), tmp.data(), given * sizeof(T), hipMemcpyHostToDevice, h->stream);
+  }
+  if (e == hipSuccess && given < cnt)
+    e = hipMemsetAsync(h->at<T>(h->lay.u) + given, 0, (cnt - given) * sizeof(T), h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   return to_code(e);
 }
@@ -201,6 +213,7 @@ int write_ctl(rte_handle* h, const Ctl* c) {
 int reset_run_state(rte_handle* h, double growth_limit) {
   Ctl c{};
   c.growth_limit = growth_limit;
+  c.stop = h->batch_owned ? 3 : 0;   // a batch slot stays idle until the batch starts it
   c.qw = h->qw;
   c.qw_rows = h->qw_rows;
   c.qw_cols = h->qw_cols;
@@ -215,17 +228,47 @@ int reset_run_state(rte_handle* h, double growth_limit) {
   return to_code(e);
 }
 
-double growth_limit_of(const rte_handle* h, const double* psi0, const double* q,
-                       const std::vector<double>& sig0) {
-  const size_t V = size_t(h->n) * h->n * h->n;
-  double f2 = 0.0, q2 = 0.0, smin = 1e300;
-  for (size_t i = 0; i < V; ++i) {
-    if (psi0) f2 += psi0[i] * psi0[i];
-    if (q) q2 += q[i] * q[i];
-    smin = std::min(smin, sig0[i]);
+// FNV-1a over the bytes of the optical maps and the source moments: a
+// snapshot restores only into a handle built from the same medium.
+inline void fnv1a(uint64_t& h, const void* p, size_t bytes) {
+  const unsigned char* b = static_cast<const unsigned char*>(p);
+  for (size_t i = 0; i < bytes; ++i) {
+    h ^= b[i];
+    h *= 1099511628211ull;
   }
-  smin = std::max(smin, 1e-6);
-  return 1e16 * (f2 + q2 / (smin * smin) + 1e-300);
+}
+
+uint64_t medium_hash_of(const rte_medium* med, size_t V, int q_moments) {
+  uint64_t h = 1469598103934665603ull;
+  fnv1a(h, med->mu_a, V * 8);
+  fnv1a(h, med->mu_s, V * 8);
+  fnv1a(h, med->g, V * 8);
+  if (med->q) fnv1a(h, med->q, size_t(q_moments) * V * 8);
+  return h;
+}
+
+// Weighted energy sum_a (2l+1) ||x_a||^2 of the leading `moments` moment
+// fields of x (the squared norm of the orthonormal-basis coefficients, in
+// which the streaming operator is skew and the loss non-negative, so the
+// source-free solution never exceeds it).
+double weighted_energy(const double* x, int moments, size_t V) {
+  if (!x) return 0.0;
+  double e = 0.0;
+  for (int a = 0; a < moments; ++a) {
+    const int l = isqrt_c(a);
+    double s = 0.0;
+    for (size_t i = 0; i < V; ++i) s += x[size_t(a) * V + i] * x[size_t(a) * V + i];
+    e += double(2 * l + 1) * s;
+  }
+  return e;
+}
+
+// Runaway-growth threshold on ||phi||^2: the fluence is one component of
+// the moment vector, so ||phi(t)||^2 stays below the initial weighted
+// energy plus the steady response to the source (source energy over the
+// smallest loss squared); the limit is that bound times 1e16.
+double growth_limit_of(double state_energy, double source_term) {
+  return 1e16 * (state_energy + source_term + 1e-300);
 }
 
 template <typename T>
@@ -250,7 +293,10 @@ int upload_tables_t(rte_handle* h, const rte_medium* med, const std::vector<doub
   convert_upload(tmp, kv.data(), kv.size());
   put(L.kv, tmp.data(), tmp.size() * sizeof(T));
   std::vector<int> qflag(n, 0);
-  if (h->has_q) {
+  if (h->has_q && !med->q) {
+    // a batch slot keeps the source section of the common layout: cleared
+    if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.q, 0, size_t(h->M) * V * sizeof(T), h->stream);
+  } else if (h->has_q) {
     std::vector<double> qm(size_t(h->M) * V);
     for (int a = 0; a < h->M; ++a)
       for (size_t i = 0; i < V; ++i) {
@@ -361,9 +407,13 @@ size_t rte_workspace_bytes(const rte_config* cfg) {
   return rte::layout_of(cfg, true).total;
 }
 
-int rte_create(const rte_config* cfg, const rte_medium* med, void* dev_ws, size_t ws_bytes,
-               void* hip_stream, rte_handle** out) {
-  using namespace rte;
+}  // extern "C"
+
+namespace rte {
+// rte_create's body; batch_slot: a slot of a batch (the common layout with a
+// source section, control block idle until the batch starts the slot).
+int create_impl(const rte_config* cfg, const rte_medium* med, void* dev_ws, size_t ws_bytes,
+                void* hip_stream, rte_handle** out, bool batch_slot) {
   if (!out) return RTE_EINVAL;
   *out = nullptr;
   if (!config_ok(cfg) || !med || !med->mu_a || !med->mu_s || !med->g) return RTE_EINVAL;
@@ -377,7 +427,14 @@ int rte_create(const rte_config* cfg, const rte_medium* med, void* dev_ws, size_
   }
   for (int p = 0; p < cfg->n_det; ++p)
     if (cfg->det_index[p] < 0 || size_t(cfg->det_index[p]) >= V) return RTE_EINVAL;
-  const bool has_q = med->q != nullptr;
+  {
+    // distinct detector voxels: the adjoint injects each reading's source
+    // at its voxel, one thread per detector
+    std::vector<int64_t> d(cfg->det_index, cfg->det_index + cfg->n_det);
+    std::sort(d.begin(), d.end());
+    if (std::adjacent_find(d.begin(), d.end()) != d.end()) return RTE_EINVAL;
+  }
+  const bool has_q = med->q != nullptr || batch_slot;
   const Layout L = layout_of(cfg, has_q);
   if (!dev_ws || (reinterpret_cast<uintptr_t>(dev_ws) % kAlign) != 0 || ws_bytes < L.total) return RTE_ENOMEM;
 
@@ -398,6 +455,7 @@ int rte_create(const rte_config* cfg, const rte_medium* med, void* dev_ws, size_
   h->stream = reinterpret_cast<hipStream_t>(hip_stream);
   h->ws = reinterpret_cast<unsigned char*>(dev_ws);
   h->lay = L;
+  h->batch_owned = batch_slot;
   h->graph_ready = false;
   h->spec_valid = false;
   h->qw = nullptr;
@@ -430,6 +488,8 @@ int rte_create(const rte_config* cfg, const rte_medium* med, void* dev_ws, size_
   A.kv = h->ws + L.kv;
   A.sig = h->ws + L.sig;
   A.q = has_q ? h->ws + L.q : nullptr;
+  A.nslot = 1;
+  A.sstride = 0;
   A.qflag = h->at<int>(L.qflag);
   A.phi_int = h->at<double>(L.phi_int);
   A.partial = h->at<double>(L.partial);
@@ -448,8 +508,26 @@ int rte_create(const rte_config* cfg, const rte_medium* med, void* dev_ws, size_
   if (!rc)
     rc = h->prec == RTE_FP64 ? upload_state_t<double>(h, med->psi0, pm) : upload_state_t<float>(h, med->psi0, pm);
   if (!rc) {
-    std::vector<double> sig0(sig.begin(), sig.begin() + V);
-    rc = reset_run_state(h, growth_limit_of(h, med->psi0, med->q, sig0));
+    double smin = 1e300;
+    for (size_t i = 0; i < V; ++i) smin = std::min(smin, sig[i]);
+    smin = std::max(smin, 1e-6);
+    h->source_term = weighted_energy(med->q, med->q ? h->q_moments : 0, V) / (smin * smin);
+    h->medium_hash = medium_hash_of(med, V, med->q ? h->q_moments : 0);
+    // the configuration that fixes the meaning of a snapshot's bytes
+    fnv1a(h->medium_hash, &n, sizeof n);
+    fnv1a(h->medium_hash, &N, sizeof N);
+    fnv1a(h->medium_hash, &cfg->precision, sizeof cfg->precision);
+    fnv1a(h->medium_hash, &cfg->scheme, sizeof cfg->scheme);
+    fnv1a(h->medium_hash, &cfg->pml_width, sizeof cfg->pml_width);
+    fnv1a(h->medium_hash, &cfg->pml_mu0, sizeof cfg->pml_mu0);
+    fnv1a(h->medium_hash, &cfg->pml_mu1, sizeof cfg->pml_mu1);
+    fnv1a(h->medium_hash, &cfg->dx_mm, sizeof cfg->dx_mm);
+    fnv1a(h->medium_hash, &cfg->c_mm_ps, sizeof cfg->c_mm_ps);
+    fnv1a(h->medium_hash, &h->dt, sizeof h->dt);
+    fnv1a(h->medium_hash, &cfg->record_steps, sizeof cfg->record_steps);
+    fnv1a(h->medium_hash, &cfg->n_det, sizeof cfg->n_det);
+    if (cfg->n_det > 0) fnv1a(h->medium_hash, cfg->det_index, size_t(cfg->n_det) * 8);
+    rc = reset_run_state(h, growth_limit_of(weighted_energy(med->psi0, med->psi0 ? pm : 0, V), h->source_term));
   }
   h->cfg.det_index = nullptr;
   if (rc) {
@@ -459,15 +537,23 @@ int rte_create(const rte_config* cfg, const rte_medium* med, void* dev_ws, size_
   *out = h;
   return RTE_OK;
 }
+}  // namespace rte
+
+extern "C" {
+
+int rte_create(const rte_config* cfg, const rte_medium* med, void* dev_ws, size_t ws_bytes,
+               void* hip_stream, rte_handle** out) {
+  return rte::create_impl(cfg, med, dev_ws, ws_bytes, hip_stream, out, false);
+}
 
 int rte_step(rte_handle* h, int64_t nsteps) {
-  if (!h || nsteps < 0) return RTE_EINVAL;
+  if (!h || nsteps < 0 || h->batch_owned) return RTE_EINVAL;
   return rte::enqueue_steps(h, nsteps);
 }
 
 int rte_run(rte_handle* h, int64_t max_steps, double steady_tol, int64_t* steps_taken) {
   using namespace rte;
-  if (!h || max_steps < 0 || !(steady_tol > 0)) return RTE_EINVAL;
+  if (!h || max_steps < 0 || !(steady_tol > 0) || h->batch_owned) return RTE_EINVAL;
   Ctl c;
   int rc = read_ctl(h, &c);
   if (rc) return rc;
@@ -549,16 +635,113 @@ int rte_get_state(rte_handle* h, double* out, size_t len) {
 }
 
 int rte_set_state(rte_handle* h, const double* in, size_t len) {
-  if (!h || !in) return RTE_EINVAL;
+  if (!h || !in || h->batch_owned) return RTE_EINVAL;
   h->spec_valid = false;
   const size_t cnt = size_t(h->M) * h->n * h->n * h->n;
   if (len < cnt) return RTE_EINVAL;
-  rte::Ctl c;
-  int rc = rte::read_ctl(h, &c);
+  const int rc = h->prec == RTE_FP64 ? rte::upload_state_t<double>(h, in, h->M)
+                                     : rte::upload_state_t<float>(h, in, h->M);
   if (rc) return rc;
-  rc = h->prec == RTE_FP64 ? rte::upload_state_t<double>(h, in, h->M) : rte::upload_state_t<float>(h, in, h->M);
+  const size_t V = size_t(h->n) * h->n * h->n;
+  return rte::reset_run_state(h, rte::growth_limit_of(rte::weighted_energy(in, h->M, V), h->source_term));
+}
+
+namespace {
+// Snapshot layout (host bytes): header, then u in the working precision
+// (bitwise), the FP64 integrated fluence [n^3], the whole record of
+// readings [record_steps][n_det] and residuals [record_steps].
+struct SnapHeader {
+  char magic[8];
+  uint64_t compat;        // hash of configuration, detectors, maps and source
+  int64_t step;
+  int32_t stop, pad;
+  double growth_limit, last_resid, last_norm2;
+};
+constexpr char kSnapMagic[8] = {'R', 'T', 'E', 'S', 'N', 'A', 'P', '1'};
+
+struct SnapSizes {
+  size_t state, phi, readings, resid, total;
+};
+SnapSizes snap_sizes(const rte_handle* h) {
+  SnapSizes z{};
+  const size_t V = size_t(h->n) * h->n * h->n;
+  z.state = rte::state_bytes(h);
+  z.phi = V * 8;
+  z.readings = size_t(h->cfg.record_steps) * size_t(h->cfg.n_det) * 8;
+  z.resid = size_t(h->cfg.record_steps) * 8;
+  z.total = sizeof(SnapHeader) + z.state + z.phi + z.readings + z.resid;
+  return z;
+}
+}  // namespace
+
+size_t rte_snapshot_bytes(const rte_handle* h) { return h ? snap_sizes(h).total : 0; }
+
+int rte_snapshot(rte_handle* h, void* out, size_t len) {
+  using namespace rte;
+  if (!h || !out) return RTE_EINVAL;
+  const SnapSizes z = snap_sizes(h);
+  if (len < z.total) return RTE_EINVAL;
+  Ctl c;
+  int rc = read_ctl(h, &c);
   if (rc) return rc;
-  return rte::reset_run_state(h, c.growth_limit);
+  SnapHeader hd{};
+  std::memcpy(hd.magic, kSnapMagic, 8);
+  hd.compat = h->medium_hash;
+  hd.step = c.step;
+  hd.stop = c.stop == 1 ? 0 : c.stop;   // a converged run's stop flag ends with its rte_run
+  hd.growth_limit = c.growth_limit;
+  hd.last_resid = c.last_resid;
+  hd.last_norm2 = c.last_norm2;
+  unsigned char* o = static_cast<unsigned char*>(out);
+  std::memcpy(o, &hd, sizeof hd);
+  o += sizeof hd;
+  hipError_t e = hipMemcpyAsync(o, h->ws + h->lay.u, z.state, hipMemcpyDeviceToHost, h->stream);
+  o += z.state;
+  if (e == hipSuccess) e = hipMemcpyAsync(o, h->ws + h->lay.phi_int, z.phi, hipMemcpyDeviceToHost, h->stream);
+  o += z.phi;
+  if (e == hipSuccess && z.readings)
+    e = hipMemcpyAsync(o, h->ws + h->lay.readings, z.readings, hipMemcpyDeviceToHost, h->stream);
+  o += z.readings;
+  if (e == hipSuccess && z.resid)
+    e = hipMemcpyAsync(o, h->ws + h->lay.resid, z.resid, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  return to_code(e);
+}
+
+int rte_restore(rte_handle* h, const void* in, size_t len) {
+  using namespace rte;
+  if (!h || !in || h->batch_owned) return RTE_EINVAL;
+  const SnapSizes z = snap_sizes(h);
+  if (len < z.total) return RTE_EINVAL;
+  SnapHeader hd;
+  const unsigned char* p = static_cast<const unsigned char*>(in);
+  std::memcpy(&hd, p, sizeof hd);
+  if (std::memcmp(hd.magic, kSnapMagic, 8) != 0 || hd.compat != h->medium_hash || hd.step < 0 ||
+      hd.stop < 0 || hd.stop > 2)
+    return RTE_EINVAL;
+  p += sizeof hd;
+  h->spec_valid = false;
+  hipError_t e = hipMemcpyAsync(h->ws + h->lay.u, p, z.state, hipMemcpyHostToDevice, h->stream);
+  p += z.state;
+  if (e == hipSuccess) e = hipMemcpyAsync(h->ws + h->lay.phi_int, p, z.phi, hipMemcpyHostToDevice, h->stream);
+  p += z.phi;
+  if (e == hipSuccess && z.readings)
+    e = hipMemcpyAsync(h->ws + h->lay.readings, p, z.readings, hipMemcpyHostToDevice, h->stream);
+  p += z.readings;
+  if (e == hipSuccess && z.resid)
+    e = hipMemcpyAsync(h->ws + h->lay.resid, p, z.resid, hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return RTE_EDEVICE;
+  Ctl c{};
+  c.step = hd.step;
+  c.stop = hd.stop;
+  c.growth_limit = hd.growth_limit;
+  c.last_resid = hd.last_resid;
+  c.last_norm2 = hd.last_norm2;
+  c.qw = h->qw;
+  c.qw_rows = h->qw_rows;
+  c.qw_cols = h->qw_cols;
+  return write_ctl(h, &c);
 }
 
 namespace {
@@ -608,7 +791,7 @@ void profile_moments(const double* sm, int64_t ns, double delta, double t0, doub
 int rte_set_source_profile(rte_handle* h, const double* samples, int64_t nsamples, double delta_ps,
                            int64_t rows, void* dev_table, size_t table_bytes) {
   using namespace rte;
-  if (!h) return RTE_EINVAL;
+  if (!h || h->batch_owned) return RTE_EINVAL;
   const int cols = h->cfg.scheme == RTE_EULER ? 1 : 4;
   if (samples == nullptr || rows == 0) {
     h->qw = nullptr;
@@ -670,7 +853,7 @@ size_t rte_adjoint_workspace_bytes(const rte_config* cfg, int64_t steps, int64_t
 
 int rte_forward_checkpointed(rte_handle* h, int64_t steps, int64_t every, void* adj_ws, size_t adj_bytes) {
   using namespace rte;
-  if (!h || steps <= 0 || every <= 0) return RTE_EINVAL;
+  if (!h || steps <= 0 || every <= 0 || h->batch_owned) return RTE_EINVAL;
   const AdjLayout A = adj_layout(&h->cfg, steps, every);
   if (!adj_ws || (reinterpret_cast<uintptr_t>(adj_ws) % kAlign) != 0 || adj_bytes < A.total) return RTE_ENOMEM;
   unsigned char* w = static_cast<unsigned char*>(adj_ws);
@@ -693,7 +876,7 @@ int rte_forward_checkpointed(rte_handle* h, int64_t steps, int64_t every, void* 
 int rte_adjoint(rte_handle* h, int64_t steps, int64_t every, void* adj_ws, size_t adj_bytes,
                 const double* dj_dr, double* grad_mu_a, double* grad_mu_s) {
   using namespace rte;
-  if (!h || steps <= 0 || every <= 0 || !grad_mu_a || !grad_mu_s) return RTE_EINVAL;
+  if (!h || steps <= 0 || every <= 0 || !grad_mu_a || !grad_mu_s || h->batch_owned) return RTE_EINVAL;
   if (h->cfg.n_det > 0 && !dj_dr) return RTE_EINVAL;
   h->spec_valid = false;   // the recomputation and transposed stages reuse the spectrum buffers
   const AdjLayout A = adj_layout(&h->cfg, steps, every);
@@ -841,7 +1024,8 @@ size_t rte_krylov_workspace_bytes(const rte_config* cfg, int32_t restart) {
 int rte_steady_gmres(rte_handle* h, int32_t restart, int64_t max_iters, double tol, int32_t steps_per_apply,
                      void* kws, size_t kbytes, int64_t* iters, double* rel_residual) {
   using namespace rte;
-  if (!h || restart < 1 || restart + 1 > kMaxBasisVectors || max_iters < 1 || !(tol > 0) || steps_per_apply < 0)
+  if (!h || restart < 1 || restart + 1 > kMaxBasisVectors || max_iters < 1 || !(tol > 0) || steps_per_apply < 0 ||
+      h->batch_owned)
     return RTE_EINVAL;
   if (h->qw) return RTE_EINVAL;   // a steady state needs a constant source
   h->spec_valid = false;          // the operator applications reuse the spectrum buffers
@@ -1050,7 +1234,7 @@ double taylor_theta(int m, double eps) {
 namespace {
 int expo_run(rte_handle* h, double t_ps, rte::ProfRec* pr) {
   using namespace rte;
-  if (!h || !std::isfinite(t_ps) || t_ps < 0) return RTE_EINVAL;
+  if (!h || !std::isfinite(t_ps) || t_ps < 0 || h->batch_owned) return RTE_EINVAL;
   if (!h->homogeneous || h->N > kDenseOrder || h->qw) return RTE_EINVAL;
   if (t_ps == 0) return RTE_OK;
   h->spec_valid = false;
@@ -1173,7 +1357,7 @@ int rte_profile_expo(rte_handle* h, double t_ps, double* ms, int64_t* counts) {
 
 int rte_profile_kernels(rte_handle* h, int64_t nsteps, double* ms, int64_t* counts) {
   using namespace rte;
-  if (!h || !ms || !counts || nsteps < 0) return RTE_EINVAL;
+  if (!h || !ms || !counts || nsteps < 0 || h->batch_owned) return RTE_EINVAL;
   ProfRec pr{};
   hipEvent_t e0;
   hipEvent_t ev[kMaxProfLaunches];
@@ -1209,7 +1393,7 @@ int rte_profile_kernels(rte_handle* h, int64_t nsteps, double* ms, int64_t* coun
 }
 
 void rte_destroy(rte_handle* h) {
-  if (!h) return;
+  if (!h || h->batch_owned) return;   // a batch slot's handle belongs to its batch
   if (h->graph_ready) {
     (void)hipGraphExecDestroy(h->exec);
     (void)hipGraphDestroy(h->graph);
@@ -1226,6 +1410,319 @@ const char* rte_strerror(int code) {
     case RTE_EDEVICE: return "HIP runtime error";
     default: return "unknown error";
   }
+}
+
+}  // extern "C"
+
+// ====================================================== batched serving ==
+//
+// A batch holds `slots` solves of one configuration in one caller-owned
+// workspace, slot s at offset s * stride with the common layout. One
+// captured step graph per number of slot rows k launches every kernel of
+// the time step once with k grid rows (the slot index), so all resident
+// solves of the configuration advance in the same launches. A slot that is
+// idle, finished or failed has a non-zero stop flag in its control block and
+// its workgroups return at once. Slots are staged (tables and state uploaded
+// on the batch's staging stream) from any thread, started in stream order on
+// the compute stream by the next rte_batch_step, and observed through
+// control-block copies taken after every queued chunk of steps.
+
+namespace rte {
+
+constexpr int kBatchRing = 4;   // chunks whose control-block copies can be in flight
+
+__global__ void k_slot_start(Ctl* ctl, long long limit) {
+  if (threadIdx.x == 0) {
+    ctl->step = 0;
+    ctl->tol = 0.0;
+    ctl->limit = limit;
+    ctl->stop = 0;
+  }
+}
+
+enum {
+  SLOT_FREE = RTE_SLOT_FREE, SLOT_STAGING = RTE_SLOT_STAGING, SLOT_STAGED = RTE_SLOT_STAGED,
+  SLOT_RUNNING = RTE_SLOT_RUNNING, SLOT_DONE = RTE_SLOT_DONE, SLOT_FAILED = RTE_SLOT_FAILED
+};
+
+}  // namespace rte
+
+struct rte_batch {
+  rte_config cfg;
+  int slots;
+  size_t stride;
+  unsigned char* ws;
+  hipStream_t stream;   // compute: step graphs, slot starts
+  hipStream_t stage;    // staging uploads
+  hipStream_t read;     // result reads of finished slots
+  std::vector<rte_handle*> h;
+  std::vector<int> state;
+  std::vector<long long> limit;
+  std::vector<long long> start_seq;   // chunk sequence number at which the slot started
+  std::vector<long long> final_step;
+  std::vector<hipEvent_t> staged_ev;
+  std::vector<hipGraph_t> graph;      // [k - 1]: k slot rows
+  std::vector<hipGraphExec_t> exec;
+  rte::Ctl* snap;                     // pinned [kBatchRing][slots]
+  hipEvent_t ring_ev[rte::kBatchRing];
+  long long ring_seq[rte::kBatchRing];
+  int ring_rows[rte::kBatchRing];
+  long long seq;                      // chunks queued
+  size_t ctl_off;
+  std::mutex mu;
+};
+
+namespace rte {
+bool batch_config_ok(const rte_config* cfg) {
+  // plane grids (the fused step) and the register coupling pass
+  return config_ok(cfg) && cfg->n <= 128 && cfg->order_N <= kDenseOrder;
+}
+}  // namespace rte
+
+extern "C" {
+
+size_t rte_batch_slot_bytes(const rte_config* cfg) {
+  if (!rte::batch_config_ok(cfg)) return 0;
+  return rte::layout_of(cfg, true).total;
+}
+
+int rte_batch_create(const rte_config* cfg, int32_t slots, void* dev_ws, size_t ws_bytes, void* hip_stream,
+                     rte_batch** out) {
+  using namespace rte;
+  if (!out) return RTE_EINVAL;
+  *out = nullptr;
+  if (!batch_config_ok(cfg) || slots < 1 || slots > 65535 || !hip_stream) return RTE_EINVAL;
+  const Layout L = layout_of(cfg, true);
+  if (!dev_ws || (reinterpret_cast<uintptr_t>(dev_ws) % kAlign) != 0 || ws_bytes / L.total < size_t(slots))
+    return RTE_ENOMEM;
+  rte_batch* b = new (std::nothrow) rte_batch();
+  if (!b) return RTE_ENOMEM;
+  b->cfg = *cfg;
+  b->cfg.det_index = nullptr;
+  b->slots = slots;
+  b->stride = L.total;
+  b->ws = static_cast<unsigned char*>(dev_ws);
+  b->stream = static_cast<hipStream_t>(hip_stream);
+  b->ctl_off = L.ctl;
+  b->h.assign(slots, nullptr);
+  b->state.assign(slots, SLOT_FREE);
+  b->limit.assign(slots, 0);
+  b->start_seq.assign(slots, 0);
+  b->final_step.assign(slots, 0);
+  b->staged_ev.assign(slots, nullptr);
+  b->graph.assign(slots, nullptr);
+  b->exec.assign(slots, nullptr);
+  b->snap = nullptr;
+  b->seq = 0;
+  hipError_t e = hipStreamCreateWithFlags(&b->stage, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->read, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&b->snap), sizeof(Ctl) * kBatchRing * slots);
+  for (int i = 0; i < kBatchRing && e == hipSuccess; ++i) {
+    e = hipEventCreateWithFlags(&b->ring_ev[i], hipEventDisableTiming);
+    b->ring_seq[i] = -1;
+    b->ring_rows[i] = 0;
+  }
+  for (int s = 0; s < slots && e == hipSuccess; ++s) e = hipEventCreateWithFlags(&b->staged_ev[s], hipEventDisableTiming);
+  if (e == hipSuccess) {
+    // every slot starts idle (stop = 3): launches that cover it skip it
+    std::vector<Ctl> idle(slots);
+    for (auto& c : idle) {
+      c = Ctl{};
+      c.stop = 3;
+    }
+    e = hipMemcpy2DAsync(b->ws + b->ctl_off, b->stride, idle.data(), sizeof(Ctl), sizeof(Ctl), size_t(slots),
+                         hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  }
+  if (e != hipSuccess) {
+    rte_batch_destroy(b);
+    return RTE_EDEVICE;
+  }
+  *out = b;
+  return RTE_OK;
+}
+
+int rte_batch_admit(rte_batch* b, int32_t slot, const rte_medium* med, const int64_t* det_index, int64_t steps) {
+  using namespace rte;
+  if (!b || slot < 0 || slot >= b->slots || !med || steps < 1) return RTE_EINVAL;
+  if (b->cfg.n_det > 0 && !det_index) return RTE_EINVAL;
+  {
+    std::lock_guard<std::mutex> lk(b->mu);
+    if (b->state[slot] != SLOT_FREE) return RTE_EINVAL;
+    b->state[slot] = SLOT_STAGING;
+  }
+  rte_config cfg = b->cfg;
+  cfg.det_index = b->cfg.n_det > 0 ? det_index : nullptr;
+  rte_handle* h = nullptr;
+  int rc = create_impl(&cfg, med, b->ws + size_t(slot) * b->stride, b->stride, b->stage, &h, true);
+  if (rc == RTE_OK && hipEventRecord(b->staged_ev[slot], b->stage) != hipSuccess) rc = RTE_EDEVICE;
+  std::lock_guard<std::mutex> lk(b->mu);
+  if (rc != RTE_OK) {
+    if (h) {
+      h->batch_owned = false;
+      rte_destroy(h);
+    }
+    b->state[slot] = SLOT_FREE;
+    return rc;
+  }
+  h->stream = b->read;   // the slot handle's reads use the batch's read stream
+  b->h[slot] = h;
+  b->limit[slot] = steps;
+  b->state[slot] = SLOT_STAGED;
+  return RTE_OK;
+}
+
+int rte_batch_step(rte_batch* b, int64_t nsteps) {
+  using namespace rte;
+  if (!b || nsteps < 0) return RTE_EINVAL;
+  std::lock_guard<std::mutex> lk(b->mu);
+  hipError_t e = hipSuccess;
+  // start staged slots, in stream order before the next chunk
+  for (int s = 0; s < b->slots && e == hipSuccess; ++s) {
+    if (b->state[s] != SLOT_STAGED) continue;
+    e = hipStreamWaitEvent(b->stream, b->staged_ev[s], 0);
+    if (e != hipSuccess) break;
+    Ctl* c = reinterpret_cast<Ctl*>(b->ws + size_t(s) * b->stride + b->ctl_off);
+    hipLaunchKernelGGL(k_slot_start, dim3(1), dim3(64), 0, b->stream, c, (long long)b->limit[s]);
+    e = hipGetLastError();
+    if (e != hipSuccess) break;
+    StepArgs a = b->h[s]->args;
+    a.stream = b->stream;
+    OpArgs f{};
+    f.kind = OP_FWD;
+    e = hipError_t(launch_enqueue_op(b->cfg.n, a, f, nullptr));
+    b->state[s] = SLOT_RUNNING;
+    b->start_seq[s] = b->seq;
+  }
+  if (e != hipSuccess) return RTE_EDEVICE;
+  int rows = 0;
+  for (int s = 0; s < b->slots; ++s)
+    if (b->state[s] == SLOT_RUNNING) rows = s + 1;
+  if (rows == 0 || nsteps == 0) return RTE_OK;
+  if (!b->exec[rows - 1]) {
+    // capture one step over `rows` slot rows (pointers of slot 0, stride)
+    int s0 = 0;
+    while (!b->h[s0]) ++s0;   // any staged slot gives the common layout
+    StepArgs a = b->h[s0]->args;
+    const ptrdiff_t shift = -ptrdiff_t(size_t(s0) * b->stride);
+    auto mv = [&](auto* p) -> decltype(p) {
+      using B = typename std::conditional<std::is_const<typename std::remove_pointer<decltype(p)>::type>::value,
+                                          const unsigned char, unsigned char>::type;
+      return p ? reinterpret_cast<decltype(p)>(reinterpret_cast<B*>(p) + shift) : p;
+    };
+    a.u = mv(a.u); a.v = mv(a.v); a.spec = mv(a.spec); a.dspec = mv(a.dspec); a.tw = mv(a.tw); a.kv = mv(a.kv);
+    a.sig = mv(a.sig); a.q = mv(a.q); a.qflag = mv(a.qflag); a.phi_int = mv(a.phi_int); a.partial = mv(a.partial);
+    a.readings = mv(a.readings); a.resid = mv(a.resid); a.det = mv(a.det); a.ctl = mv(a.ctl);
+    a.stream = b->stream;
+    a.nslot = rows;
+    a.sstride = (long long)b->stride;
+    e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      hipError_t e2 = hipError_t(launch_enqueue_op(b->cfg.n, a, step_op(), nullptr));
+      e = hipStreamEndCapture(b->stream, &b->graph[rows - 1]);
+      if (e2 != hipSuccess) e = e2;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec[rows - 1], b->graph[rows - 1], nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      b->exec[rows - 1] = nullptr;
+      return RTE_EDEVICE;
+    }
+  }
+  for (int64_t i = 0; i < nsteps && e == hipSuccess; ++i) e = hipGraphLaunch(b->exec[rows - 1], b->stream);
+  if (e != hipSuccess) return RTE_EDEVICE;
+  // control blocks of the slot rows after this chunk, into the pinned ring
+  const int idx = int(b->seq % kBatchRing);
+  if (b->ring_seq[idx] >= 0) e = hipEventSynchronize(b->ring_ev[idx]);   // at most kBatchRing chunks in flight
+  if (e == hipSuccess)
+    e = hipMemcpy2DAsync(b->snap + size_t(idx) * b->slots, sizeof(Ctl), b->ws + b->ctl_off, b->stride, sizeof(Ctl),
+                         size_t(rows), hipMemcpyDeviceToHost, b->stream);
+  if (e == hipSuccess) e = hipEventRecord(b->ring_ev[idx], b->stream);
+  if (e != hipSuccess) return RTE_EDEVICE;
+  b->ring_seq[idx] = b->seq;
+  b->ring_rows[idx] = rows;
+  b->seq += 1;
+  return RTE_OK;
+}
+
+int rte_batch_poll(rte_batch* b, int64_t* steps_done, int32_t* status, int32_t* in_flight) {
+  using namespace rte;
+  if (!b) return RTE_EINVAL;
+  std::lock_guard<std::mutex> lk(b->mu);
+  // newest chunk whose control-block copies have landed
+  int best = -1, pending = 0;
+  for (int i = 0; i < kBatchRing; ++i) {
+    if (b->ring_seq[i] < 0) continue;
+    const hipError_t q = hipEventQuery(b->ring_ev[i]);
+    if (q == hipErrorNotReady) {
+      ++pending;
+      continue;
+    }
+    if (q != hipSuccess) return RTE_EDEVICE;
+    if (best < 0 || b->ring_seq[i] > b->ring_seq[best]) best = i;
+  }
+  if (in_flight) *in_flight = pending;
+  for (int s = 0; s < b->slots; ++s) {
+    if (b->state[s] == SLOT_RUNNING && best >= 0 && b->ring_seq[best] >= b->start_seq[s] && s < b->ring_rows[best]) {
+      const Ctl& c = b->snap[size_t(best) * b->slots + s];
+      b->final_step[s] = c.step;
+      if (c.stop == 3) b->state[s] = SLOT_DONE;
+      else if (c.stop != 0) b->state[s] = SLOT_FAILED;
+    }
+    if (status) status[s] = b->state[s];
+    if (steps_done)
+      steps_done[s] = (b->state[s] == SLOT_RUNNING || b->state[s] == SLOT_DONE || b->state[s] == SLOT_FAILED)
+                          ? b->final_step[s] : 0;
+  }
+  return RTE_OK;
+}
+
+int rte_batch_handle(rte_batch* b, int32_t slot, rte_handle** out) {
+  using namespace rte;
+  if (!b || !out || slot < 0 || slot >= b->slots) return RTE_EINVAL;
+  std::lock_guard<std::mutex> lk(b->mu);
+  if (b->state[slot] != SLOT_DONE && b->state[slot] != SLOT_FAILED) return RTE_EINVAL;
+  *out = b->h[slot];
+  return RTE_OK;
+}
+
+int rte_batch_release(rte_batch* b, int32_t slot) {
+  using namespace rte;
+  if (!b || slot < 0 || slot >= b->slots) return RTE_EINVAL;
+  std::lock_guard<std::mutex> lk(b->mu);
+  const int st = b->state[slot];
+  if (st != SLOT_DONE && st != SLOT_FAILED && st != SLOT_STAGED) return RTE_EINVAL;
+  if (b->h[slot]) {
+    b->h[slot]->batch_owned = false;
+    rte_destroy(b->h[slot]);
+    b->h[slot] = nullptr;
+  }
+  b->state[slot] = SLOT_FREE;
+  b->final_step[slot] = 0;
+  return RTE_OK;
+}
+
+void rte_batch_destroy(rte_batch* b) {
+  if (!b) return;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  if (b->stage) (void)hipStreamSynchronize(b->stage);
+  if (b->read) (void)hipStreamSynchronize(b->read);
+  for (size_t k = 0; k < b->exec.size(); ++k) {
+    if (b->exec[k]) (void)hipGraphExecDestroy(b->exec[k]);
+    if (b->graph[k]) (void)hipGraphDestroy(b->graph[k]);
+  }
+  for (auto* h : b->h)
+    if (h) {
+      h->batch_owned = false;
+      rte_destroy(h);
+    }
+  for (auto ev : b->staged_ev)
+    if (ev) (void)hipEventDestroy(ev);
+  for (int i = 0; i < rte::kBatchRing; ++i)
+    if (b->ring_ev[i]) (void)hipEventDestroy(b->ring_ev[i]);
+  if (b->snap) (void)hipHostFree(b->snap);
+  if (b->stage) (void)hipStreamDestroy(b->stage);
+  if (b->read) (void)hipStreamDestroy(b->read);
+  delete b;
 }
 
 }  // extern "C"

@@ -27,8 +27,11 @@ EXPORTS = (
     "rte_set_state", "rte_coupling_dense", "rte_profile_kernels", "rte_destroy",
     "rte_strerror", "rte_adjoint_workspace_bytes", "rte_forward_checkpointed",
     "rte_adjoint", "rte_krylov_workspace_bytes", "rte_steady_gmres", "rte_expo_advance",
-    "rte_profile_expo", "rte_set_source_profile",
+    "rte_profile_expo", "rte_set_source_profile", "rte_snapshot_bytes", "rte_snapshot",
+    "rte_restore", "rte_batch_slot_bytes", "rte_batch_create", "rte_batch_admit", "rte_batch_step",
+    "rte_batch_poll", "rte_batch_handle", "rte_batch_release", "rte_batch_destroy",
 )
+RTE_SLOT_FREE, RTE_SLOT_STAGING, RTE_SLOT_STAGED, RTE_SLOT_RUNNING, RTE_SLOT_DONE, RTE_SLOT_FAILED = range(6)
 KERNEL_CLASSES = ("fwd_plane", "zderiv", "couple", "inv_plane", "end_step",
                   "fwd_rows", "y_fwd", "y_inv", "inv_rows", "z_fwd", "expo", "z_inv", "expo_table")
 
@@ -113,6 +116,28 @@ def lib():
         L.rte_set_source_profile.restype = C.c_int
         L.rte_profile_expo.argtypes = [vp, C.c_double, dp, C.POINTER(C.c_int64)]
         L.rte_profile_expo.restype = C.c_int
+        L.rte_snapshot_bytes.argtypes = [vp]
+        L.rte_snapshot_bytes.restype = C.c_size_t
+        L.rte_snapshot.argtypes = [vp, vp, C.c_size_t]
+        L.rte_snapshot.restype = C.c_int
+        L.rte_restore.argtypes = [vp, vp, C.c_size_t]
+        L.rte_restore.restype = C.c_int
+        L.rte_batch_slot_bytes.argtypes = [C.POINTER(rte_config)]
+        L.rte_batch_slot_bytes.restype = C.c_size_t
+        L.rte_batch_create.argtypes = [C.POINTER(rte_config), C.c_int32, vp, C.c_size_t, vp, C.POINTER(vp)]
+        L.rte_batch_create.restype = C.c_int
+        L.rte_batch_admit.argtypes = [vp, C.c_int32, C.POINTER(rte_medium), C.POINTER(C.c_int64), C.c_int64]
+        L.rte_batch_admit.restype = C.c_int
+        L.rte_batch_step.argtypes = [vp, C.c_int64]
+        L.rte_batch_step.restype = C.c_int
+        L.rte_batch_poll.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.rte_batch_poll.restype = C.c_int
+        L.rte_batch_handle.argtypes = [vp, C.c_int32, C.POINTER(vp)]
+        L.rte_batch_handle.restype = C.c_int
+        L.rte_batch_release.argtypes = [vp, C.c_int32]
+        L.rte_batch_release.restype = C.c_int
+        L.rte_batch_destroy.argtypes = [vp]
+        L.rte_batch_destroy.restype = None
         L.rte_destroy.argtypes = [vp]
         L.rte_destroy.restype = None
         L.rte_strerror.argtypes = [C.c_int]
@@ -257,6 +282,20 @@ class Solver:
         a = _f64(psi).ravel()
         _check(lib().rte_set_state(self.h, _dptr(a), a.size), "rte_set_state")
 
+    def snapshot(self) -> bytes:
+        """Checkpoint of the run (state, step count, integrated fluence,
+        record, flags) as host bytes."""
+        nb = int(lib().rte_snapshot_bytes(self.h))
+        buf = (C.c_ubyte * nb)()
+        _check(lib().rte_snapshot(self.h, C.cast(buf, C.c_void_p), nb), "rte_snapshot")
+        return bytes(buf)
+
+    def restore(self, snap: bytes):
+        """Resume from a snapshot taken on a solver with the same
+        configuration, detectors, maps and source."""
+        buf = C.create_string_buffer(bytes(snap), len(snap))
+        _check(lib().rte_restore(self.h, C.cast(buf, C.c_void_p), len(snap)), "rte_restore")
+
     # -- time-dependent source ---------------------------------------------
     def set_source_profile(self, samples, delta_ps: float, rows: int):
         """Source q(r) s(t), s linear between samples spaced delta_ps apart
@@ -355,6 +394,100 @@ class Solver:
             self.stream.synchronize()
             lib().rte_destroy(self.h)
             self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many solves of one configuration advanced together (``rte_batch_*``):
+    ``slots`` slots in one torch-owned workspace, stepped in chunks on
+    ``self.stream``; requests are admitted into free slots (from any
+    thread), polled, read and released."""
+
+    def __init__(self, n, N, dx, c, dt, W, slots, mu0=0.01, mu1=1.0, precision="f32",
+                 n_det=0, record_steps=0, scheme="rk4", stream=None, device="cuda"):
+        import torch
+        self.n, self.N, self.M, self.slots = n, N, (N + 1) ** 2, int(slots)
+        prec = RTE_FP64 if precision in ("f64", RTE_FP64) else RTE_FP32
+        sch = RTE_EULER if scheme in ("euler", RTE_EULER) else RTE_RK4
+        self.cfg, _ = make_config(n, N, prec, dx, c, dt, W, mu0, mu1, None, record_steps, sch)
+        self.cfg.n_det = int(n_det)
+        self.n_det = int(n_det)
+        self.slot_bytes = int(lib().rte_batch_slot_bytes(C.byref(self.cfg)))
+        if self.slot_bytes == 0:
+            raise RteError(RTE_EINVAL, "rte_batch_slot_bytes")
+        self.workspace = torch.empty(self.slot_bytes * self.slots, dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device)
+        b = C.c_void_p()
+        _check(lib().rte_batch_create(C.byref(self.cfg), self.slots, C.c_void_p(self.workspace.data_ptr()),
+                                      self.workspace.numel(), C.c_void_p(self.stream.cuda_stream), C.byref(b)),
+               "rte_batch_create")
+        self.b = b
+        self._steps = np.zeros(self.slots, np.int64)
+        self._status = np.zeros(self.slots, np.int32)
+
+    def admit(self, slot, mu_a, mu_s, g, steps, psi0=None, q=None, det_index=None):
+        n = self.n
+        arrs = [_f64(mu_a), _f64(mu_s), _f64(g), _f64(psi0), _f64(q)]
+        pm = 0 if psi0 is None else arrs[3].size // n ** 3
+        qm = 0 if q is None else arrs[4].size // n ** 3
+        med = rte_medium(*[_dptr(a) for a in arrs], pm, qm)
+        det = np.ascontiguousarray(det_index if det_index is not None else [], np.int64)
+        if det.size != self.n_det:
+            raise RteError(RTE_EINVAL, "detector count differs from the batch configuration")
+        dp = det.ctypes.data_as(C.POINTER(C.c_int64)) if det.size else None
+        _check(lib().rte_batch_admit(self.b, int(slot), C.byref(med), dp, int(steps)), "rte_batch_admit")
+
+    def step(self, k: int):
+        _check(lib().rte_batch_step(self.b, int(k)), "rte_batch_step")
+
+    def poll(self):
+        """(steps_done[slots], status[slots], chunks in flight) from the
+        newest completed chunk."""
+        fl = C.c_int32(0)
+        _check(lib().rte_batch_poll(self.b, self._steps.ctypes.data_as(C.POINTER(C.c_int64)),
+                                    self._status.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(fl)),
+               "rte_batch_poll")
+        return self._steps.copy(), self._status.copy(), int(fl.value)
+
+    def _handle(self, slot):
+        h = C.c_void_p()
+        _check(lib().rte_batch_handle(self.b, int(slot), C.byref(h)), "rte_batch_handle")
+        return h
+
+    def fluence(self, slot, which: int = RTE_FLUENCE_NOW) -> np.ndarray:
+        out = np.zeros(self.n ** 3)
+        _check(lib().rte_fluence(self._handle(slot), which, _dptr(out), out.size), "rte_fluence")
+        return out.reshape(self.n, self.n, self.n)
+
+    def get_state(self, slot) -> np.ndarray:
+        out = np.zeros(self.M * self.n ** 3)
+        _check(lib().rte_get_state(self._handle(slot), _dptr(out), out.size), "rte_get_state")
+        return out.reshape(self.M, self.n, self.n, self.n)
+
+    def readings(self, slot) -> np.ndarray:
+        cap = max(1, int(self.cfg.record_steps) * max(self.n_det, 1))
+        out = np.zeros(cap)
+        rows = C.c_int64(0)
+        _check(lib().rte_readings(self._handle(slot), _dptr(out), out.size, C.byref(rows)), "rte_readings")
+        return out[: rows.value * self.n_det].reshape(rows.value, self.n_det)
+
+    def steps_done(self, slot) -> int:
+        s = C.c_int64(0)
+        _check(lib().rte_steps_done(self._handle(slot), C.byref(s)), "rte_steps_done")
+        return int(s.value)
+
+    def release(self, slot):
+        _check(lib().rte_batch_release(self.b, int(slot)), "rte_batch_release")
+
+    def close(self):
+        if getattr(self, "b", None):
+            lib().rte_batch_destroy(self.b)
+            self.b = None
 
     def __del__(self):
         try:

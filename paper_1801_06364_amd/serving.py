@@ -1,37 +1,38 @@
 """Continuous-batching request server for P_N transport solves on one GPU.
 
 Requests (grid size, P_N order, optical maps, step count) arrive over time.
-A request is admitted as soon as it has arrived, a slot is free and its
-device workspace (``rte_workspace_bytes``) fits the HBM budget next to the
-requests already resident; admission is first-come first-served (the head
-of the queue is never overtaken, so no request starves). Each admitted
-request gets its own solver handle, device-resident state and HIP stream,
-and all of its RK4 steps are queued at once as replays of its captured
-step graph; requests on different streams run concurrently on the GPU, so
-small grids fill the compute units left idle by large ones and newly
-admitted requests start while earlier ones are still running. A request
-retires when the event recorded after its last step completes; its
-workspace is released and the next request can be admitted.
+Requests of one configuration class (grid size and order; spacing, time
+step, layer and precision follow from them) share a batch engine
+(``rte.Batch``): up to ``slots`` resident solves in one device workspace,
+every kernel of a time step launched once for all of them (the slot is a grid
+coordinate) from a captured graph, in chunks of ``chunk`` steps on the
+engine's own stream. Engines of different classes run on different streams
+and overlap on the GPU.
 
-Admission has two lanes, each first-come first-served: requests whose
-workspace exceeds ``large_bytes`` (large grids / high orders, which on their
-own already keep HBM busy) share ``large_slots`` slots, the others the
-remaining slots, so a short request never queues behind a long one and no
-request is overtaken within its lane (no starvation). The total resident
-workspace never exceeds the budget.
+Admission: a request waits in its class's first-come first-served queue
+until its engine has a free slot; an engine's workspace is allocated when
+its class first needs it and counts against the HBM budget, and idle engines
+are released when another class needs the memory. The oldest waiting request
+has priority for memory (no other engine is created while it waits), so no
+request starves. Building a request's phantom and uploading its tables and
+state (``rte_batch_admit``) happen on worker threads; the serving thread only
+queues chunks, polls the engines' control-block copies (non-blocking) and
+reads finished results, so a large admission never delays the retirement of
+other requests.
 
-The one-at-a-time baseline serves the same trace first-come first-served on
-one stream: each request's service time is measured alone, and the FIFO
-single-server queue is replayed from those times.
+The one-at-a-time baseline serves the same trace first-come first-served:
+each request's service time is measured alone (its own solver and step
+graph), and the single-server queue is replayed from those times.
 
-Every result is computed by the same kernels in the same order whether a
-request runs alone or in the mix, so the fluence is bitwise identical.
+A slot runs the same kernels in the same order as a solver alone, so every
+fluence is bitwise identical alone and in the mix.
 """
 from __future__ import annotations
 
 import collections
-import math
+import hashlib
 import time
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 from typing import Dict, List, Optional
 
@@ -49,7 +50,7 @@ class Result:
     ok: bool = False
     error: str = ""
     updates: int = 0
-    checksum: float = 0.0
+    digest: str = ""            # SHA-256 of the final fluence's bytes
     fluence: Optional[np.ndarray] = None
 
     @property
@@ -63,7 +64,8 @@ class Report:
     results: Dict[int, Result] = field(default_factory=dict)
     makespan: float = 0.0
     peak_resident_bytes: int = 0
-    peak_slots: int = 0
+    peak_slots: int = 0          # requests running at once (all engines)
+    peak_batch: int = 0          # requests running at once in one batch (one launch per kernel)
 
     def latencies(self) -> np.ndarray:
         return np.array([r.latency for r in self.results.values() if r.ok])
@@ -79,122 +81,192 @@ class Report:
                 "makespan_s": self.makespan,
                 "updates_per_s": ups / self.makespan if self.makespan > 0 else None,
                 "peak_resident_GiB": self.peak_resident_bytes / 2 ** 30,
-                "peak_concurrent": self.peak_slots}
-
-
-def footprint(spec, precision: str = "f32") -> int:
-    """Device bytes a request needs (its solver workspace)."""
-    prec = rte.RTE_FP64 if precision == "f64" else rte.RTE_FP32
-    cfg, _ = rte.make_config(spec.n, spec.N, prec, 0.25, 0.3, 0.0, spec.n // 8, 0.01, 1.0)
-    return rte.rte_workspace_bytes(cfg)
+                "peak_concurrent": self.peak_slots, "peak_batch": self.peak_batch}
 
 
 def updates_of(spec) -> int:
     return spec.n ** 3 * (spec.N + 1) ** 2 * 4 * spec.steps
 
 
-class Server:
-    """Continuous batching over ``max_slots`` concurrent solves within an
-    HBM budget of ``budget_bytes``; at most ``large_slots`` of them may be
-    requests larger than ``large_bytes``."""
+def digest_of(fl: np.ndarray) -> str:
+    return hashlib.sha256(np.ascontiguousarray(fl).tobytes()).hexdigest()
 
-    def __init__(self, budget_bytes: int = 12 << 30, max_slots: int = 12,
-                 precision: str = "f32", keep_fluence: bool = False,
-                 large_bytes: int = 512 << 20, large_slots: int = 2):
+
+def class_of(spec):
+    """Configuration class of a request: requests of one class share a
+    batch. A request's spacing, time step and layer follow from its grid
+    size (RequestSpec.workload), so the class is (grid size, order)."""
+    return (spec.n, spec.N)
+
+
+class _Engine:
+    """One batch of a configuration class and its serving state."""
+
+    def __init__(self, key, wl, slots, precision, chunk):
+        self.key = key
+        self.batch = rte.Batch(wl.n, wl.N, wl.dx, wl.c, wl.dt, wl.W, slots, wl.mu0, wl.mu1,
+                               precision=precision, n_det=0, record_steps=0)
+        self.nbytes = self.batch.workspace.numel()
+        self.free = list(range(slots - 1, -1, -1))
+        self.pending = {}        # slot -> (index, future) while staging
+        self.running = {}        # slot -> index
+        self.chunk = chunk
+
+    def busy(self) -> bool:
+        return bool(self.pending or self.running)
+
+    def close(self):
+        self.batch.close()
+
+
+class Server:
+    """Continuous batching within an HBM budget of ``budget_bytes``; each
+    class's engine holds up to ``max_slots`` solves (fewer if one class
+    would take more than ``class_share`` of the budget)."""
+
+    def __init__(self, budget_bytes: int = 48 << 30, max_slots: int = 16, precision: str = "f32",
+                 keep_fluence: bool = False, chunk: int = 16, class_share: float = 0.25,
+                 workers: int = 2):
         import torch
         self.torch = torch
         self.budget = int(budget_bytes)
         self.max_slots = int(max_slots)
-        self.large_bytes = int(large_bytes)
-        self.large_slots = max(1, min(int(large_slots), self.max_slots - 1)) \
-            if self.max_slots > 1 else 1
         self.precision = precision
         self.keep = keep_fluence
-        self.streams = [torch.cuda.Stream() for _ in range(self.max_slots)]
+        self.chunk = int(chunk)
+        self.class_share = float(class_share)
+        self.workers = int(workers)
 
-    def _finish(self, res: Result, solver, t0: float):
-        try:
-            solver.steps_done()            # raises on a non-finite / runaway run
-            fl = solver.fluence()
-            res.ok = bool(np.all(np.isfinite(fl)))
-            if not res.ok:
-                res.error = "non-finite fluence"
-            res.checksum = float(fl.sum())
-            if self.keep:
-                res.fluence = fl
-        except rte.RteError as e:          # e.g. unstable run
-            res.ok, res.error = False, str(e)
-        res.finished = time.perf_counter() - t0
+    def _slots_for(self, spec):
+        wl = spec.workload(self.precision)
+        cfg, _ = rte.make_config(wl.n, wl.N, rte.RTE_FP64 if self.precision == "f64" else rte.RTE_FP32,
+                                 wl.dx, wl.c, wl.dt, wl.W, wl.mu0, wl.mu1)
+        per = int(rte.lib().rte_batch_slot_bytes(cfg))
+        return max(1, min(self.max_slots, int(self.class_share * self.budget) // per)), per
+
+    @staticmethod
+    def _admit(engine, slot, spec, precision):
+        wl = spec.workload(precision)
+        engine.batch.admit(slot, wl.mu_a, wl.mu_s, wl.g, spec.steps, psi0=wl.psi0, q=wl.q)
 
     def serve(self, specs: List, arrivals: List[float]) -> Report:
         """Serve requests whose arrival times (seconds from start) are given."""
         order = sorted(range(len(specs)), key=lambda i: arrivals[i])
         incoming = collections.deque(order)
-        sizes = [footprint(sp, self.precision) for sp in specs]
-        lanes = {False: collections.deque(), True: collections.deque()}   # large?
-        slots = {True: list(range(self.large_slots)),
-                 False: list(range(self.large_slots, self.max_slots))}
-        if not slots[False]:
-            slots[False] = slots[True]
+        waiting = collections.OrderedDict()     # class -> deque of request indices (FIFO)
+        engines: Dict[tuple, _Engine] = {}
+        slot_info = {}
+        for i, sp in enumerate(specs):
+            k = class_of(sp)
+            if k not in slot_info:
+                slot_info[k] = self._slots_for(sp)
         rep = Report("batched")
-        active = {}            # slot -> (index, solver, event, bytes, large)
         resident = 0
+        pool = ThreadPoolExecutor(self.workers)
         t0 = time.perf_counter()
-        while incoming or active or lanes[False] or lanes[True]:
-            now = time.perf_counter() - t0
-            progressed = False
-            for slot in list(active):
-                i, solver, ev, nb, big = active[slot]
-                if ev.query():
-                    res = rep.results[specs[i].rid]
-                    self._finish(res, solver, t0)
-                    solver.close()
-                    del active[slot]
-                    slots[big].append(slot)
-                    resident -= nb
-                    progressed = True
-            while incoming and arrivals[incoming[0]] <= now:
-                i = incoming.popleft()
-                lanes[sizes[i] > self.large_bytes].append(i)
-            for big in (False, True):
-                q = lanes[big]
-                while q and slots[big]:
-                    i = q[0]
-                    nb = sizes[i]
-                    if resident + nb > self.budget and active:
-                        break               # wait for memory; keep FIFO order
-                    q.popleft()
-                    slot = slots[big].pop()
-                    spec = specs[i]
-                    res = Result(spec.rid, arrivals[i], admitted=time.perf_counter() - t0,
-                                 updates=updates_of(spec))
-                    rep.results[spec.rid] = res
-                    try:
-                        solver = rte.Solver.from_workload(spec.workload(self.precision),
-                                                          stream=self.streams[slot], record_steps=0)
-                        solver.step(spec.steps)
-                    except rte.RteError as e:
-                        res.ok, res.error = False, str(e)
-                        res.finished = time.perf_counter() - t0
-                        slots[big].append(slot)
+        try:
+            while incoming or any(waiting.values()) or any(e.busy() for e in engines.values()):
+                now = time.perf_counter() - t0
+                while incoming and arrivals[incoming[0]] <= now:
+                    i = incoming.popleft()
+                    waiting.setdefault(class_of(specs[i]), collections.deque()).append(i)
+                # admissions: per class FIFO; the oldest waiting request has
+                # priority for memory
+                oldest = min((q[0] for q in waiting.values() if q), key=lambda j: arrivals[j], default=None)
+                order_k = sorted((k for k, q in waiting.items() if q), key=lambda k: arrivals[waiting[k][0]])
+                for k in order_k:
+                    q = waiting[k]
+                    if oldest is not None and k != class_of(specs[oldest]) and \
+                            class_of(specs[oldest]) not in engines:
+                        break   # the oldest request waits for memory: others do not overtake it
+                    while q:
+                        e = engines.get(k)
+                        if e is None:
+                            slots, per = slot_info[k]
+                            if per > self.budget:
+                                i = q.popleft()   # cannot fit even alone
+                                rep.results[specs[i].rid] = Result(specs[i].rid, arrivals[i], now, now,
+                                                                   False, "exceeds the HBM budget",
+                                                                   updates_of(specs[i]))
+                                continue
+                            slots = min(slots, self.budget // per)
+                            if resident + slots * per > self.budget:
+                                for kk in [kk for kk, ee in engines.items() if not ee.busy()]:
+                                    resident -= engines[kk].nbytes
+                                    engines.pop(kk).close()
+                            if resident + slots * per > self.budget:
+                                break
+                            e = engines[k] = _Engine(k, specs[q[0]].workload(self.precision), slots,
+                                                     self.precision, self.chunk)
+                            resident += e.nbytes
+                            rep.peak_resident_bytes = max(rep.peak_resident_bytes, resident)
+                        if not e.free:
+                            break
+                        i = q.popleft()
+                        slot = e.free.pop()
+                        sp = specs[i]
+                        rep.results[sp.rid] = Result(sp.rid, arrivals[i], admitted=time.perf_counter() - t0,
+                                                     updates=updates_of(sp))
+                        e.pending[slot] = (i, pool.submit(self._admit, e, slot, sp, self.precision))
+                # staged admissions become running at the engine's next chunk
+                for e in engines.values():
+                    for slot, (i, fut) in list(e.pending.items()):
+                        if not fut.done():
+                            continue
+                        del e.pending[slot]
+                        err = fut.exception()
+                        if err is not None:
+                            res = rep.results[specs[i].rid]
+                            res.ok, res.error = False, str(err)
+                            res.finished = time.perf_counter() - t0
+                            e.free.append(slot)
+                        else:
+                            e.running[slot] = i
+                rep.peak_slots = max(rep.peak_slots, sum(len(e.running) for e in engines.values()))
+                rep.peak_batch = max([rep.peak_batch] + [len(e.running) for e in engines.values()])
+                # queue chunks, poll, retire
+                progressed = False
+                for e in engines.values():
+                    if not e.running:
                         continue
-                    ev = self.torch.cuda.Event()
-                    ev.record(self.streams[slot])
-                    active[slot] = (i, solver, ev, nb, big)
-                    resident += nb
-                    rep.peak_resident_bytes = max(rep.peak_resident_bytes, resident)
-                    rep.peak_slots = max(rep.peak_slots, len(active))
-                    progressed = True
-            if not progressed:
-                time.sleep(2e-4)
+                    steps, status, in_flight = e.batch.poll()
+                    for slot, i in list(e.running.items()):
+                        st = status[slot]
+                        if st not in (rte.RTE_SLOT_DONE, rte.RTE_SLOT_FAILED):
+                            continue
+                        res = rep.results[specs[i].rid]
+                        if st == rte.RTE_SLOT_DONE:
+                            fl = e.batch.fluence(slot)
+                            res.ok = bool(np.all(np.isfinite(fl)))
+                            res.error = "" if res.ok else "non-finite fluence"
+                            res.digest = digest_of(fl)
+                            if self.keep:
+                                res.fluence = fl
+                        else:
+                            res.ok, res.error = False, "unstable run (non-finite or runaway fluence)"
+                        res.finished = time.perf_counter() - t0
+                        e.batch.release(slot)
+                        del e.running[slot]
+                        e.free.append(slot)
+                        progressed = True
+                    if e.running and in_flight < 2:
+                        e.batch.step(e.chunk)     # keeps two chunks queued per engine
+                        progressed = True
+                if not progressed:
+                    time.sleep(2e-4)
+        finally:
+            pool.shutdown(wait=True)
+            for e in engines.values():
+                e.close()
         rep.makespan = time.perf_counter() - t0 - (min(arrivals) if arrivals else 0.0)
         return rep
 
     def service_times(self, specs: List) -> Dict[int, Result]:
-        """Each request alone on one stream (back to back): the measured
-        service time is finished - admitted."""
+        """Each request alone on one stream (back to back), through its own
+        solver and captured step graph: the measured service time is
+        finished - admitted."""
         out = {}
-        st = self.streams[0]
+        st = self.torch.cuda.Stream()
         t0 = time.perf_counter()
         for spec in specs:
             res = Result(spec.rid, 0.0, admitted=time.perf_counter() - t0, updates=updates_of(spec))
@@ -203,7 +275,14 @@ class Server:
                                                   record_steps=0)
                 solver.step(spec.steps)
                 st.synchronize()
-                self._finish(res, solver, t0)
+                solver.steps_done()            # raises on a non-finite / runaway run
+                fl = solver.fluence()
+                res.ok = bool(np.all(np.isfinite(fl)))
+                res.error = "" if res.ok else "non-finite fluence"
+                res.digest = digest_of(fl)
+                if self.keep:
+                    res.fluence = fl
+                res.finished = time.perf_counter() - t0
                 solver.close()
             except rte.RteError as e:
                 res.ok, res.error = False, str(e)
@@ -223,7 +302,7 @@ def fifo_replay(specs: List, arrivals: List[float], alone: Dict[int, Result]) ->
         start = max(arrivals[i], t_free)
         t_free = start + svc
         rep.results[specs[i].rid] = Result(specs[i].rid, arrivals[i], start, t_free, a.ok, a.error,
-                                           a.updates, a.checksum)
+                                           a.updates, a.digest)
     first = min(arrivals) if arrivals else 0.0
     rep.makespan = t_free - first
     rep.peak_slots = 1

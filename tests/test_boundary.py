@@ -128,3 +128,44 @@ def test_krylov_workspace_bytes_bounds():
     for m in (1, 16, 31):
         b = lib.rte_krylov_workspace_bytes(cfg, m)
         assert (m + 3) * F <= b <= (m + 3) * F + (1 << 20)
+
+
+def _create_code(cfg, n, ws_ptr, ws_bytes):
+    """rte_create on host maps with the given workspace pointer value; the
+    argument checks run before any device call."""
+    import ctypes as C
+    ma, ms, gg, q = (np.full(n ** 3, v) for v in (0.01, 10.0, 0.9, 1.0))
+    # with a source the workspace layout is the one rte_workspace_bytes sizes
+    med = rte.rte_medium(*[rte._dptr(a) for a in (ma, ms, gg)], None, rte._dptr(q), 0, 1)
+    h = C.c_void_p()
+    return rte.lib().rte_create(C.byref(cfg), C.byref(med), C.c_void_p(ws_ptr), C.c_size_t(ws_bytes),
+                                None, C.byref(h)), h
+
+
+def test_create_rejects_small_or_misaligned_workspace():
+    """RTE_ENOMEM for a missing, misaligned or one-byte-short workspace
+    (refused before the workspace is touched)."""
+    n = 16
+    cfg, _keep = rte.make_config(n, 1, rte.RTE_FP32, 0.5, 0.3, 0.0, 2, 0.01, 1.0,
+                                 det_index=[3, 7], record_steps=4)
+    need = rte.rte_workspace_bytes(cfg)
+    assert need > 0
+    for ptr, nb in ((0, need), (256 * 1024 + 8, need), (256 * 1024, need - 1), (256 * 1024, 0)):
+        rc, h = _create_code(cfg, n, ptr, nb)
+        assert rc == rte.RTE_ENOMEM and not h.value, (ptr, nb, rc)
+
+
+def test_create_rejects_duplicate_detectors():
+    """A detector voxel listed twice is refused (RTE_EINVAL): the adjoint
+    injects each reading's source at its own voxel."""
+    n = 16
+    cfg, _keep = rte.make_config(n, 1, rte.RTE_FP32, 0.5, 0.3, 0.0, 2, 0.01, 1.0,
+                                 det_index=[3, 7, 3], record_steps=4)
+    # one byte short: were the detector check ever moved after the workspace
+    # check, the call would still fail before touching the device
+    rc, h = _create_code(cfg, n, 256 * 1024, rte.rte_workspace_bytes(cfg) - 1)
+    assert rc == rte.RTE_EINVAL and not h.value
+    cfg, _keep = rte.make_config(n, 1, rte.RTE_FP32, 0.5, 0.3, 0.0, 2, 0.01, 1.0,
+                                 det_index=[3, 7, n ** 3], record_steps=4)
+    rc, h = _create_code(cfg, n, 256 * 1024, rte.rte_workspace_bytes(cfg) - 1)
+    assert rc == rte.RTE_EINVAL and not h.value

@@ -164,7 +164,11 @@ def test_full_size_adjoint_vs_finite_differences(torch_cuda):
         s.forward_checkpointed(steps, 0)
         grads[w.precision] = s.adjoint(djdr)
         s.close()
-    assert rel(grads["f32"][0], grads["f64"][0]) <= 1e-3
+    # FP32 against FP64 gradient: the reading A14 proposes (1e-4 relative L2)
+    e32 = rel(grads["f32"][0], grads["f64"][0])
+    print(f"[adjoint] FP32 vs FP64 gradient rel-L2 {e32:.2e}", flush=True)
+    assert e32 <= 1e-4
+    assert rel(grads["f32"][1], grads["f64"][1]) <= 1e-4
     rng = np.random.default_rng(5)
     omega = np.argwhere(pn.pml_depth(96, wl.W) == 0)
     ga = grads["f64"][0]

@@ -85,8 +85,15 @@ def test_parity_against_oracle(torch_cuda, name, n, steps, prec):
         # a reading is one voxel of a field whose rounding error is set by the
         # whole field (the spectral operator couples every voxel), so the
         # bound is tol times the field's peak at that step
-        err = np.abs(s.readings() - ref["readings"])
+        got_r = s.readings()
+        err = np.abs(got_r - ref["readings"])
         assert np.all(err <= tol * ref["peak"][:, None]), err.max()
+        # where the detectors see a sizeable part of the field, the series
+        # itself meets the bar in relative L2
+        frac = np.linalg.norm(ref["readings"]) / (np.linalg.norm(ref["peak"]) *
+                                                   np.sqrt(wl.det_index.size))
+        if frac >= 1e-2:
+            assert rel(got_r, ref["readings"]) <= tol
     res = s.residuals()
     assert res.shape == (steps,)
     assert np.allclose(res, ref["residual"], rtol=1e-3 if prec == "f32" else 1e-9, atol=1e-7)

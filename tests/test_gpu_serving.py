@@ -1,8 +1,10 @@
-"""Serving: continuous batching of heterogeneous solves on one GPU."""
+"""Serving: continuous batching of heterogeneous solves on one GPU (batched
+launches over the resident solves of each configuration)."""
 import numpy as np
 import pytest
 
 import rte_inputs as ri
+from oracle import pn
 
 pytestmark = pytest.mark.gpu
 
@@ -15,13 +17,19 @@ def torch_cuda():
     return torch
 
 
-def _trace(count=10, seed=11):
-    return ri.serving_requests(count=count, seed=seed, sizes=(32, 48, 64), orders=(1, 3, 5),
-                               steps=(20, 60))
+def rel(a, b):
+    a = np.asarray(a, float).ravel()
+    b = np.asarray(b, float).ravel()
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-class _Unstable:
-    """A request whose time step is far beyond the stability limit."""
+def _trace(count=10, seed=11, sizes=(32, 48, 64), orders=(1, 3, 5), steps=(20, 60)):
+    return ri.serving_requests(count=count, seed=seed, sizes=sizes, orders=orders, steps=steps)
+
+
+class _Poisoned:
+    """A request whose medium has one voxel of absorption so large that the
+    time step is far beyond its stability limit: its run blows up."""
 
     def __init__(self, spec):
         self.__dict__.update(spec.__dict__)
@@ -29,31 +37,111 @@ class _Unstable:
 
     def workload(self, precision="f32"):
         wl = self._spec.workload(precision)
-        wl.dt *= 40.0
+        c = wl.n // 2
+        wl.mu_a = wl.mu_a.copy()
+        wl.mu_a[c, c, c] = 1e4
         return wl
+
+
+def test_batch_slots_match_solvers_alone(torch_cuda):
+    """Three requests of one configuration in one batch, admitted at
+    different times, with different maps and step counts; a finished slot is
+    released and reused. Each slot's fluence and state equal bitwise those of
+    the same request run alone on its own solver."""
+    from paper_1801_06364_amd import rte
+    specs = [ri.RequestSpec(i, 32, 3, st, ns, 100 + i, 1.0) for i, (st, ns) in
+             enumerate([(37, 0), (21, 3), (50, 5), (18, 2)])]
+    alone = {}
+    for sp in specs:
+        s = rte.Solver.from_workload(sp.workload("f32"), record_steps=0)
+        s.step(sp.steps)
+        alone[sp.rid] = s.get_state()
+        s.close()
+    wl = specs[0].workload("f32")
+    b = rte.Batch(wl.n, wl.N, wl.dx, wl.c, wl.dt, wl.W, 3, wl.mu0, wl.mu1, precision="f32")
+
+    def admit(slot, sp):
+        w = sp.workload("f32")
+        b.admit(slot, w.mu_a, w.mu_s, w.g, sp.steps, psi0=w.psi0)
+
+    admit(0, specs[0])
+    admit(2, specs[1])
+    b.step(8)
+    admit(1, specs[2])                 # joins while the others run
+    got, where = {}, {0: specs[0], 2: specs[1], 1: specs[2]}
+    reused = False
+    for _ in range(400):
+        b.step(4)
+        torch_cuda.cuda.synchronize()
+        steps, status, _ = b.poll()
+        for slot, sp in list(where.items()):
+            if status[slot] == rte.RTE_SLOT_DONE:
+                assert steps[slot] == sp.steps and b.steps_done(slot) == sp.steps
+                got[sp.rid] = b.get_state(slot)
+                b.release(slot)
+                del where[slot]
+                if not reused:
+                    admit(slot, specs[3])
+                    where[slot] = specs[3]
+                    reused = True
+            else:
+                assert status[slot] in (rte.RTE_SLOT_RUNNING, rte.RTE_SLOT_STAGED), status
+        if not where:
+            break
+    b.close()
+    assert set(got) == {sp.rid for sp in specs}
+    for sp in specs:
+        assert np.array_equal(got[sp.rid], alone[sp.rid]), sp.rid
 
 
 def test_results_identical_alone_and_in_the_mix(torch_cuda):
     """Every request's fluence is bitwise the same when it runs alone and
-    when it shares the GPU with others (all arriving at once)."""
+    when it shares batched launches with others (all arriving at once)."""
     from paper_1801_06364_amd import serving
-    specs = _trace()
+    specs = _trace(count=12, sizes=(32, 48), orders=(1, 3))
     srv = serving.Server(budget_bytes=8 << 30, max_slots=6, keep_fluence=True)
     alone = srv.service_times(specs)
     rep = srv.serve(specs, [0.0] * len(specs))
-    assert rep.peak_slots > 1
+    assert rep.peak_batch > 1
     for s in specs:
         a, b = alone[s.rid], rep.results[s.rid]
         assert a.ok and b.ok
         assert np.array_equal(a.fluence, b.fluence), s.rid
+        assert a.digest == b.digest
+
+
+def test_served_results_match_oracle(torch_cuda):
+    """A handful of mixed requests served together (FP32, batched) against
+    the FP64 oracle run on each request alone: fluence within 1e-5 relative
+    L2."""
+    from paper_1801_06364_amd import serving
+    specs = _trace(count=6, seed=21, sizes=(16, 32), orders=(1, 3), steps=(8, 20))
+    srv = serving.Server(budget_bytes=4 << 30, max_slots=4, keep_fluence=True)
+    rep = srv.serve(specs, [0.0] * len(specs))
+    assert rep.peak_batch > 1
+    for sp in specs:
+        res = rep.results[sp.rid]
+        assert res.ok, res.error
+        wl = sp.workload("f64")
+        ref = pn.solve(wl.n, wl.N, wl.dx, wl.c, wl.dt, wl.mu_a, wl.mu_s, wl.g, wl.psi0, None, wl.W,
+                       wl.mu0, wl.mu1, sp.steps, return_state=False)["fluence"]
+        err = rel(res.fluence, ref)
+        print(f"\n[serving] request {sp.rid} n={sp.n} N={sp.N} steps={sp.steps}: rel-L2 {err:.2e}",
+              flush=True)
+        assert err <= 1e-5
 
 
 def test_admission_respects_memory_budget(torch_cuda):
-    """With a budget that holds only one request at a time every request
-    still completes, in arrival order, never above the budget."""
-    from paper_1801_06364_amd import serving
+    """With a budget that holds one solve at a time every request still
+    completes, in arrival order, never above the budget."""
+    from paper_1801_06364_amd import rte, serving
     specs = _trace(count=5, seed=3)
-    budget = max(serving.footprint(s) for s in specs)
+    per = []
+    for sp in specs:
+        wl = sp.workload("f32")
+        cfg, _ = rte.make_config(wl.n, wl.N, rte.RTE_FP32, wl.dx, wl.c, wl.dt, wl.W, wl.mu0, wl.mu1)
+        per.append(int(rte.lib().rte_batch_slot_bytes(cfg)))
+    budget = max(per)
     srv = serving.Server(budget_bytes=budget, max_slots=4)
     arr = [0.001 * i for i in range(len(specs))]
     rep = srv.serve(specs, arr)
@@ -64,15 +152,16 @@ def test_admission_respects_memory_budget(torch_cuda):
 
 
 def test_poisoned_request_fails_alone(torch_cuda):
-    """An unstable request is reported as failed; the others complete with
-    the same results as alone."""
+    """An unstable request is reported as failed; the others, some in the
+    same batch, complete with the same results as alone."""
     from paper_1801_06364_amd import serving
-    specs = _trace(count=6, seed=5)
-    bad = _Unstable(specs[2])
+    specs = _trace(count=6, seed=5, sizes=(32,), orders=(1,))
+    bad = _Poisoned(specs[2])
     mix = specs[:2] + [bad] + specs[3:]
     srv = serving.Server(budget_bytes=8 << 30, max_slots=6, keep_fluence=True)
     alone = srv.service_times(specs)
     rep = srv.serve(mix, [0.0] * len(mix))
+    assert rep.peak_batch > 1
     assert not rep.results[bad.rid].ok
     for s in specs:
         if s.rid == bad.rid:
