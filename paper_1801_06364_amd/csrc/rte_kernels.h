@@ -1405,7 +1405,30 @@ k_expo_blocks(typename cplx_of<T>::type* __restrict__ spec, const typename cplx_
   expo_blocks<V, T, N>(spec + pt, qs ? qs + pt : nullptr, MS, tab + (size_t)f2 * expo_row_size(N));
 }
 
+}  // namespace rte
+
+#include "rte_plane128.h"
+
+namespace rte {
+
 // ---------------------------------------------------------------- launch ---
+
+// FP32 128^3 time steps and operator applications use the register-fused
+// plane pass (rte_plane128.h); other sizes and FP64 the generic one.
+template <typename T, int NN> constexpr bool plane128() { return std::is_same<T, float>::value && NN == 128; }
+
+// Forward xy transform of `planes` real planes into the packed spectrum
+// (plane grids): the FP32 128^3 path uses the same arithmetic as the forward
+// half of its fused inverse pass.
+template <typename T, int NN>
+void launch_fwd_plane(hipStream_t st, const T* src, typename cplx_of<T>::type* spec,
+                      const typename cplx_of<T>::type* tw, const Ctl* ctl, int planes) {
+  if constexpr (plane128<T, NN>())
+    hipLaunchKernelGGL(p128::k_fwd128<512>, dim3(planes), dim3(512), p128::kLds, st, src, spec, tw, ctl, planes);
+  else
+    hipLaunchKernelGGL((k_fwd_plane<T, NN>), dim3((planes + kFwdPlanes - 1) / kFwdPlanes), dim3(kPBlock),
+                       (plane_lds<T, NN>()), st, src, spec, tw, ctl, planes);
+}
 
 // Grids up to 128 points per axis keep a whole plane in LDS (plane passes);
 // larger grids split each plane pass into a row pass and a y-pencil pass.
@@ -1441,6 +1464,19 @@ hipError_t prepare_t(const StepArgs& a) {
     set(reinterpret_cast<const void*>(&k_inv_plane<T, NN, EPI_MID, true>), plane_lds<T, NN>());
     set(reinterpret_cast<const void*>(&k_inv_plane<T, NN, EPI_LAST, true>), plane_lds<T, NN>());
     set(reinterpret_cast<const void*>(&k_inv_plane<T, NN, EPI_EULER, true>), plane_lds<T, NN>());
+    if constexpr (plane128<T, NN>()) {
+      set(reinterpret_cast<const void*>(&p128::k_fwd128<512>), p128::kLds);
+      set(reinterpret_cast<const void*>(&p128::k_plane128<EPI_FIRST, false>), p128::kLds);
+      set(reinterpret_cast<const void*>(&p128::k_plane128<EPI_MID, false>), p128::kLds);
+      set(reinterpret_cast<const void*>(&p128::k_plane128<EPI_LAST, false>), p128::kLds);
+      set(reinterpret_cast<const void*>(&p128::k_plane128<EPI_ADJ, false>), p128::kLds);
+      set(reinterpret_cast<const void*>(&p128::k_plane128<EPI_EULER, false>), p128::kLds);
+      set(reinterpret_cast<const void*>(&p128::k_plane128<EPI_APPLY, false>), p128::kLds);
+      set(reinterpret_cast<const void*>(&p128::k_plane128<EPI_FIRST, true>), p128::kLds);
+      set(reinterpret_cast<const void*>(&p128::k_plane128<EPI_MID, true>), p128::kLds);
+      set(reinterpret_cast<const void*>(&p128::k_plane128<EPI_LAST, true>), p128::kLds);
+      set(reinterpret_cast<const void*>(&p128::k_plane128<EPI_EULER, true>), p128::kLds);
+    }
   }
   set(reinterpret_cast<const void*>(&k_pencil<T, NN, PENCIL_ZDERIV>), zd_lds<T, NN>());
   set(reinterpret_cast<const void*>(&k_pencil<T, NN, PENCIL_ZFWD>), zd_lds<T, NN>());
@@ -1495,8 +1531,7 @@ void enqueue_stage(const StepArgs& a, ProfRec* pr, double hs, double sgn, const 
   } else if constexpr (!FUSE) {
     // (fused stages find the spectrum of src already written by the
     // previous inverse pass)
-    hipLaunchKernelGGL((k_fwd_plane<T, NN>), dim3((planes + kFwdPlanes - 1) / kFwdPlanes), pblk, lp, st, src,
-                       spec, tw, cctl, planes);
+    launch_fwd_plane<T, NN>(st, src, spec, tw, cctl, planes);
     rec(PROF_FWD_PLANE);
   }
   hipLaunchKernelGGL((k_pencil<T, NN, PENCIL_ZDERIV>), dim3(pencils, ns), zblk, lz, st, spec, dspec, tw, kv, cctl,
@@ -1519,6 +1554,11 @@ void enqueue_stage(const StepArgs& a, ProfRec* pr, double hs, double sgn, const 
     hipLaunchKernelGGL((k_rows_inv<T, NN, MODE>), dim3(rblocks), zblk, lr, st, coupled, src, u, out, sig, q,
                        a.qflag, a.phi_int, a.partial, tw, M, T(hs), a.dt, cctl, stage, step1);
     rec(PROF_INV_ROWS);
+  } else if constexpr (plane128<T, NN>()) {
+    hipLaunchKernelGGL((p128::k_plane128<MODE, FUSE>), dim3(planes, ns), pblk, p128::kLds, st, coupled, src, u,
+                       out, sig, q, a.qflag, a.phi_int, a.partial, tw, M, T(hs), a.dt, cctl, stage, step1,
+                       FUSE ? spec : static_cast<V*>(nullptr), bs);
+    rec(PROF_INV_PLANE);
   } else {
     hipLaunchKernelGGL((k_inv_plane<T, NN, MODE, FUSE>), dim3(planes, ns), pblk, lp, st, coupled, src, u, out,
                        sig, q, a.qflag, a.phi_int, a.partial, tw, M, T(hs), a.dt, cctl, stage, step1,
@@ -1743,13 +1783,11 @@ hipError_t enqueue_t(const StepArgs& a, const OpArgs& op, ProfRec* pr) {
       if constexpr (!split_planes<NN>()) {
         using V = typename cplx_of<T>::type;
         constexpr int planes = M * NN;
-        const size_t lds = plane_lds<T, NN>();
         const T* src = static_cast<const T*>(a.u);
         V* spec = static_cast<V*>(a.spec);
         const V* tw = static_cast<const V*>(a.tw);
         const Ctl* cctl = static_cast<const Ctl*>(a.ctl);
-        hipLaunchKernelGGL((k_fwd_plane<T, NN>), dim3((planes + kFwdPlanes - 1) / kFwdPlanes), dim3(kPBlock),
-                           lds, st, src, spec, tw, cctl, planes);
+        launch_fwd_plane<T, NN>(st, src, spec, tw, cctl, planes);
       }
       break;
     }
