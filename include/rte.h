@@ -238,8 +238,11 @@ int rte_set_source_profile(rte_handle* h, const double* samples, int64_t nsample
  * Instead of marching to steady state, solve for it with a Krylov method
  * (Sec. II.A: the time-integrated form gives an operator whose steady state
  * a Krylov solver can find; Sec. IV: host-side Krylov solvers were limited
- * by transfers). Restarted GMRES with every vector on the device; only the
- * small Hessenberg system lives on the host. Inner product: sum over
+ * by transfers). Restarted GMRES with every vector on the device; each
+ * Arnoldi step (two Gram-Schmidt passes, normalisation, Givens update of
+ * the Hessenberg column, convergence test) runs on the device without a
+ * host round trip, and the host solves the cycle's triangular system once
+ * per restart (two synchronisations per cycle). Inner product: sum over
  * moments of (2l+1) x_a y_a (orthonormal-basis coefficients). The current
  * state u is the initial guess and receives the solution (read it back with
  * rte_fluence / rte_get_state). Two operators:

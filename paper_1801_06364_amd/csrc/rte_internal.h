@@ -99,6 +99,25 @@ bool grid_supported(int n);
 constexpr int kMaxBasisVectors = 32;
 constexpr int kDotPartials = 1024 * kMaxBasisVectors;
 
+// Device-side state of one GMRES restart cycle (in the Krylov workspace):
+// the Arnoldi coefficients of the newest vector, the rotated Hessenberg
+// matrix and the Givens rotations, so that an Arnoldi step needs no host
+// round trip; the host reads the block once per cycle.
+struct GmDev {
+  double hv[kMaxBasisVectors + 1];   // <v_i, w> of the first Gram-Schmidt pass
+  double h2[kMaxBasisVectors + 1];   // of the second pass
+  double hn2;                        // squared norm of the orthogonalised vector
+  double hn;                         // its norm (the normalisation divisor)
+  double ref;                        // reference norm of the relative residual
+  double tol;                        // stop when |g[j+1]| / ref <= tol
+  double R[kMaxBasisVectors * kMaxBasisVectors];  // rotated Hessenberg, R[i * m + j], i <= j
+  double cs[kMaxBasisVectors];
+  double sn[kMaxBasisVectors];
+  double g[kMaxBasisVectors + 1];    // rotated residual vector
+  int m;                             // restart length (row stride of R)
+  int jdone;                         // Arnoldi steps completed in this cycle
+};
+
 // Device control block: step counter and run/stop flags shared by every
 // kernel of a step (kernels return at once when stop != 0).
 struct Ctl {
@@ -190,7 +209,9 @@ enum {
   OP_RHS_MINUS = 9,  // y = x - y (x may be null)
   OP_EXPO = 10,      // u <- exact propagation over time coef (homogeneous medium)
   OP_PSTEP = 11,     // u <- one time step of u (y: stage scratch), no bookkeeping
-  OP_FWD = 12        // spectrum of u (the entry condition of a fused OP_STEP)
+  OP_FWD = 12,       // spectrum of u (the entry condition of a fused OP_STEP)
+  OP_GM_UPDATE = 13  // GMRES: Hessenberg column count (= j + 1) from the GmDev at u;
+                     // sets the control block's stop flag once converged
 };
 struct OpArgs {
   int kind;

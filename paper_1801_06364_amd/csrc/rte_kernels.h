@@ -862,15 +862,18 @@ k_adj_inject(T* __restrict__ lam, const long long* __restrict__ det, const doubl
 // streaming operator is skew and the steady-state operator positive real).
 // k_wdots: per block partial sums of <basis_i, w>_W for i < count (fixed
 // element partition and tree: deterministic); k_cols_sum adds the block
-// partials in a fixed order.
+// partials in a fixed order. Every vector kernel returns at once while the
+// control block's stop flag is set (a GMRES cycle that has converged skips
+// its remaining queued Arnoldi steps).
 constexpr int kDotBlocks = 1024;
 constexpr int kMaxBasis = 32;
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_wdots(const T* __restrict__ basis, long long stride, int count, const T* __restrict__ w, int M,
-        long long n3, double* __restrict__ partial) {
+        long long n3, double* __restrict__ partial, const Ctl* __restrict__ ctl) {
   __shared__ double red[kBlock];
+  if (ctl->stop) return;
   double acc[kMaxBasis];
 #pragma unroll
   for (int i = 0; i < kMaxBasis; ++i) acc[i] = 0.0;
@@ -902,9 +905,10 @@ k_wdots(const T* __restrict__ basis, long long stride, int count, const T* __res
 
 template <typename T>   // instantiated per working precision (one copy per translation unit)
 __global__ void __launch_bounds__(kBlock)
-k_cols_sum(const double* __restrict__ partial, int nblocks, int count, double* __restrict__ out) {
+k_cols_sum(const double* __restrict__ partial, int nblocks, int count, double* __restrict__ out,
+           const Ctl* __restrict__ ctl) {
   const int i = threadIdx.x;
-  if (i >= count) return;
+  if (ctl->stop || i >= count) return;
   double s = 0.0;
   for (int b = 0; b < nblocks; ++b) s += partial[(long long)b * kMaxBasis + i];
   out[i] = s;
@@ -914,7 +918,8 @@ k_cols_sum(const double* __restrict__ partial, int nblocks, int count, double* _
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_combine(T* __restrict__ w, double sgn, const T* __restrict__ basis, long long stride, int count,
-          const double* __restrict__ coef, double cscale, long long len) {
+          const double* __restrict__ coef, double cscale, long long len, const Ctl* __restrict__ ctl) {
+  if (ctl->stop) return;
   for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < len; e += (long long)gridDim.x * kBlock) {
     double x = sgn * double(w[e]);
     for (int i = 0; i < count; ++i) x += cscale * coef[i] * double(basis[i * stride + e]);
@@ -925,7 +930,9 @@ k_combine(T* __restrict__ w, double sgn, const T* __restrict__ basis, long long 
 // dst = src / s[0]
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_scale_by(T* __restrict__ dst, const T* __restrict__ src, const double* __restrict__ s, long long len) {
+k_scale_by(T* __restrict__ dst, const T* __restrict__ src, const double* __restrict__ s, long long len,
+           const Ctl* __restrict__ ctl) {
+  if (ctl->stop) return;
   const double inv = 1.0 / s[0];
   for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < len; e += (long long)gridDim.x * kBlock)
     dst[e] = T(double(src[e]) * inv);
@@ -934,9 +941,44 @@ k_scale_by(T* __restrict__ dst, const T* __restrict__ src, const double* __restr
 // dst = b - dst (b may be null: zero right-hand side)
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_rhs_minus(T* __restrict__ dst, const T* __restrict__ b, long long len) {
+k_rhs_minus(T* __restrict__ dst, const T* __restrict__ b, long long len, const Ctl* __restrict__ ctl) {
+  if (ctl->stop) return;
   for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < len; e += (long long)gridDim.x * kBlock)
     dst[e] = (b ? b[e] : T(0)) - dst[e];
+}
+
+// One Arnoldi step's small-matrix work on the device (a single thread):
+// Hessenberg column j = first + second Gram-Schmidt coefficients and the
+// new vector's norm, the previous Givens rotations applied to it, a new
+// rotation that zeroes its subdiagonal, the rotated residual vector g
+// updated; sets the stop flag once |g[j+1]| / ref <= tol (this includes a
+// breakdown, norm 0, where the Krylov space holds the solution).
+template <typename T>   // instantiated per working precision (one copy per translation unit)
+__global__ void __launch_bounds__(64)
+k_gm_update(GmDev* __restrict__ gm, int j, Ctl* __restrict__ ctl) {
+  if (threadIdx.x != 0 || ctl->stop) return;
+  const int m = gm->m;
+  double hv[kMaxBasisVectors + 1];
+  for (int i = 0; i <= j; ++i) hv[i] = gm->hv[i] + gm->h2[i];
+  const double hn = sqrt(gm->hn2);
+  hv[j + 1] = hn;
+  gm->hn = hn;
+  for (int i = 0; i < j; ++i) {
+    const double t = gm->cs[i] * hv[i] + gm->sn[i] * hv[i + 1];
+    hv[i + 1] = -gm->sn[i] * hv[i] + gm->cs[i] * hv[i + 1];
+    hv[i] = t;
+  }
+  const double r = hypot(hv[j], hv[j + 1]);
+  const double c = r > 0 ? hv[j] / r : 1.0, sn = r > 0 ? hv[j + 1] / r : 0.0;
+  gm->cs[j] = c;
+  gm->sn[j] = sn;
+  hv[j] = r;
+  const double gj = gm->g[j];
+  gm->g[j + 1] = -sn * gj;
+  gm->g[j] = c * gj;
+  for (int i = 0; i <= j; ++i) gm->R[i * m + j] = hv[i];
+  gm->jdone = j + 1;
+  if (fabs(gm->g[j + 1]) / gm->ref <= gm->tol) ctl->stop = 1;
 }
 
 // ------------------------------------ E: exact propagation per mode ---
@@ -1674,6 +1716,7 @@ constexpr double kRkAlpha[4] = {0.25, 1.0 / 3.0, 0.5, 1.0};
 template <typename T, int NN, int N>
 hipError_t enqueue_t(const StepArgs& a, const OpArgs& op, ProfRec* pr) {
   hipStream_t st = reinterpret_cast<hipStream_t>(a.stream);
+  const Ctl* cctl = static_cast<const Ctl*>(a.ctl);
   const double hc = a.dt * a.c;
   const long long nvox = (long long)NN * NN * NN;
   constexpr int M = (N + 1) * (N + 1);
@@ -1756,26 +1799,32 @@ hipError_t enqueue_t(const StepArgs& a, const OpArgs& op, ProfRec* pr) {
     case OP_WDOTS: {
       const long long len = (long long)M * nvox;
       hipLaunchKernelGGL((k_wdots<T>), dim3(kDotBlocks), dim3(kBlock), 0, st, static_cast<const T*>(op.x),
-                         len, op.count, static_cast<const T*>(op.y), M, nvox, op.gmua);
-      hipLaunchKernelGGL((k_cols_sum<T>), dim3(1), dim3(kBlock), 0, st, op.gmua, kDotBlocks, op.count, op.gmus);
+                         len, op.count, static_cast<const T*>(op.y), M, nvox, op.gmua, cctl);
+      hipLaunchKernelGGL((k_cols_sum<T>), dim3(1), dim3(kBlock), 0, st, op.gmua, kDotBlocks, op.count, op.gmus,
+                         cctl);
       break;
     }
     case OP_COMBINE: {
       const long long len = (long long)M * nvox;
       hipLaunchKernelGGL((k_combine<T>), dim3(kDotBlocks), dim3(kBlock), 0, st, static_cast<T*>(op.y),
-                         op.coef, static_cast<const T*>(op.x), len, op.count, op.djdr, op.scale, len);
+                         op.coef, static_cast<const T*>(op.x), len, op.count, op.djdr, op.scale, len, cctl);
       break;
     }
     case OP_SCALE: {
       const long long len = (long long)M * nvox;
       hipLaunchKernelGGL((k_scale_by<T>), dim3(kDotBlocks), dim3(kBlock), 0, st, static_cast<T*>(op.y),
-                         static_cast<const T*>(op.x), op.djdr, len);
+                         static_cast<const T*>(op.x), op.djdr, len, cctl);
       break;
     }
     case OP_RHS_MINUS: {
       const long long len = (long long)M * nvox;
       hipLaunchKernelGGL((k_rhs_minus<T>), dim3(kDotBlocks), dim3(kBlock), 0, st, static_cast<T*>(op.y),
-                         static_cast<const T*>(op.x), len);
+                         static_cast<const T*>(op.x), len, cctl);
+      break;
+    }
+    case OP_GM_UPDATE: {
+      hipLaunchKernelGGL((k_gm_update<T>), dim3(1), dim3(64), 0, st, static_cast<GmDev*>(op.u), op.count,
+                         static_cast<Ctl*>(a.ctl));
       break;
     }
     case OP_FWD: {
@@ -1786,7 +1835,6 @@ hipError_t enqueue_t(const StepArgs& a, const OpArgs& op, ProfRec* pr) {
         const T* src = static_cast<const T*>(a.u);
         V* spec = static_cast<V*>(a.spec);
         const V* tw = static_cast<const V*>(a.tw);
-        const Ctl* cctl = static_cast<const Ctl*>(a.ctl);
         launch_fwd_plane<T, NN>(st, src, spec, tw, cctl, planes);
       }
       break;

@@ -16,6 +16,7 @@
 #include "../../include/rte.h"
 #include "rte_internal.h"
 
+
 namespace rte {
 
 // ------------------------------------------------------------ runtime ---
@@ -1018,19 +1019,34 @@ size_t rte_krylov_workspace_bytes(const rte_config* cfg, int32_t restart) {
   size_t o = rte::up(size_t(restart + 3) * F);            // basis, right-hand side, stage scratch
   o = rte::up(o + size_t(rte::kDotPartials) * 8);         // dot partial sums
   o = rte::up(o + 2 * size_t(rte::kMaxBasisVectors) * 8); // device coefficients
+  o = rte::up(o + sizeof(rte::GmDev));                     // device cycle state
   return o;
 }
 
-int rte_steady_gmres(rte_handle* h, int32_t restart, int64_t max_iters, double tol, int32_t steps_per_apply,
-                     void* kws, size_t kbytes, int64_t* iters, double* rel_residual) {
-  using namespace rte;
+}  // extern "C"
+
+namespace rte {
+namespace {
+
+// Restarted GMRES on the handle's state with the Krylov workspace kws (the
+// caller's, or the library's static scratch array). Every Arnoldi step runs
+// on the device without a host round trip: the Gram-Schmidt coefficients,
+// the norm, the Givens update of the Hessenberg column and the convergence
+// test (GmDev, k_gm_update) stay in device memory, and once a cycle has
+// converged its remaining queued steps return at once (stop flag). The host
+// synchronises twice per restart cycle: for the residual norm that decides
+// whether to start a cycle, and to read the cycle's rotated Hessenberg
+// system, which it solves (at most 31 unknowns) before the solution update.
+// No heap allocation: the host arrays have the fixed maximum size.
+int gmres_run(rte_handle* h, int32_t restart, int64_t max_iters, double tol, int32_t steps_per_apply, void* kws,
+              size_t kbytes, int64_t* iters, double* rel_residual) {
   if (!h || restart < 1 || restart + 1 > kMaxBasisVectors || max_iters < 1 || !(tol > 0) || steps_per_apply < 0 ||
       h->batch_owned)
     return RTE_EINVAL;
   if (h->qw) return RTE_EINVAL;   // a steady state needs a constant source
-  h->spec_valid = false;          // the operator applications reuse the spectrum buffers
   const size_t need = rte_krylov_workspace_bytes(&h->cfg, restart);
   if (!kws || (reinterpret_cast<uintptr_t>(kws) % kAlign) != 0 || kbytes < need) return RTE_ENOMEM;
+  h->spec_valid = false;          // the operator applications reuse the spectrum buffers
   {
     // kernels skip their work once a run has stopped: clear the stop flag
     // (and the run bookkeeping, which a steady solve does not produce)
@@ -1049,6 +1065,9 @@ int rte_steady_gmres(rte_handle* h, int32_t restart, int64_t max_iters, double t
   double* partial = reinterpret_cast<double*>(w + up(size_t(m + 3) * F));
   double* dcoef = reinterpret_cast<double*>(w + up(up(size_t(m + 3) * F) + size_t(kDotPartials) * 8));
   double* dout = dcoef + kMaxBasisVectors;
+  GmDev* gm = reinterpret_cast<GmDev*>(w + up(up(up(size_t(m + 3) * F) + size_t(kDotPartials) * 8) +
+                                              2 * size_t(kMaxBasisVectors) * 8));
+  int* dstop = &static_cast<Ctl*>(h->args.ctl)->stop;
   hipStream_t st = h->stream;
   hipError_t e = hipSuccess;
   StepArgs nosrc = h->args;
@@ -1087,42 +1106,44 @@ int rte_steady_gmres(rte_handle* h, int32_t restart, int64_t max_iters, double t
       rhs_minus(x, y);
     }
   };
-  // out[0..count) = <basis_0..count-1, y>_W, copied to host vals
-  auto wdots = [&](const void* base, int count, const void* y, double* vals) {
+  // out[0..count) (device) = <basis_0..count-1, y>_W
+  auto wdots = [&](const void* base, int count, const void* y, double* out) {
     OpArgs o{};
     o.kind = OP_WDOTS;
     o.x = base;
     o.y = const_cast<void*>(y);
     o.count = count;
     o.gmua = partial;
-    o.gmus = dout;
+    o.gmus = out;
     op(h->args, o);
-    if (e == hipSuccess) e = hipMemcpyAsync(vals, dout, size_t(count) * 8, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
   };
-  // y = sgn * y + scale * sum_i c[i] basis_i, with c uploaded first
+  // <x, x>_W on the host (synchronises)
+  auto norm2 = [&](const void* x) {
+    double v = 0.0;
+    wdots(x, 1, x, dout);
+    if (e == hipSuccess) e = hipMemcpyAsync(&v, dout, 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    return v;
+  };
+  // y = sgn * y + scale * sum_i c[i] basis_i, coefficients c on the device
   auto combine = [&](void* y, double sgn, int count, const double* c, double scale) {
-    if (e == hipSuccess) e = hipMemcpyAsync(dcoef, c, size_t(count) * 8, hipMemcpyHostToDevice, st);
     OpArgs o{};
     o.kind = OP_COMBINE;
     o.x = basis;
     o.y = y;
     o.coef = sgn;
     o.count = count;
-    o.djdr = dcoef;
+    o.djdr = c;
     o.scale = scale;
     op(h->args, o);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);   // dcoef is reused
   };
-  auto scale_into = [&](void* y, const void* x, double s) {
-    if (e == hipSuccess) e = hipMemcpyAsync(dcoef, &s, 8, hipMemcpyHostToDevice, st);
+  auto scale_by = [&](void* y, const double* s) {   // y /= s[0] (device)
     OpArgs o{};
     o.kind = OP_SCALE;
-    o.x = x;
+    o.x = y;
     o.y = y;
-    o.djdr = dcoef;
+    o.djdr = s;
     op(h->args, o);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
   };
   const void* qv = h->has_q ? static_cast<const void*>(h->ws + h->lay.q) : nullptr;
   // right-hand side: q, or the K source-driven steps from zero
@@ -1136,66 +1157,59 @@ int rte_steady_gmres(rte_handle* h, int32_t restart, int64_t max_iters, double t
     apply(h->ws + h->lay.u, r);
     rhs_minus(b, r);
   };
-  double bnorm = 0.0;
-  if (b) {
-    wdots(b, 1, b, &bnorm);
-    bnorm = std::sqrt(bnorm);
-  }
+  const double bnorm = b ? std::sqrt(norm2(b)) : 0.0;
+  const double ref = bnorm > 0 ? bnorm : 1.0;
   int64_t it = 0;
   double rel = 1.0;
-  std::vector<double> H(size_t(m + 1) * m), cs(m), sn(m), g(m + 1), hv(m + 1), h2(m + 1), y(m);
+  GmDev gh;                        // host copy of the cycle state
+  double y[kMaxBasisVectors];
   while (e == hipSuccess) {
     residual_into(vec(0));
-    double beta = 0.0;
-    wdots(vec(0), 1, vec(0), &beta);
-    beta = std::sqrt(beta);
-    const double ref = bnorm > 0 ? bnorm : 1.0;
+    const double beta = std::sqrt(norm2(vec(0)));
     rel = beta / ref;
     if (e != hipSuccess || rel <= tol || it >= max_iters || beta == 0.0) break;
-    scale_into(vec(0), vec(0), beta);
-    std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta;
-    int j = 0;
-    for (; j < m && it < max_iters && e == hipSuccess; ++j, ++it) {
+    // cycle state: g = beta e_0; v_0 = r / beta
+    std::memset(&gh, 0, sizeof gh);
+    gh.g[0] = beta;
+    gh.ref = ref;
+    gh.tol = tol;
+    gh.m = m;
+    if (e == hipSuccess) e = hipMemcpyAsync(gm, &gh, sizeof gh, hipMemcpyHostToDevice, st);
+    scale_by(vec(0), &gm->g[0]);
+    const int jmax = int(std::min<int64_t>(m, max_iters - it));
+    for (int j = 0; j < jmax; ++j) {
       apply(vec(j), vec(j + 1));
       // classical Gram-Schmidt, applied twice, against v_0..v_j
-      wdots(basis, j + 1, vec(j + 1), hv.data());
-      combine(vec(j + 1), 1.0, j + 1, hv.data(), -1.0);
-      wdots(basis, j + 1, vec(j + 1), h2.data());
-      combine(vec(j + 1), 1.0, j + 1, h2.data(), -1.0);
-      for (int i = 0; i <= j; ++i) hv[i] += h2[i];
-      double hn = 0.0;
-      wdots(vec(j + 1), 1, vec(j + 1), &hn);
-      hn = std::sqrt(hn);
-      hv[j + 1] = hn;
-      if (hn > 0) scale_into(vec(j + 1), vec(j + 1), hn);
-      // Givens rotations on the new Hessenberg column
-      for (int i = 0; i < j; ++i) {
-        const double t = cs[i] * hv[i] + sn[i] * hv[i + 1];
-        hv[i + 1] = -sn[i] * hv[i] + cs[i] * hv[i + 1];
-        hv[i] = t;
-      }
-      const double r = std::hypot(hv[j], hv[j + 1]);
-      cs[j] = r > 0 ? hv[j] / r : 1.0;
-      sn[j] = r > 0 ? hv[j + 1] / r : 0.0;
-      hv[j] = r;
-      hv[j + 1] = 0.0;
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = cs[j] * g[j];
-      for (int i = 0; i <= j; ++i) H[size_t(i) * m + j] = hv[i];
-      if (std::fabs(g[j + 1]) / ref <= tol) {
-        ++j;
-        ++it;
-        break;
-      }
+      wdots(basis, j + 1, vec(j + 1), gm->hv);
+      combine(vec(j + 1), 1.0, j + 1, gm->hv, -1.0);
+      wdots(basis, j + 1, vec(j + 1), gm->h2);
+      combine(vec(j + 1), 1.0, j + 1, gm->h2, -1.0);
+      wdots(vec(j + 1), 1, vec(j + 1), &gm->hn2);
+      OpArgs o{};
+      o.kind = OP_GM_UPDATE;
+      o.u = gm;
+      o.count = j;
+      op(h->args, o);
+      scale_by(vec(j + 1), &gm->hn);
     }
-    // solve the j x j triangular system and update u += sum y_i v_i
+    if (e == hipSuccess) e = hipMemcpyAsync(&gh, gm, sizeof gh, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) break;
+    const int j = gh.jdone;
+    it += j;
+    // a converged cycle left the stop flag set: clear it for the update
+    // and the next cycle
+    e = hipMemsetAsync(dstop, 0, sizeof(int), st);
+    // solve the j x j triangular system R y = g and update u += sum y_i v_i
     for (int i = j - 1; i >= 0; --i) {
-      double t = g[i];
-      for (int k = i + 1; k < j; ++k) t -= H[size_t(i) * m + k] * y[k];
-      y[i] = t / H[size_t(i) * m + i];
+      double t = gh.g[i];
+      for (int k = i + 1; k < j; ++k) t -= gh.R[i * m + k] * y[k];
+      y[i] = t / gh.R[i * m + i];
     }
-    if (j > 0) combine(h->ws + h->lay.u, 1.0, j, y.data(), 1.0);
+    if (j > 0) {
+      if (e == hipSuccess) e = hipMemcpyAsync(dcoef, y, size_t(j) * 8, hipMemcpyHostToDevice, st);
+      combine(h->ws + h->lay.u, 1.0, j, dcoef, 1.0);
+    }
   }
   if (K > 0 && e == hipSuccess) {
     // report the residual of the steady-state equation A u = q itself
@@ -1205,15 +1219,24 @@ int rte_steady_gmres(rte_handle* h, int32_t restart, int64_t max_iters, double t
     o.y = vec(0);
     op(h->args, o);
     rhs_minus(qv, vec(0));
-    double rn = 0.0, qn = 0.0;
-    wdots(vec(0), 1, vec(0), &rn);
-    if (qv) wdots(qv, 1, qv, &qn);
+    const double rn = norm2(vec(0));
+    const double qn = qv ? norm2(qv) : 0.0;
     rel = std::sqrt(rn) / (qn > 0 ? std::sqrt(qn) : 1.0);
   }
   if (iters) *iters = it;
   if (rel_residual) *rel_residual = rel;
   if (e != hipSuccess) return RTE_EDEVICE;
   return std::isfinite(rel) ? RTE_OK : RTE_EUNSTABLE;
+}
+
+}  // namespace
+}  // namespace rte
+
+extern "C" {
+
+int rte_steady_gmres(rte_handle* h, int32_t restart, int64_t max_iters, double tol, int32_t steps_per_apply,
+                     void* kws, size_t kbytes, int64_t* iters, double* rel_residual) {
+  return rte::gmres_run(h, restart, max_iters, tol, steps_per_apply, kws, kbytes, iters, rel_residual);
 }
 
 namespace {

@@ -34,6 +34,12 @@ namespace rte {
 namespace p128 {
 
 constexpr int n = 128, H = 64, PITCH = 65;
+#ifndef RTE_P128_NT
+#define RTE_P128_NT 1
+#endif
+#ifndef RTE_P128_XCD
+#define RTE_P128_XCD 1
+#endif
 #ifndef RTE_P128_BATCH
 #define RTE_P128_BATCH 2
 #endif
@@ -48,6 +54,26 @@ template <typename E, typename P> __device__ __forceinline__ E& at_b(P* base, un
 }
 template <typename E, typename P> __device__ __forceinline__ E ld_b(P* base, unsigned byte_off) {
   return *reinterpret_cast<const E*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+// Store of a stream that no kernel of the pass reads again (RTE_P128_NT:
+// nontemporal).
+__device__ __forceinline__ void st_stream(float4* p, float4 v) {
+#if RTE_P128_NT
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  const v4 x = {v.x, v.y, v.z, v.w};
+  __builtin_nontemporal_store(x, reinterpret_cast<v4*>(p));
+#else
+  *p = v;
+#endif
+}
+__device__ __forceinline__ void st_stream(float2* p, float2 v) {
+#if RTE_P128_NT
+  typedef float v2 __attribute__((ext_vector_type(2)));
+  const v2 x = {v.x, v.y};
+  __builtin_nontemporal_store(x, reinterpret_cast<v2*>(p));
+#else
+  *p = v;
+#endif
 }
 
 // w or conj(w): the tables hold exp(-2 pi i t / n); the inverse (DIR = +1)
@@ -247,7 +273,7 @@ __device__ __forceinline__ void forward_plane(float2* c0, float2* c1, float2* pl
     for (int r = 1; r < 8; ++r) v[r] = cmul(v[r], twg[r * jp]);
     Bfly<float2, 8, -1>::run(v);
 #pragma unroll
-    for (int k = 0; k < 8; ++k) at_b<float2>(fd, lo + unsigned((jp + 16 * k) * H * 8)) = v[k];
+    for (int k = 0; k < 8; ++k) st_stream(&at_b<float2>(fd, lo + unsigned((jp + 16 * k) * H * 8)), v[k]);
   }
 }
 
@@ -303,7 +329,11 @@ k_plane128(const float2* spec, const float* vin, float* u, float* dst, const flo
   extern __shared__ __align__(16) unsigned char smem[];
   float2* tw = reinterpret_cast<float2*>(smem);
   float2* pl = tw + n;
+#if RTE_P128_XCD
   const int lt = xcd_tile(blockIdx.x, gridDim.x);
+#else
+  const int lt = blockIdx.x;
+#endif
   const int z = lt / M, b = lt - z * M;
   const int plane = b * n + z;
   const int tid = threadIdx.x, ln = tid & 63;
@@ -420,7 +450,7 @@ k_plane128(const float2* spec, const float* vin, float* u, float* dst, const flo
         const unsigned e = off + 64u * unsigned(k);
         const float4 w4 = make_float4(c0[k].x, c0[k].y, c1[k].x, c1[k].y);
         const float4 o = epi4<MODE>(w4, uu[i], vv[i], ss[i], qq[i], qs, h);
-        at_b<float4>(db, e) = o;
+        st_stream(&at_b<float4>(db, e), o);
         if constexpr (MODE == EPI_ADJ)
           at_b<float4>(ubw, e) = make_float4(uu[i].x + o.x, uu[i].y + o.y, uu[i].z + o.z, uu[i].w + o.w);
         if constexpr (kLast) {
