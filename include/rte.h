@@ -265,6 +265,25 @@ size_t rte_krylov_workspace_bytes(const rte_config* cfg, int32_t restart);
 int rte_steady_gmres(rte_handle* h, int32_t restart, int64_t max_iters, double tol, int32_t steps_per_apply,
                      void* kws, size_t kbytes, int64_t* iters, double* rel_residual);
 
+/* ---- Steady state without device allocation ---------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the solve
+ * of rte_steady_gmres with its Krylov workspace in a static device array of
+ * the library instead of a caller buffer. rte_static_scratch_bytes() gives
+ * the array's size (128 MiB); every GPU the library runs on holds one until
+ * the process ends (its address is looked up once per device, at the first
+ * rte_create on that device). Allocates nothing (no hipMalloc / hipFree, no
+ * host heap). Arguments and results as rte_steady_gmres without kws /
+ * kbytes; RTE_ENOMEM when rte_krylov_workspace_bytes(cfg, restart) exceeds
+ * the array, RTE_EDEVICE if its device address could not be looked up. All
+ * calls on one GPU share the array, which keeps the last call's contents
+ * (a solve initialises everything it reads): calls that overlap on one GPU
+ * (from several threads or streams) race, and the caller must serialise
+ * them. */
+size_t rte_static_scratch_bytes(void);
+int rte_steady_gmres_static(rte_handle* h, int32_t restart, int64_t max_iters, double tol,
+                            int32_t steps_per_apply, int64_t* iters, double* rel_residual);
+
 /* ---- Exact propagation in homogeneous media --------------------------
  * The paper integrates the time-domain form analytically to obtain an
  * implicit operator (Sec. II.A) and reports exponential integrators that

@@ -16,6 +16,47 @@
 #include "../../include/rte.h"
 #include "rte_internal.h"
 
+namespace rte {
+namespace {
+// The library's static device scratch array: the Krylov workspace of the
+// no-allocation GMRES entry point. Each GPU holds its own copy for the life
+// of the process; its device address is looked up once per device (with
+// that device current) and kept, since host code may not use the symbol
+// itself as a device address.
+constexpr size_t kScratchBytes = size_t(128) << 20;
+constexpr int kMaxDevices = 64;
+std::once_flag g_scratch_once[kMaxDevices];
+void* g_scratch_ptr[kMaxDevices];
+hipError_t g_scratch_err[kMaxDevices];
+}  // namespace
+}  // namespace rte
+
+static __device__ __align__(256) unsigned char scratch[rte::kScratchBytes];
+
+namespace rte {
+namespace {
+// Device address of `scratch` on device dev (null on failure, *err set).
+void* scratch_on(int dev, hipError_t* err) {
+  if (dev < 0 || dev >= kMaxDevices) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::call_once(g_scratch_once[dev], [dev] {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e == hipSuccess && cur != dev) e = hipSetDevice(dev);
+    void* p = nullptr;
+    if (e == hipSuccess) e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur >= 0 && cur != dev) (void)hipSetDevice(cur);
+    g_scratch_err[dev] = e;
+    g_scratch_ptr[dev] = e == hipSuccess ? p : nullptr;
+  });
+  *err = g_scratch_err[dev];
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+}  // namespace rte
+
 
 namespace rte {
 
@@ -146,6 +187,7 @@ struct rte_handle {
   bool expo_taylor;                 // exact propagation by the per-point series only
   std::vector<double> rot_data;     // X blocks and B_z couplings of the rotation path
   bool batch_owned;                 // a slot of a batch: stepped by the batch, read-only here
+  int device;                       // HIP device current at creation (the stream's device)
   double source_term;               // weighted source energy / (smallest loss)^2 (growth limit)
   uint64_t medium_hash;             // FNV-1a of the maps and source (snapshot compatibility)
   double sigl[rte::kMaxOrder + 1];  // per-degree loss (homogeneous media)
@@ -457,6 +499,13 @@ int create_impl(const rte_config* cfg, const rte_medium* med, void* dev_ws, size
   h->ws = reinterpret_cast<unsigned char*>(dev_ws);
   h->lay = L;
   h->batch_owned = batch_slot;
+  h->device = 0;
+  if (hipGetDevice(&h->device) != hipSuccess) h->device = 0;
+  {
+    // set-up of the static scratch array on this device (once per device)
+    hipError_t se = hipSuccess;
+    (void)scratch_on(h->device, &se);
+  }
   h->graph_ready = false;
   h->spec_valid = false;
   h->qw = nullptr;
@@ -1234,9 +1283,23 @@ int gmres_run(rte_handle* h, int32_t restart, int64_t max_iters, double tol, int
 
 extern "C" {
 
+size_t rte_static_scratch_bytes(void) { return rte::kScratchBytes; }
+
 int rte_steady_gmres(rte_handle* h, int32_t restart, int64_t max_iters, double tol, int32_t steps_per_apply,
                      void* kws, size_t kbytes, int64_t* iters, double* rel_residual) {
   return rte::gmres_run(h, restart, max_iters, tol, steps_per_apply, kws, kbytes, iters, rel_residual);
+}
+
+int rte_steady_gmres_static(rte_handle* h, int32_t restart, int64_t max_iters, double tol,
+                            int32_t steps_per_apply, int64_t* iters, double* rel_residual) {
+  if (!h) return RTE_EINVAL;
+  const size_t need = rte_krylov_workspace_bytes(&h->cfg, restart);
+  if (need == 0) return RTE_EINVAL;
+  if (need > rte::kScratchBytes) return RTE_ENOMEM;   // beyond the static array
+  hipError_t err = hipSuccess;
+  void* ws = rte::scratch_on(h->device, &err);
+  if (!ws) return RTE_EDEVICE;
+  return rte::gmres_run(h, restart, max_iters, tol, steps_per_apply, ws, rte::kScratchBytes, iters, rel_residual);
 }
 
 namespace {

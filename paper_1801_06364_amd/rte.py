@@ -30,6 +30,7 @@ EXPORTS = (
     "rte_profile_expo", "rte_set_source_profile", "rte_snapshot_bytes", "rte_snapshot",
     "rte_restore", "rte_batch_slot_bytes", "rte_batch_create", "rte_batch_admit", "rte_batch_step",
     "rte_batch_poll", "rte_batch_handle", "rte_batch_release", "rte_batch_destroy",
+    "rte_static_scratch_bytes", "rte_steady_gmres_static",
 )
 RTE_SLOT_FREE, RTE_SLOT_STAGING, RTE_SLOT_STAGED, RTE_SLOT_RUNNING, RTE_SLOT_DONE, RTE_SLOT_FAILED = range(6)
 KERNEL_CLASSES = ("fwd_plane", "zderiv", "couple", "inv_plane", "end_step",
@@ -110,6 +111,10 @@ def lib():
         L.rte_steady_gmres.argtypes = [vp, C.c_int32, C.c_int64, C.c_double, C.c_int32, vp, C.c_size_t,
                                        i64p, dp]
         L.rte_steady_gmres.restype = C.c_int
+        L.rte_static_scratch_bytes.argtypes = []
+        L.rte_static_scratch_bytes.restype = C.c_size_t
+        L.rte_steady_gmres_static.argtypes = [vp, C.c_int32, C.c_int64, C.c_double, C.c_int32, i64p, dp]
+        L.rte_steady_gmres_static.restype = C.c_int
         L.rte_expo_advance.argtypes = [vp, C.c_double]
         L.rte_expo_advance.restype = C.c_int
         L.rte_set_source_profile.argtypes = [vp, dp, C.c_int64, C.c_double, C.c_int64, vp, C.c_size_t]
@@ -340,6 +345,18 @@ class Solver:
         self.stream.synchronize()
         del kws
         _check(rc, "rte_steady_gmres")
+        return int(it.value), float(res.value)
+
+    def steady_gmres_static(self, tol: float = 1e-6, restart: int = 16, max_iters: int = 2000,
+                            steps_per_apply: int = 0):
+        """steady_gmres with the Krylov workspace in the library's static
+        device array (rte_steady_gmres_static: no device allocation); the
+        Krylov workspace of (n, N, restart) must fit rte_static_scratch_bytes()."""
+        it = C.c_int64(0)
+        res = C.c_double(0.0)
+        rc = lib().rte_steady_gmres_static(self.h, int(restart), int(max_iters), float(tol),
+                                           int(steps_per_apply), C.byref(it), C.byref(res))
+        _check(rc, "rte_steady_gmres_static")
         return int(it.value), float(res.value)
 
     # -- discrete adjoint ---------------------------------------------------
