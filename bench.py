@@ -61,7 +61,8 @@ def algorithmic_bytes(kind: str, n: int, M: int, N: int, s: int) -> float:
     spectrum; averaged over the four RK stages (the first stage reads u
     once, the last one also updates the FP64 integrated fluence, 16 bytes
     per voxel).
-    inv_rows (larger grids, not fused): the same without the spectrum write.
+    inv_rows (larger grids: x transforms only, fused with the next
+    stage's forward row transform): the same bytes as inv_plane.
     """
     F = M * n ** 3 * s
     if kind == "fwd_plane":
@@ -73,7 +74,7 @@ def algorithmic_bytes(kind: str, n: int, M: int, N: int, s: int) -> float:
     if kind == "inv_plane":
         return 4.75 * F + (N + 1) * n ** 3 * s + 16 * n ** 3 / 4
     if kind == "inv_rows":
-        return 3.75 * F + (N + 1) * n ** 3 * s + 16 * n ** 3 / 4
+        return 4.75 * F + (N + 1) * n ** 3 * s + 16 * n ** 3 / 4
     if kind in ("fwd_rows", "y_fwd", "y_inv"):
         return 2 * F
     return 0.0
@@ -587,6 +588,34 @@ def adjoint_bench(a):
     print(json.dumps(out), flush=True)
 
 
+def accuracy_timed(name, steps):
+    """FP32 against the FP64 GPU path on the timed configuration itself
+    (full size, `steps` RK4 steps from the recipe's initial state):
+    relative L2 of the final fluence, the integrated fluence and the
+    flattened detector series. The FP64 GPU path stands in for the oracle at
+    this size (the oracle takes about 12 s per step here); it matches the
+    oracle to <= 1e-12 on every parity case, the full 128^3 / P_7 grid
+    included."""
+    import numpy as np
+
+    import rte_inputs as ri
+    from paper_1801_06364_amd.rte import Solver
+
+    def rel(x, y):
+        return float(np.linalg.norm(np.ravel(x) - np.ravel(y)) / np.linalg.norm(np.ravel(y)))
+
+    res = {}
+    for prec in ("f64", "f32"):
+        s = Solver.from_workload(ri.workload(name, steps=steps, precision=prec))
+        s.step(steps)
+        res[prec] = (s.fluence(), s.fluence(1), s.readings())
+        s.close()
+    f64, f32 = res["f64"], res["f32"]
+    return {"workload": f"{name} (the timed configuration), {steps} RK4 steps, FP32 vs FP64 GPU",
+            "fluence": rel(f32[0], f64[0]), "integrated_fluence": rel(f32[1], f64[1]),
+            "readings_series": rel(f32[2], f64[2])}
+
+
 def accuracy_report():
     """FP32 and FP64 GPU results against the FP64 oracle on the bench recipe
     at a reduced size (p7_spheres, 32^3, 12 steps): relative L2 per result
@@ -636,6 +665,8 @@ def main():
     ap.add_argument("--slots", type=int, default=16, help="largest batch per configuration class")
     ap.add_argument("--chunk", type=int, default=16, help="time steps per queued batch chunk")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--accuracy-steps", type=int, default=200,
+                    help="RK4 steps of the FP32-vs-FP64 comparison on the timed configuration")
     ap.add_argument("--expo", action="store_true",
                     help="exact propagation vs RK4 marching in a homogeneous medium (separate JSON line)")
     ap.add_argument("--expo-reps", type=int, default=5)
@@ -747,6 +778,7 @@ def main():
     }
     if not a.no_accuracy:
         out["accuracy"] = accuracy_report()
+        out["accuracy"]["timed_config"] = accuracy_timed(a.workload, a.accuracy_steps)
     if not a.no_cpu_baseline:
         workers = int(os.environ.get("OMP_NUM_THREADS", "0")) or min(16, os.cpu_count() or 1)
         wlc = ri.workload(a.workload, steps=1)

@@ -730,14 +730,18 @@ k_inv_plane(const typename cplx_of<T>::type* spec, const T* vin, T* u, T* dst,
 // Inverse x transform + epilogue of RB rows per workgroup (grids whose
 // plane does not fit in LDS; the y transform ran before as a pencil pass).
 // Logical order (z, row block, moment) so moments sharing loss rows are
-// neighbours on one XCD.
-template <typename T, int NN, int MODE>
+// neighbours on one XCD. FUSE: the output rows, still in LDS, are
+// transformed forward at once (x real-to-complex, as k_rows_fwd) and
+// written as the next stage's row spectrum to fspec (which may be the
+// spectrum just read: each workgroup owns its rows), so the next stage
+// needs no separate row pass.
+template <typename T, int NN, int MODE, bool FUSE = false>
 __global__ void __launch_bounds__(kZBlock)
-k_rows_inv(const typename cplx_of<T>::type* __restrict__ spec, const T* vin, T* u, T* dst,
+k_rows_inv(const typename cplx_of<T>::type* spec, const T* vin, T* u, T* dst,
            const T* __restrict__ sig, const T* __restrict__ q, const int* __restrict__ qflag,
            double* __restrict__ phi_int, double* __restrict__ partial,
            const typename cplx_of<T>::type* __restrict__ twg, int M, T h, double dt,
-           const Ctl* __restrict__ ctl, int stage, long long step1) {
+           const Ctl* __restrict__ ctl, int stage, long long step1, typename cplx_of<T>::type* fspec = nullptr) {
   using V = typename cplx_of<T>::type;
   constexpr int n = NN, H = NN / 2, RB = RowShape<NN>::RB, NB = NN / RB;
   using Lay = PlaneLayout<NN, RB>;
@@ -761,8 +765,19 @@ k_rows_inv(const typename cplx_of<T>::type* __restrict__ spec, const T* vin, T* 
   double acc_d = 0.0, acc_o = 0.0;
   const bool hasq = (q != nullptr) && qflag[z];
   const T qs = hasq ? T(source_weight(ctl, stage, step1)) : T(0);
-  epilogue<V, T, NN, RB, Lay, kZBlock, MODE>(pl, y0, b, z, vin, u, dst, sig, q, hasq, qs, phi_int, h, dt, acc_d,
-                                            acc_o);
+  epilogue<V, T, NN, RB, Lay, kZBlock, MODE, FUSE>(pl, y0, b, z, vin, u, dst, sig, q, hasq, qs, phi_int, h, dt,
+                                                  acc_d, acc_o);
+  if constexpr (FUSE) {
+    __syncthreads();
+    fft_batch<V, H, 2 * H, -1, RB, kZBlock>(tw, Lay::xat(pl));
+    __syncthreads();
+    r2c_split<V, T, NN, RB, Lay, kZBlock>(pl, tw);
+    __syncthreads();
+    V* fd = fspec + ((size_t(b) * n + z) * n + y0) * H;
+    staged_copy<RB * H, kZBlock>([&](int i) { return pl[Lay::pos(i / H, i % H)]; },
+                                 [&](int i, V x) { fd[i] = x; });
+  }
+  // (block_sum2 reuses the LDS: it synchronises first)
   if ((MODE == EPI_LAST || MODE == EPI_EULER) && b == 0) block_sum2<kZBlock>(smem, acc_d, acc_o, partial + 2 * zy);
 }
 
@@ -1431,6 +1446,58 @@ __device__ __forceinline__ void expo_blocks(V* a, const V* q, size_t ms, const V
   }
 }
 
+// Thread -> spectral point. The block products read one table row per
+// |k|^2; the four points (+-fy, +-fz) of a given kx share it. Lanes are
+// grouped so that one wavefront instruction holds those four points for TX
+// consecutive kx (sub-group s of a quad of 4 TX lanes takes y -> y' if s & 1,
+// z -> z' if s & 2, with i' = n - i, and 0' = n/2 for the index pair whose
+// frequency is 0): the four lanes that share a row read it in the same
+// instruction, which fetches it once. A bijection of the points, so the
+// results are those of any other order.
+#ifndef RTE_EXPO_OCT
+#define RTE_EXPO_OCT 0
+#endif
+template <int NN> struct ExpoQuad {
+  static constexpr int H = NN / 2;
+  static constexpr bool OCT = RTE_EXPO_OCT;   // also pair (y, z) with (z, y): eight points per row
+  static constexpr int G = OCT ? 8 : 4;       // points per group
+  static constexpr int TXMAX = 64 / G;
+  static constexpr int TX = (H % TXMAX == 0) ? TXMAX : (H % 8 == 0 ? 8 : (H % 4 == 0 ? 4 : 1));
+  static_assert(64 % (G * TX) == 0, "groups must tile a wavefront");
+  static constexpr int C = NN / 2;                                 // classes per axis
+  static constexpr int NCLS = OCT ? C * (C + 1) / 2 : C * C;       // (y, z) classes
+  static constexpr int THREADS = NCLS * (H / TX) * G * TX;          // threads launched
+  static __device__ __forceinline__ int mirror(int i) { return i == 0 ? NN / 2 : NN - i; }
+  // point index (z n + y) H + x of thread t < THREADS, or -1 (an idle lane
+  // of a diagonal class, whose swapped points are the same points)
+  static __device__ __forceinline__ int point(int t) {
+    const int Q = t / (G * TX), l = t - Q * G * TX;
+    const int sub = l / TX, xl = l - sub * TX;
+    constexpr int XT = H / TX;
+    const int xt = Q % XT, cls = Q / XT;
+    int yc, zc;
+    if constexpr (OCT) {
+      // cls -> (yc <= zc): row zc holds zc + 1 classes
+      int z = int((sqrtf(8.f * cls + 1.f) - 1.f) * 0.5f);
+      while ((z + 1) * (z + 2) / 2 <= cls) ++z;
+      while (z * (z + 1) / 2 > cls) --z;
+      zc = z;
+      yc = cls - z * (z + 1) / 2;
+      if (sub & 4) {
+        if (yc == zc) return -1;
+        const int tmp = yc;
+        yc = zc;
+        zc = tmp;
+      }
+    } else {
+      yc = cls % C;
+      zc = cls / C;
+    }
+    const int y = (sub & 1) ? mirror(yc) : yc, z = (sub & 2) ? mirror(zc) : zc;
+    return (z * NN + y) * H + xt * TX + xl;
+  }
+};
+
 template <typename T, int NN, int N>
 __global__ void __launch_bounds__(kEBlock)
 k_expo_blocks(typename cplx_of<T>::type* __restrict__ spec, const typename cplx_of<T>::type* __restrict__ qs,
@@ -1438,8 +1505,10 @@ k_expo_blocks(typename cplx_of<T>::type* __restrict__ spec, const typename cplx_
   using V = typename cplx_of<T>::type;
   constexpr int n = NN, H = NN / 2;
   constexpr size_t MS = size_t(n) * n * H;
-  const int pt = blockIdx.x * kEBlock + threadIdx.x;
-  if (pt >= n * n * H) return;
+  const int t = blockIdx.x * kEBlock + threadIdx.x;
+  if (t >= ExpoQuad<NN>::THREADS) return;
+  const int pt = ExpoQuad<NN>::point(t);
+  if (pt < 0) return;
   const int xi = pt % H, yi = (pt / H) % n, zi = pt / (n * H);
   auto freq = [](int i) { return i < n / 2 ? i : (i == n / 2 ? 0 : i - n); };
   const int fy = freq(yi), fz = freq(zi);
@@ -1491,6 +1560,10 @@ hipError_t prepare_t(const StepArgs& a) {
     set(reinterpret_cast<const void*>(&k_rows_inv<T, NN, EPI_EULER>), rows_lds<T, NN>());
     set(reinterpret_cast<const void*>(&k_rows_inv<T, NN, EPI_APPLY>), rows_lds<T, NN>());
     set(reinterpret_cast<const void*>(&k_rows_inv<T, NN, EPI_SET>), rows_lds<T, NN>());
+    set(reinterpret_cast<const void*>(&k_rows_inv<T, NN, EPI_FIRST, true>), rows_lds<T, NN>());
+    set(reinterpret_cast<const void*>(&k_rows_inv<T, NN, EPI_MID, true>), rows_lds<T, NN>());
+    set(reinterpret_cast<const void*>(&k_rows_inv<T, NN, EPI_LAST, true>), rows_lds<T, NN>());
+    set(reinterpret_cast<const void*>(&k_rows_inv<T, NN, EPI_EULER, true>), rows_lds<T, NN>());
     set(reinterpret_cast<const void*>(&k_pencil<T, NN, PENCIL_YFWD>), zd_lds<T, NN>());
     set(reinterpret_cast<const void*>(&k_pencil<T, NN, PENCIL_YINV>), zd_lds<T, NN>());
   } else {
@@ -1537,7 +1610,6 @@ template <int NN> constexpr int partial_count() {
 template <typename T, int NN, int N, int MODE, bool FUSE = false>
 void enqueue_stage(const StepArgs& a, ProfRec* pr, double hs, double sgn, const T* src, T* u, T* out,
                    int stage = 0, long long step1 = 0) {
-  static_assert(!FUSE || !split_planes<NN>(), "the fused forward transform needs a plane in LDS");
   using V = typename cplx_of<T>::type;
   using Z = ZdShape<T, NN>;
   constexpr int M = (N + 1) * (N + 1);
@@ -1566,8 +1638,12 @@ void enqueue_stage(const StepArgs& a, ProfRec* pr, double hs, double sgn, const 
     }
   };
   if constexpr (split_planes<NN>()) {
-    hipLaunchKernelGGL((k_rows_fwd<T, NN>), dim3(rblocks), zblk, lr, st, src, spec, tw, cctl);
-    rec(PROF_FWD_ROWS);
+    // (fused stages find the row spectrum of src already written by the
+    // previous inverse row pass)
+    if constexpr (!FUSE) {
+      hipLaunchKernelGGL((k_rows_fwd<T, NN>), dim3(rblocks), zblk, lr, st, src, spec, tw, cctl);
+      rec(PROF_FWD_ROWS);
+    }
     hipLaunchKernelGGL((k_pencil<T, NN, PENCIL_YFWD>), dim3(pencils), zblk, lz, st, spec, spec, tw, kv, cctl);
     rec(PROF_Y_FWD);
   } else if constexpr (!FUSE) {
@@ -1593,8 +1669,9 @@ void enqueue_stage(const StepArgs& a, ProfRec* pr, double hs, double sgn, const 
     hipLaunchKernelGGL((k_pencil<T, NN, PENCIL_YINV>), dim3(pencils), zblk, lz, st, coupled, coupled, tw, kv,
                        cctl);
     rec(PROF_Y_INV);
-    hipLaunchKernelGGL((k_rows_inv<T, NN, MODE>), dim3(rblocks), zblk, lr, st, coupled, src, u, out, sig, q,
-                       a.qflag, a.phi_int, a.partial, tw, M, T(hs), a.dt, cctl, stage, step1);
+    hipLaunchKernelGGL((k_rows_inv<T, NN, MODE, FUSE>), dim3(rblocks), zblk, lr, st, coupled, src, u, out, sig,
+                       q, a.qflag, a.phi_int, a.partial, tw, M, T(hs), a.dt, cctl, stage, step1,
+                       FUSE ? spec : static_cast<V*>(nullptr));
     rec(PROF_INV_ROWS);
   } else if constexpr (plane128<T, NN>()) {
     hipLaunchKernelGGL((p128::k_plane128<MODE, FUSE>), dim3(planes, ns), pblk, p128::kLds, st, coupled, src, u,
@@ -1686,8 +1763,8 @@ hipError_t enqueue_expo(const StepArgs& a, const OpArgs& op, ProfRec* pr) {
                          p.inv_n3);
     hipLaunchKernelGGL((k_expo_frame<T, NN, N, false>), dim3(eblocks), dim3(kEBlock), 0, st, spec, kv, xrot,
                        p.inv_n3);
-    hipLaunchKernelGGL((k_expo_blocks<T, NN, N>), dim3(eblocks), dim3(kEBlock), 0, st, spec, q ? dspec : nullptr,
-                       tab);
+    hipLaunchKernelGGL((k_expo_blocks<T, NN, N>), dim3((ExpoQuad<NN>::THREADS + kEBlock - 1) / kEBlock),
+                       dim3(kEBlock), 0, st, spec, q ? dspec : nullptr, tab);
     hipLaunchKernelGGL((k_expo_frame<T, NN, N, true>), dim3(eblocks), dim3(kEBlock), 0, st, spec, kv, xrot, T(1));
   } else {
     hipLaunchKernelGGL((k_expo<T, NN, N>), dim3(eblocks), dim3(kEBlock), 0, st, spec, q ? dspec : nullptr, kv, p);
@@ -1730,21 +1807,19 @@ hipError_t enqueue_t(const StepArgs& a, const OpArgs& op, ProfRec* pr) {
       }
       const long long s1 = op.step1;
       bool done = false;
-      if constexpr (!split_planes<NN>()) {
-        if (op.fused) {
-          // the spectrum of u is in place on entry; every inverse pass
-          // leaves the spectrum of its output for the next stage (the last
-          // one that of the new u, for the next step)
-          if (a.scheme == 1) {
-            enqueue_stage<T, NN, N, EPI_EULER, true>(a, pr, hc, 1.0, u, u, u, 0, s1);
-          } else {
-            enqueue_stage<T, NN, N, EPI_FIRST, true>(a, pr, kRkAlpha[0] * hc, 1.0, u, u, v, 0, s1);
-            enqueue_stage<T, NN, N, EPI_MID, true>(a, pr, kRkAlpha[1] * hc, 1.0, v, u, v, 1, s1);
-            enqueue_stage<T, NN, N, EPI_MID, true>(a, pr, kRkAlpha[2] * hc, 1.0, v, u, v, 2, s1);
-            enqueue_stage<T, NN, N, EPI_LAST, true>(a, pr, kRkAlpha[3] * hc, 1.0, v, u, u, 3, s1);
-          }
-          done = true;
+      if (op.fused) {
+        // the spectrum of u (xy on plane grids, x on split grids) is in
+        // place on entry; every inverse pass leaves that of its output for
+        // the next stage (the last one that of the new u, for the next step)
+        if (a.scheme == 1) {
+          enqueue_stage<T, NN, N, EPI_EULER, true>(a, pr, hc, 1.0, u, u, u, 0, s1);
+        } else {
+          enqueue_stage<T, NN, N, EPI_FIRST, true>(a, pr, kRkAlpha[0] * hc, 1.0, u, u, v, 0, s1);
+          enqueue_stage<T, NN, N, EPI_MID, true>(a, pr, kRkAlpha[1] * hc, 1.0, v, u, v, 1, s1);
+          enqueue_stage<T, NN, N, EPI_MID, true>(a, pr, kRkAlpha[2] * hc, 1.0, v, u, v, 2, s1);
+          enqueue_stage<T, NN, N, EPI_LAST, true>(a, pr, kRkAlpha[3] * hc, 1.0, v, u, u, 3, s1);
         }
+        done = true;
       }
       if (done) {
       } else if (a.scheme == 1) {
@@ -1828,8 +1903,15 @@ hipError_t enqueue_t(const StepArgs& a, const OpArgs& op, ProfRec* pr) {
       break;
     }
     case OP_FWD: {
-      // spectrum of u for the fused step (plane grids only)
-      if constexpr (!split_planes<NN>()) {
+      // spectrum of u for the fused step: the row spectrum on split grids,
+      // the xy spectrum on plane grids
+      if constexpr (split_planes<NN>()) {
+        using V = typename cplx_of<T>::type;
+        const int rblocks = M * NN * (NN / RowShape<NN>::RB);
+        hipLaunchKernelGGL((k_rows_fwd<T, NN>), dim3(rblocks), dim3(kZBlock), (rows_lds<T, NN>()), st,
+                           static_cast<const T*>(a.u), static_cast<V*>(a.spec), static_cast<const V*>(a.tw),
+                           cctl);
+      } else {
         using V = typename cplx_of<T>::type;
         constexpr int planes = M * NN;
         const T* src = static_cast<const T*>(a.u);

@@ -180,6 +180,32 @@ def test_split_grid_256_against_oracle(torch_cuda):
     assert rel(st, ref["state"]) <= TOL["f32"]
 
 
+@pytest.mark.parametrize("scheme,steps", [("rk4", 1), ("euler", 2)])
+def test_split_grid_256_source_and_fused_row_pass(torch_cuda, scheme, steps):
+    """256^3 split grid with a constant collimated slab source: the inverse
+    row pass writes the next stage's row spectrum (fused), across the stages
+    of an RK4 step and across Euler steps; P_1, FP32, element by element
+    against the FP64 oracle."""
+    n, N = 256, 1
+    print(f"\n[parity] split grid 256^3 P_1 f32 {scheme} {steps} step(s) with source", flush=True)
+    mu_a, mu_s, g = ri.sphere_maps(n, 32, 3, seed=8, radius=(8, 32))
+    psi0 = ri.gaussian_ic(n, N, sigma=3.0)
+    q = ri.collimated_slab_source(n, N, 32)
+    dt = 0.2 * 0.25 / 0.3 if scheme == "rk4" else 0.04
+    wl = ri.Workload("split_q", n, N, "f32", 0.25, 0.3, dt, 32, 0.01, 1.0, steps,
+                     mu_a, mu_s, g, psi0, q, scheme=scheme)
+    s = _solver(wl)
+    s.step(steps)
+    st = s.get_state()
+    phi = s.fluence(1)
+    s.close()
+    ref = pn.solve(n, N, wl.dx, wl.c, wl.dt, mu_a, mu_s, g, psi0, q, wl.W, wl.mu0, wl.mu1, steps,
+                   scheme=scheme)
+    e_state, e_phi = rel(st, ref["state"]), rel(phi, ref["phi_int"])
+    print(f"[parity] state {e_state:.2e} phi_int {e_phi:.2e}", flush=True)
+    assert e_state <= TOL["f32"] and e_phi <= TOL["f32"]
+
+
 def test_single_fourier_mode_256_p5(torch_cuda):
     """Full 256^3 / P_5 / FP32 size: single Fourier mode against the closed
     form R(dt M(k))^n, element by element."""
