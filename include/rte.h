@@ -211,6 +211,36 @@ int rte_forward_checkpointed(rte_handle* h, int64_t steps, int64_t every, void* 
 int rte_adjoint(rte_handle* h, int64_t steps, int64_t every, void* adj_ws, size_t adj_bytes,
                 const double* dj_dr, double* grad_mu_a, double* grad_mu_s);
 
+/* ---- Device-resident inputs and outputs (gradient loops) --------------
+ * For repeated forward / adjoint solves with changing mu_a, mu_s (fitting
+ * the optical maps, eqs. 1-2 and 12, through torch.autograd) without host
+ * copies of maps, readings or gradients. All pointers below are device
+ * pointers (8-byte aligned, FP64, caller-owned; read or written during the
+ * call only). RTE_EINVAL for null or misaligned pointers; values are not
+ * checked on the host (they must be what rte_create would accept).
+ *
+ * rte_set_medium_device: replace mu_a and mu_s (n^3 each) and rebuild the
+ * per-degree loss mu_a + mu_s (1 - g^l) inside the real domain on the
+ * device (same arithmetic as at creation; g and the absorbing layer are
+ * kept). The state and run bookkeeping are unchanged; exact propagation is
+ * no longer available on the handle, and snapshots taken before no longer
+ * restore into it. Synchronises.
+ *
+ * rte_set_state_device: as rte_set_state from `moments` leading FP64
+ * moments [moments][n^3] (0 <= moments <= M; the rest set to 0); the
+ * growth threshold is recomputed on the device from the new state.
+ * Synchronises.
+ *
+ * rte_readings_device: as rte_readings into a device buffer.
+ *
+ * rte_adjoint_device: as rte_adjoint with dj_dr [steps][n_det] and the two
+ * gradients (n^3 each) in device memory. */
+int rte_set_medium_device(rte_handle* h, const double* mu_a, const double* mu_s);
+int rte_set_state_device(rte_handle* h, const double* psi, int32_t moments);
+int rte_readings_device(rte_handle* h, double* out, size_t len, int64_t* rows);
+int rte_adjoint_device(rte_handle* h, int64_t steps, int64_t every, void* adj_ws, size_t adj_bytes,
+                       const double* dj_dr, double* grad_mu_a, double* grad_mu_s);
+
 /* ---- Time-dependent sources ------------------------------------------
  * Eq. (4) lets the source depend on time. rte_set_source_profile makes the
  * handle's source q(r) s(t): s is linear between samples[i] at

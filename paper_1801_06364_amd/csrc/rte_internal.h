@@ -210,8 +210,13 @@ enum {
   OP_EXPO = 10,      // u <- exact propagation over time coef (homogeneous medium)
   OP_PSTEP = 11,     // u <- one time step of u (y: stage scratch), no bookkeeping
   OP_FWD = 12,       // spectrum of u (the entry condition of a fused OP_STEP)
-  OP_GM_UPDATE = 13  // GMRES: Hessenberg column count (= j + 1) from the GmDev at u;
+  OP_GM_UPDATE = 13, // GMRES: Hessenberg column count (= j + 1) from the GmDev at u;
                      // sets the control block's stop flag once converged
+  OP_SET_LOSS = 14,  // loss maps inside the real domain from device FP64 mu_a (x) and
+                     // mu_s (djdr), with g from gin (the layer keeps its loss)
+  OP_SET_STATE = 15, // u <- device FP64 moments x (count leading moments, the rest 0)
+  OP_GROWTH = 16     // growth threshold of the control block from the weighted energy of u
+                     // and the source term (scale)
 };
 struct OpArgs {
   int kind;

@@ -870,6 +870,64 @@ k_adj_inject(T* __restrict__ lam, const long long* __restrict__ det, const doubl
   for (int p = threadIdx.x; p < ndet; p += kBlock) lam[det[p]] += T(djdr[p]);
 }
 
+// ------------------------------------------- media and states from HBM ---
+
+// Per-degree loss inside the real domain, Sigma_l = mu_a + mu_s (1 - g^l),
+// from device FP64 maps (the same FP64 arithmetic as the host construction,
+// without contraction, rounded once); voxels of the absorbing layer (gin > 1)
+// keep their loss, which does not depend on the medium.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_set_loss(T* __restrict__ sig, const double* __restrict__ mua, const double* __restrict__ mus,
+           const double* __restrict__ gin, int N, long long V) {
+#pragma clang fp contract(off)
+  for (long long v = (long long)blockIdx.x * kBlock + threadIdx.x; v < V; v += (long long)gridDim.x * kBlock) {
+    const double g = gin[v];
+    if (!(g <= 1.0)) continue;
+    const double a = mua[v], s = mus[v];
+    double gl = 1.0;
+    for (int l = 0; l <= N; ++l) {
+      sig[(long long)l * V + v] = T(a + s * (1.0 - gl));
+      gl *= g;
+    }
+  }
+}
+
+// u <- psi (device FP64, the `given` leading entries), zero beyond
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_set_state_f64(T* __restrict__ u, const double* __restrict__ psi, long long given, long long total) {
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < total; i += (long long)gridDim.x * kBlock)
+    u[i] = i < given ? T(psi[i]) : T(0);
+}
+
+// Runaway-growth threshold 1e16 (E + source_term + 1e-300) with E the
+// (2l+1)-weighted energy of u (one workgroup, fixed partition and tree:
+// deterministic); the same rule as the host-side threshold of a state set
+// from host memory.
+template <typename T>
+__global__ void __launch_bounds__(1024)
+k_growth_limit(const T* __restrict__ u, int M, long long V, double source_term, Ctl* __restrict__ ctl) {
+  __shared__ double red[1024];
+  double e = 0.0;
+  for (int a = 0; a < M; ++a) {
+    const double wt = double(2 * isqrt_c(a) + 1);
+    double s = 0.0;
+    for (long long i = threadIdx.x; i < V; i += 1024) {
+      const double x = double(u[(long long)a * V + i]);
+      s += x * x;
+    }
+    e += wt * s;
+  }
+  red[threadIdx.x] = e;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) ctl->growth_limit = 1e16 * (red[0] + source_term + 1e-300);
+}
+
 // ------------------------------------------------- Krylov vector kernels ---
 
 // Weighted inner products <x, y>_W = sum_a (2l+1) sum_r x_a(r) y_a(r) (the
@@ -1895,6 +1953,21 @@ hipError_t enqueue_t(const StepArgs& a, const OpArgs& op, ProfRec* pr) {
       const long long len = (long long)M * nvox;
       hipLaunchKernelGGL((k_rhs_minus<T>), dim3(kDotBlocks), dim3(kBlock), 0, st, static_cast<T*>(op.y),
                          static_cast<const T*>(op.x), len, cctl);
+      break;
+    }
+    case OP_SET_LOSS: {
+      hipLaunchKernelGGL((k_set_loss<T>), dim3(kDotBlocks), dim3(kBlock), 0, st, static_cast<T*>(const_cast<void*>(a.sig)),
+                         static_cast<const double*>(op.x), op.djdr, op.gin, N, nvox);
+      break;
+    }
+    case OP_SET_STATE: {
+      hipLaunchKernelGGL((k_set_state_f64<T>), dim3(kDotBlocks), dim3(kBlock), 0, st, static_cast<T*>(a.u),
+                         static_cast<const double*>(op.x), (long long)op.count * nvox, (long long)M * nvox);
+      break;
+    }
+    case OP_GROWTH: {
+      hipLaunchKernelGGL((k_growth_limit<T>), dim3(1), dim3(1024), 0, st, static_cast<const T*>(a.u), M, nvox,
+                         op.scale, static_cast<Ctl*>(a.ctl));
       break;
     }
     case OP_GM_UPDATE: {

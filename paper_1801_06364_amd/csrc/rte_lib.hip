@@ -923,9 +923,14 @@ int rte_forward_checkpointed(rte_handle* h, int64_t steps, int64_t every, void* 
   return c.stop == 2 ? RTE_EUNSTABLE : RTE_OK;
 }
 
-int rte_adjoint(rte_handle* h, int64_t steps, int64_t every, void* adj_ws, size_t adj_bytes,
-                const double* dj_dr, double* grad_mu_a, double* grad_mu_s) {
-  using namespace rte;
+}  // extern "C"
+
+namespace rte {
+namespace {
+// The reverse sweep of rte_adjoint; dev: dj_dr and the gradients are device
+// buffers (copied device to device) instead of host arrays.
+int adjoint_run(rte_handle* h, int64_t steps, int64_t every, void* adj_ws, size_t adj_bytes,
+                const double* dj_dr, double* grad_mu_a, double* grad_mu_s, bool dev) {
   if (!h || steps <= 0 || every <= 0 || !grad_mu_a || !grad_mu_s || h->batch_owned) return RTE_EINVAL;
   if (h->cfg.n_det > 0 && !dj_dr) return RTE_EINVAL;
   h->spec_valid = false;   // the recomputation and transposed stages reuse the spectrum buffers
@@ -940,7 +945,9 @@ int rte_adjoint(rte_handle* h, int64_t steps, int64_t every, void* adj_ws, size_
   auto ok = [&](hipError_t x) {
     if (e == hipSuccess) e = x;
   };
-  if (nd > 0) ok(hipMemcpyAsync(w + A.djdr, dj_dr, size_t(steps) * nd * 8, hipMemcpyHostToDevice, st));
+  if (nd > 0)
+    ok(hipMemcpyAsync(w + A.djdr, dj_dr, size_t(steps) * nd * 8,
+                      dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
   ok(hipMemsetAsync(w + A.gmua, 0, V * 8, st));
   ok(hipMemsetAsync(w + A.gmus, 0, V * 8, st));
   ok(hipMemsetAsync(w + A.lam, 0, F, st));
@@ -1055,10 +1062,81 @@ int rte_adjoint(rte_handle* h, int64_t steps, int64_t every, void* adj_ws, size_
     }
   }
   if (e != hipSuccess) return RTE_EDEVICE;
-  ok(hipMemcpyAsync(grad_mu_a, w + A.gmua, V * 8, hipMemcpyDeviceToHost, st));
-  ok(hipMemcpyAsync(grad_mu_s, w + A.gmus, V * 8, hipMemcpyDeviceToHost, st));
+  const hipMemcpyKind back = dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  ok(hipMemcpyAsync(grad_mu_a, w + A.gmua, V * 8, back, st));
+  ok(hipMemcpyAsync(grad_mu_s, w + A.gmus, V * 8, back, st));
   ok(hipStreamSynchronize(st));
   return to_code(e);
+}
+
+bool aligned8(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 7) == 0; }
+}  // namespace
+}  // namespace rte
+
+extern "C" {
+
+int rte_adjoint(rte_handle* h, int64_t steps, int64_t every, void* adj_ws, size_t adj_bytes,
+                const double* dj_dr, double* grad_mu_a, double* grad_mu_s) {
+  return rte::adjoint_run(h, steps, every, adj_ws, adj_bytes, dj_dr, grad_mu_a, grad_mu_s, false);
+}
+
+int rte_adjoint_device(rte_handle* h, int64_t steps, int64_t every, void* adj_ws, size_t adj_bytes,
+                       const double* dj_dr, double* grad_mu_a, double* grad_mu_s) {
+  using rte::aligned8;
+  if (!aligned8(dj_dr) || !aligned8(grad_mu_a) || !aligned8(grad_mu_s)) return RTE_EINVAL;
+  return rte::adjoint_run(h, steps, every, adj_ws, adj_bytes, dj_dr, grad_mu_a, grad_mu_s, true);
+}
+
+int rte_set_medium_device(rte_handle* h, const double* mu_a, const double* mu_s) {
+  using namespace rte;
+  if (!h || !mu_a || !mu_s || h->batch_owned || !aligned8(mu_a) || !aligned8(mu_s)) return RTE_EINVAL;
+  OpArgs o{};
+  o.kind = OP_SET_LOSS;
+  o.x = mu_a;
+  o.djdr = mu_s;
+  o.gin = h->at<double>(h->lay.gin);
+  if (launch_enqueue_op(h->n, h->args, o, nullptr) != 0) return RTE_EDEVICE;
+  // constant maps are no longer known on the host (no exact propagation),
+  // and snapshots taken under the previous medium no longer fit
+  h->homogeneous = false;
+  const uint64_t salt = 0x6d656469756d2121ULL;
+  fnv1a(h->medium_hash, &salt, sizeof salt);
+  return to_code(hipStreamSynchronize(h->stream));
+}
+
+int rte_set_state_device(rte_handle* h, const double* psi, int32_t moments) {
+  using namespace rte;
+  if (!h || h->batch_owned || moments < 0 || moments > h->M || (moments > 0 && !psi) || !aligned8(psi))
+    return RTE_EINVAL;
+  h->spec_valid = false;
+  int rc = reset_run_state(h, 1e300);   // threshold replaced on the device below
+  if (rc) return rc;
+  OpArgs o{};
+  o.kind = OP_SET_STATE;
+  o.x = psi;
+  o.count = moments;
+  if (launch_enqueue_op(h->n, h->args, o, nullptr) != 0) return RTE_EDEVICE;
+  OpArgs g{};
+  g.kind = OP_GROWTH;
+  g.scale = h->source_term;
+  if (launch_enqueue_op(h->n, h->args, g, nullptr) != 0) return RTE_EDEVICE;
+  return to_code(hipStreamSynchronize(h->stream));
+}
+
+int rte_readings_device(rte_handle* h, double* out, size_t len, int64_t* rows) {
+  if (!h || (!out && len) || !rte::aligned8(out)) return RTE_EINVAL;
+  rte::Ctl c;
+  int rc = rte::read_ctl(h, &c);
+  if (rc) return rc;
+  int64_t r = std::min<int64_t>(c.step, h->cfg.record_steps);
+  if (h->cfg.n_det == 0) r = 0;
+  else r = std::min<int64_t>(r, int64_t(len / size_t(h->cfg.n_det)));
+  if (rows) *rows = r;
+  if (r == 0) return RTE_OK;
+  hipError_t e = hipMemcpyAsync(out, h->ws + h->lay.readings, size_t(r) * h->cfg.n_det * 8,
+                                hipMemcpyDeviceToDevice, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  return rte::to_code(e);
 }
 
 size_t rte_krylov_workspace_bytes(const rte_config* cfg, int32_t restart) {

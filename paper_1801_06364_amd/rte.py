@@ -30,7 +30,8 @@ EXPORTS = (
     "rte_profile_expo", "rte_set_source_profile", "rte_snapshot_bytes", "rte_snapshot",
     "rte_restore", "rte_batch_slot_bytes", "rte_batch_create", "rte_batch_admit", "rte_batch_step",
     "rte_batch_poll", "rte_batch_handle", "rte_batch_release", "rte_batch_destroy",
-    "rte_static_scratch_bytes", "rte_steady_gmres_static",
+    "rte_static_scratch_bytes", "rte_steady_gmres_static", "rte_set_medium_device",
+    "rte_set_state_device", "rte_readings_device", "rte_adjoint_device",
 )
 RTE_SLOT_FREE, RTE_SLOT_STAGING, RTE_SLOT_STAGED, RTE_SLOT_RUNNING, RTE_SLOT_DONE, RTE_SLOT_FAILED = range(6)
 KERNEL_CLASSES = ("fwd_plane", "zderiv", "couple", "inv_plane", "end_step",
@@ -106,6 +107,14 @@ def lib():
         L.rte_forward_checkpointed.restype = C.c_int
         L.rte_adjoint.argtypes = [vp, C.c_int64, C.c_int64, vp, C.c_size_t, dp, dp, dp]
         L.rte_adjoint.restype = C.c_int
+        L.rte_adjoint_device.argtypes = [vp, C.c_int64, C.c_int64, vp, C.c_size_t, vp, vp, vp]
+        L.rte_adjoint_device.restype = C.c_int
+        L.rte_set_medium_device.argtypes = [vp, vp, vp]
+        L.rte_set_medium_device.restype = C.c_int
+        L.rte_set_state_device.argtypes = [vp, vp, C.c_int32]
+        L.rte_set_state_device.restype = C.c_int
+        L.rte_readings_device.argtypes = [vp, vp, C.c_size_t, i64p]
+        L.rte_readings_device.restype = C.c_int
         L.rte_krylov_workspace_bytes.argtypes = [C.POINTER(rte_config), C.c_int32]
         L.rte_krylov_workspace_bytes.restype = C.c_size_t
         L.rte_steady_gmres.argtypes = [vp, C.c_int32, C.c_int64, C.c_double, C.c_int32, vp, C.c_size_t,
@@ -386,6 +395,56 @@ class Solver:
                                  C.c_void_p(self.adj_ws.data_ptr()), self.adj_ws.numel(),
                                  _dptr(d), _dptr(ga), _dptr(gs)), "rte_adjoint")
         return ga.reshape(n, n, n), gs.reshape(n, n, n)
+
+    # -- device-resident inputs and outputs ----------------------------------
+    @staticmethod
+    def _dev_f64(t, numel, what):
+        import torch
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+                and t.numel() == numel):
+            raise RteError(RTE_EINVAL, f"{what}: a contiguous FP64 CUDA tensor of {numel} elements")
+        return C.c_void_p(t.data_ptr())
+
+    def set_medium_device(self, mu_a, mu_s):
+        """New mu_a, mu_s from FP64 CUDA tensors (n^3 each), loss maps rebuilt on the device."""
+        n3 = self.n ** 3
+        _check(lib().rte_set_medium_device(self.h, self._dev_f64(mu_a, n3, "mu_a"),
+                                           self._dev_f64(mu_s, n3, "mu_s")), "rte_set_medium_device")
+
+    def set_state_device(self, psi):
+        """State from an FP64 CUDA tensor holding K leading moments (K n^3 elements)."""
+        n3 = self.n ** 3
+        k = psi.numel() // n3
+        if k * n3 != psi.numel() or k > self.M:
+            raise RteError(RTE_EINVAL, "psi must hold whole leading moments")
+        _check(lib().rte_set_state_device(self.h, self._dev_f64(psi, k * n3, "psi"), k),
+               "rte_set_state_device")
+
+    def readings_device(self):
+        """Readings [rows][n_det] as an FP64 CUDA tensor (device-to-device copy)."""
+        import torch
+        cap = int(self.cfg.record_steps)
+        out = torch.empty((max(cap, 1), max(self.n_det, 1)), dtype=torch.float64, device=self.workspace.device)
+        rows = C.c_int64(0)
+        _check(lib().rte_readings_device(self.h, C.c_void_p(out.data_ptr()), cap * self.n_det, C.byref(rows)),
+               "rte_readings_device")
+        return out[:int(rows.value), :self.n_det]
+
+    def adjoint_device(self, dj_dr):
+        """dJ/dmu_a, dJ/dmu_s as FP64 CUDA tensors (n, n, n) for adjoint
+        sources dj_dr[step][det] given as an FP64 CUDA tensor."""
+        import torch
+        n = self.n
+        dev = self.workspace.device
+        ga = torch.empty(n ** 3, dtype=torch.float64, device=dev)
+        gs = torch.empty(n ** 3, dtype=torch.float64, device=dev)
+        d = dj_dr.to(device=dev, dtype=torch.float64).contiguous()
+        _check(lib().rte_adjoint_device(self.h, self.adj_steps, self.adj_every,
+                                        C.c_void_p(self.adj_ws.data_ptr()), self.adj_ws.numel(),
+                                        self._dev_f64(d, self.adj_steps * self.n_det, "dj_dr"),
+                                        C.c_void_p(ga.data_ptr()), C.c_void_p(gs.data_ptr())),
+               "rte_adjoint_device")
+        return ga.view(n, n, n), gs.view(n, n, n)
 
     def profile_kernels(self, nsteps: int):
         """Per-kernel-class milliseconds (summed) and launch counts over

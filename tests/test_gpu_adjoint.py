@@ -186,3 +186,61 @@ def test_full_size_adjoint_vs_finite_differences(torch_cuda):
         Jm = float(((_readings(wl64, ma, wl.mu_s) - target) ** 2).sum())
         fd = (Jp - Jm) / (2 * h)
         assert abs(fd - ga[z, y, x]) <= 1e-4 * abs(fd), (v, fd, ga[z, y, x])
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_device_medium_and_state_reproduce_host_creation(torch_cuda, prec):
+    """A handle created with other maps, then given mu_a, mu_s and the
+    initial state from device memory (loss maps rebuilt on the device),
+    steps bitwise like a handle created from those maps on the host: state
+    and readings (read back device to device)."""
+    torch = torch_cuda
+    from paper_1801_06364_amd.rte import Solver
+    wl, tgt = _problem(n=16, steps=6, prec=prec)
+    a = Solver.from_workload(wl)
+    a.step(wl.steps)
+    ref_state, ref_read = a.get_state(), a.readings()
+    a.close()
+    b = Solver.from_workload(wl, mu_a=tgt[0], mu_s=tgt[1])   # created with other maps
+    b.set_medium_device(torch.tensor(wl.mu_a.ravel(), dtype=torch.float64, device="cuda"),
+                        torch.tensor(wl.mu_s.ravel(), dtype=torch.float64, device="cuda"))
+    b.step(3)                                                  # state and record are replaced next
+    b.set_state_device(torch.tensor(wl.psi0.ravel(), dtype=torch.float64, device="cuda"))
+    assert b.steps_done() == 0
+    b.step(wl.steps)
+    st, rd = b.get_state(), b.readings_device().cpu().numpy()
+    b.close()
+    assert np.array_equal(st, ref_state)
+    assert np.array_equal(rd, ref_read)
+
+
+def test_autograd_device_path_repeated_solves(torch_cuda):
+    """Two solves with different maps through one device-resident problem:
+    each gradient equals the host-path adjoint of its own maps (FP64,
+    <= 1e-12) and the oracle's reverse mode (<= 1e-10)."""
+    torch = torch_cuda
+    from paper_1801_06364_amd.autograd import RteProblem, rte_solve
+    from paper_1801_06364_amd.rte import Solver
+    wl, tgt = _problem(n=16, steps=5)
+    prob = RteProblem(wl.n, wl.N, wl.dx, wl.c, wl.dt, wl.g, psi0=wl.psi0, W=wl.W, mu0=wl.mu0, mu1=wl.mu1,
+                      precision="f64", det_index=wl.det_index, steps=wl.steps, every=2)
+    for ma, ms in ((wl.mu_a, wl.mu_s), (tgt[0], tgt[1])):
+        mua = torch.tensor(ma, dtype=torch.float64, device="cuda", requires_grad=True)
+        mus = torch.tensor(ms, dtype=torch.float64, device="cuda", requires_grad=True)
+        r = rte_solve(mua, mus, prob)
+        assert r.is_cuda
+        (r ** 2).sum().backward()
+        rr = r.detach().cpu().numpy()
+        h = Solver.from_workload(wl, mu_a=ma, mu_s=ms)
+        h.forward_checkpointed(wl.steps, 2)
+        assert np.array_equal(h.readings(), rr)
+        ga_h, gs_h = h.adjoint(2.0 * rr)
+        h.close()
+        assert mua.grad.is_cuda and mus.grad.is_cuda
+        assert rel(mua.grad.cpu().numpy(), ga_h) <= 1e-12
+        assert rel(mus.grad.cpu().numpy(), gs_h) <= 1e-12
+        ga_ref, gs_ref = pn.adjoint_gradient(wl.n, wl.N, wl.dx, wl.c, wl.dt, ma, ms, wl.g, wl.psi0, None, wl.W,
+                                             wl.mu0, wl.mu1, wl.steps, wl.det_index, 2.0 * rr)
+        assert rel(mua.grad.cpu().numpy(), ga_ref) <= 1e-10
+        assert rel(mus.grad.cpu().numpy(), gs_ref) <= 1e-10
+    prob.close()
