@@ -133,7 +133,7 @@ def serving_bench(a):
     torch.cuda.set_device(0)
     specs = ri.serving_requests(count=a.requests, seed=4)
     srv = serving.Server(budget_bytes=int(a.budget_gib * 2 ** 30), max_slots=a.slots,
-                         chunk=a.chunk)
+                         chunk=a.chunk, big_slots=a.big_slots)
     # warm-up: one small request (library load, first launches), not reported
     srv.service_times([ri.RequestSpec(-1, 32, 1, 5, 0, 0, 1.0)])
     print(f"[serving] {len(specs)} requests; measuring one-at-a-time service times",
@@ -158,6 +158,7 @@ def serving_bench(a):
                                   "inclusions, Gaussian pulse; Poisson arrivals at 1.5 / mean "
                                   "one-at-a-time service time",
                       "budget_GiB": a.budget_gib, "max_slots_per_batch": a.slots,
+                      "slots_above_512MiB": a.big_slots,
                       "chunk_steps": a.chunk,
                       "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES"), "rate_per_s": rate,
                       "mean_service_s": float(svc.mean())},
@@ -362,9 +363,10 @@ def gmres_iteration_bytes(n, M, N, s, m, K):
 
 def steady_bench(a):
     """Steady state of the absorbing-layer recipe (log-normal medium,
-    collimated slab source) at 64^3 / P_5 by device GMRES against time
-    marching, both in FP32, each measured to the same distance from an FP64
-    GMRES reference."""
+    collimated slab source) at n^3 / P_5 (n = 128 by default: at 64^3 a
+    state of 38 MB sits in the caches, so an HBM roofline means little
+    there) by device GMRES against time marching, both in FP32, each
+    measured to the same distance from an FP64 GMRES reference."""
     import numpy as np
     import torch
 
@@ -373,7 +375,7 @@ def steady_bench(a):
 
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
-    n = 64
+    n = a.steady_n
     ref_wl = ri.workload("p5_steady", n=n, steps=0, precision="f64")
     r = Solver.from_workload(ref_wl, stream=stream)
     it_ref, res_ref = r.steady_gmres(tol=1e-10, restart=30, max_iters=4000, steps_per_apply=a.steady_k)
@@ -443,6 +445,86 @@ def steady_bench(a):
                         "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": gbs / HBM_PEAK_GBS, "traffic": None,
                         "algorithmic_bytes": bytes_it}}
+    print(json.dumps(out), flush=True)
+
+
+def cfg3_bench(a):
+    """The 256^3 / P_5 steady-state workload (log-normal medium, collimated
+    slab source): FP32 time marching until the relative fluence change of a
+    step drops below 1e-6 (steady state by marching, Sec. II.A / III.B),
+    then the FP64 GPU march over the same number of steps n* (the same
+    trajectory: the error of FP32 alone, at the full horizon), both timed.
+    Fluence and FP64 integrated fluence compared by relative L2. Optionally
+    (--cfg3-gmres) also the FP64 fixed point by GMRES on I - P^K."""
+    import numpy as np
+    import torch
+
+    import rte_inputs as ri
+    from paper_1801_06364_amd.rte import Solver
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    n, tol, chunk = 256, 1e-6, 500
+
+    def rel(x, y):
+        return float(np.linalg.norm(np.ravel(x) - np.ravel(y)) / np.linalg.norm(np.ravel(y)))
+
+    def log(msg):
+        print(f"[cfg3] {msg}", file=sys.stderr, flush=True)
+
+    def march(prec, limit, stop_tol):
+        m = Solver.from_workload(ri.workload("p5_steady", n=n, steps=0, precision=prec), stream=stream,
+                                 record_steps=0)
+        steps, t = 0, 0.0
+        while steps < limit:
+            k = min(chunk, limit - steps)
+            t0 = time.perf_counter()
+            if stop_tol > 0:
+                took = m.run(k, stop_tol)
+            else:
+                m.step(k)
+                took = k
+            stream.synchronize()
+            t += time.perf_counter() - t0
+            steps += took
+            log(f"{prec} march: {steps} steps, {t:.1f} s")
+            if stop_tol > 0 and took < chunk:
+                break
+        out = (steps, t, m.fluence(), m.fluence(1))
+        m.close()
+        return out
+
+    s32, t32, f32, p32 = march("f32", a.cfg3_max_steps, tol)
+    converged = s32 < a.cfg3_max_steps
+    s64, t64, f64, p64 = march("f64", s32, 0.0)
+    out = {"metric": "steady state of the 256^3 P_5 workload by FP32 marching, against FP64 marching",
+           "value": t32, "unit": "s", "n_gpus": 1, "steps": s32, "warmup": 0,
+           "ms_per_step": 1e3 * t32 / max(s32, 1), "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "p5_steady: P_5 (36 moments), 256^3, log-normal mu_a / mu_s "
+                                  "(correlation 20 voxels), g 0.85, 32-voxel absorbing layer, "
+                                  "constant collimated slab source; march until the relative fluence "
+                                  "change of a step < 1e-6",
+                      "n": n, "order_N": 5, "steady_tol": tol},
+           "march_fp32": {"steps": s32, "converged": converged, "seconds": t32},
+           "march_fp64_same_steps": {"steps": s64, "seconds": t64},
+           "fp32_vs_fp64": {"fluence": rel(f32, f64), "integrated_fluence": rel(p32, p64)}}
+    if a.cfg3_gmres:
+        g = Solver.from_workload(ri.workload("p5_steady", n=n, steps=0, precision="f64"), stream=stream)
+        t0 = time.perf_counter()
+        it, res = 0, 1.0
+        while it < a.cfg3_max_arnoldi:
+            k, res = g.steady_gmres(tol=1e-8, restart=a.cfg3_restart, max_iters=a.cfg3_restart,
+                                    steps_per_apply=a.steady_k)
+            it += k
+            log(f"f64 GMRES: {it} Arnoldi steps, residual {res:.2e}, {time.perf_counter() - t0:.1f} s")
+            if res <= 1e-8 or k == 0:
+                break
+        f_ref = g.fluence()
+        g.close()
+        out["gmres_fp64"] = {"arnoldi_steps": it, "residual": res, "seconds": time.perf_counter() - t0,
+                             "fp32_march_vs_fixed_point": rel(f32, f_ref),
+                             "fp64_march_vs_fixed_point": rel(f64, f_ref)}
     print(json.dumps(out), flush=True)
 
 
@@ -661,9 +743,11 @@ def main():
     ap.add_argument("--serving", action="store_true",
                     help="serve the seeded Poisson request trace instead (separate JSON line)")
     ap.add_argument("--requests", type=int, default=256)
-    ap.add_argument("--budget-gib", type=float, default=48.0)
+    ap.add_argument("--budget-gib", type=float, default=160.0)
     ap.add_argument("--slots", type=int, default=16, help="largest batch per configuration class")
     ap.add_argument("--chunk", type=int, default=16, help="time steps per queued batch chunk")
+    ap.add_argument("--big-slots", type=int, default=16,
+                    help="slots per batch for configurations above 512 MiB per solve")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--accuracy-steps", type=int, default=200,
                     help="RK4 steps of the FP32-vs-FP64 comparison on the timed configuration")
@@ -680,6 +764,14 @@ def main():
     ap.add_argument("--steady-k", type=int, default=20,
                     help="time steps per operator application of the steady GMRES")
     ap.add_argument("--steady-march-limit", type=float, default=60.0)
+    ap.add_argument("--steady-n", type=int, default=128, help="grid of the --steady comparison")
+    ap.add_argument("--cfg3", action="store_true",
+                    help="256^3 P_5 steady state: FP32 march to a 1e-6 change vs FP64 GMRES (JSON line)")
+    ap.add_argument("--cfg3-max-steps", type=int, default=30000)
+    ap.add_argument("--cfg3-restart", type=int, default=16)
+    ap.add_argument("--cfg3-max-arnoldi", type=int, default=480)
+    ap.add_argument("--cfg3-gmres", action="store_true",
+                    help="also the FP64 fixed point by GMRES (long at 256^3)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the hot path is a single-GPU solve "
@@ -699,6 +791,8 @@ def main():
         return expo_bench(a)
     if a.steady:
         return steady_bench(a)
+    if a.cfg3:
+        return cfg3_bench(a)
     if a.paper:
         return paper_bench(a)
     if a.adjoint:

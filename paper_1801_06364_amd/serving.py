@@ -121,12 +121,13 @@ class _Engine:
 
 class Server:
     """Continuous batching within an HBM budget of ``budget_bytes``; each
-    class's engine holds up to ``max_slots`` solves (fewer if one class
-    would take more than ``class_share`` of the budget)."""
+    class's engine holds up to ``max_slots`` solves (``big_slots`` for
+    classes whose solves take more than ``big_bytes`` each, fewer if one
+    class would take more than ``class_share`` of the budget)."""
 
     def __init__(self, budget_bytes: int = 48 << 30, max_slots: int = 16, precision: str = "f32",
                  keep_fluence: bool = False, chunk: int = 16, class_share: float = 0.25,
-                 workers: int = 2):
+                 workers: int = 2, big_bytes: int = 512 << 20, big_slots: int = 16):
         import torch
         self.torch = torch
         self.budget = int(budget_bytes)
@@ -136,13 +137,16 @@ class Server:
         self.chunk = int(chunk)
         self.class_share = float(class_share)
         self.workers = int(workers)
+        self.big_bytes = int(big_bytes)
+        self.big_slots = int(big_slots)
 
     def _slots_for(self, spec):
         wl = spec.workload(self.precision)
         cfg, _ = rte.make_config(wl.n, wl.N, rte.RTE_FP64 if self.precision == "f64" else rte.RTE_FP32,
                                  wl.dx, wl.c, wl.dt, wl.W, wl.mu0, wl.mu1)
         per = int(rte.lib().rte_batch_slot_bytes(cfg))
-        return max(1, min(self.max_slots, int(self.class_share * self.budget) // per)), per
+        cap = self.big_slots if per > self.big_bytes else self.max_slots
+        return max(1, min(cap, int(self.class_share * self.budget) // per)), per
 
     @staticmethod
     def _admit(engine, slot, spec, precision):
