@@ -139,6 +139,47 @@ template <typename V, int DIR> struct Bfly<V, 8, DIR> {
   }
 };
 
+// 16-point DFT, v[q] <- sum_r v[r] exp(DIR 2 pi i q r / 16): radix 4 over
+// r = 4 r1 + r2, internal twiddles exp(DIR 2 pi i q1 r2 / 16), radix 4 over
+// r2; output q = q1 + 4 q2.
+template <typename V, int DIR> struct Bfly<V, 16, DIR> {
+  static __device__ __forceinline__ void run(V* v) {
+    using T = decltype(V::x);
+    const T c1 = T(0.92387953251128675613), s1 = T(0.38268343236508977173);   // cos, sin(pi/8)
+    const T r2 = T(0.70710678118654752440);
+    const T dr = T(DIR);
+    V y[4][4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      y[b][0] = v[b];
+      y[b][1] = v[b + 4];
+      y[b][2] = v[b + 8];
+      y[b][3] = v[b + 12];
+      Bfly<V, 4, DIR>::run(y[b]);
+    }
+    // y[r2][q1] *= exp(DIR 2 pi i q1 r2 / 16)
+    auto rot = [dr](V a, T c, T s) { return cmk<V>(a.x * c - dr * a.y * s, a.y * c + dr * a.x * s); };
+    auto r8 = [dr, r2](V a) { return cmk<V>((a.x - dr * a.y) * r2, (a.y + dr * a.x) * r2); };
+    auto r38 = [dr, r2](V a) { return cmk<V>((-a.x - dr * a.y) * r2, (-a.y + dr * a.x) * r2); };
+    y[1][1] = rot(y[1][1], c1, s1);
+    y[1][2] = r8(y[1][2]);
+    y[1][3] = rot(y[1][3], s1, c1);
+    y[2][1] = r8(y[2][1]);
+    y[2][2] = cmul_i<V, DIR>(y[2][2]);
+    y[2][3] = r38(y[2][3]);
+    y[3][1] = rot(y[3][1], s1, c1);
+    y[3][2] = r38(y[3][2]);
+    y[3][3] = rot(y[3][3], -c1, -s1);   // exp(DIR i 9 pi / 8)
+#pragma unroll
+    for (int q1 = 0; q1 < 4; ++q1) {
+      V t[4] = {y[0][q1], y[1][q1], y[2][q1], y[3][q1]};
+      Bfly<V, 4, DIR>::run(t);
+#pragma unroll
+      for (int q2 = 0; q2 < 4; ++q2) v[q1 + 4 * q2] = t[q2];
+    }
+  }
+};
+
 // Element accessors. An FFT pass addresses element i of FFT f through an
 // accessor `at` with i split as i = a + b: `a` holds the lane-dependent
 // part and `b` a compile-time part whose bits are disjoint from those of a

@@ -1577,8 +1577,28 @@ k_expo_blocks(typename cplx_of<T>::type* __restrict__ spec, const typename cplx_
 }  // namespace rte
 
 #include "rte_plane128.h"
+#include "rte_pencil.h"
 
 namespace rte {
+
+// One pencil pass over all M n (n/2) / TZ tiles: the register pencils of FP32
+// 128^3 / 256^3 grids where they apply, k_pencil otherwise (ns slot rows,
+// bs slot stride for batched launches).
+template <typename T, int NN, int MODE>
+void launch_pencil(hipStream_t st, const typename cplx_of<T>::type* src, typename cplx_of<T>::type* dst,
+                   const typename cplx_of<T>::type* tw, const T* kv, const Ctl* ctl, int M, unsigned ns = 1,
+                   long long bs = 0) {
+  if constexpr (pen::use_reg<T, NN, MODE>()) {
+    const int tiles = M * NN * pen::Shape<NN>::NTILE;
+    hipLaunchKernelGGL((pen::k_pencil_reg<NN, MODE>), dim3(tiles, ns), dim3(pen::Shape<NN>::THREADS), 0, st, src, dst, tw, kv, ctl,
+                       bs);
+  } else {
+    using Z = ZdShape<T, NN>;
+    const int tiles = M * NN * Z::NTILE;
+    hipLaunchKernelGGL((k_pencil<T, NN, MODE>), dim3(tiles, ns), dim3(kZBlock), (zd_lds<T, NN>()), st, src, dst,
+                       tw, kv, ctl, bs);
+  }
+}
 
 // ---------------------------------------------------------------- launch ---
 
@@ -1682,10 +1702,9 @@ void enqueue_stage(const StepArgs& a, ProfRec* pr, double hs, double sgn, const 
   const double n2 = double(NN) * NN;
   const dim3 pblk(kPBlock), zblk(kZBlock), cblk(kCBlock);
   const int planes = M * NN;
-  const int pencils = M * NN * Z::NTILE;
   const int cblocks = (NN * NN * (NN / 2) + kCBlock - 1) / kCBlock;
   const int rblocks = M * NN * (NN / RowShape<NN>::RB);
-  const size_t lp = plane_lds<T, NN>(), lz = zd_lds<T, NN>(), lr = rows_lds<T, NN>();
+  const size_t lp = plane_lds<T, NN>(), lr = rows_lds<T, NN>();
   // batched launches (plane grids, register coupling): grid rows = slots
   const unsigned ns = a.nslot > 1 ? unsigned(a.nslot) : 1u;
   const long long bs = ns > 1 ? a.sstride : 0;
@@ -1702,7 +1721,7 @@ void enqueue_stage(const StepArgs& a, ProfRec* pr, double hs, double sgn, const 
       hipLaunchKernelGGL((k_rows_fwd<T, NN>), dim3(rblocks), zblk, lr, st, src, spec, tw, cctl);
       rec(PROF_FWD_ROWS);
     }
-    hipLaunchKernelGGL((k_pencil<T, NN, PENCIL_YFWD>), dim3(pencils), zblk, lz, st, spec, spec, tw, kv, cctl);
+    launch_pencil<T, NN, PENCIL_YFWD>(st, spec, spec, tw, kv, cctl, M);
     rec(PROF_Y_FWD);
   } else if constexpr (!FUSE) {
     // (fused stages find the spectrum of src already written by the
@@ -1710,8 +1729,7 @@ void enqueue_stage(const StepArgs& a, ProfRec* pr, double hs, double sgn, const 
     launch_fwd_plane<T, NN>(st, src, spec, tw, cctl, planes);
     rec(PROF_FWD_PLANE);
   }
-  hipLaunchKernelGGL((k_pencil<T, NN, PENCIL_ZDERIV>), dim3(pencils, ns), zblk, lz, st, spec, dspec, tw, kv, cctl,
-                     bs);
+  launch_pencil<T, NN, PENCIL_ZDERIV>(st, spec, dspec, tw, kv, cctl, M, ns, bs);
   rec(PROF_ZDERIV);
   V* coupled = spec;   // the inverse passes read the coupled spectrum from here
   if constexpr (N <= kDenseOrder) {
@@ -1724,8 +1742,7 @@ void enqueue_stage(const StepArgs& a, ProfRec* pr, double hs, double sgn, const 
   }
   rec(PROF_COUPLE);
   if constexpr (split_planes<NN>()) {
-    hipLaunchKernelGGL((k_pencil<T, NN, PENCIL_YINV>), dim3(pencils), zblk, lz, st, coupled, coupled, tw, kv,
-                       cctl);
+    launch_pencil<T, NN, PENCIL_YINV>(st, coupled, coupled, tw, kv, cctl, M);
     rec(PROF_Y_INV);
     hipLaunchKernelGGL((k_rows_inv<T, NN, MODE, FUSE>), dim3(rblocks), zblk, lr, st, coupled, src, u, out, sig,
                        q, a.qflag, a.phi_int, a.partial, tw, M, T(hs), a.dt, cctl, stage, step1,

@@ -83,43 +83,6 @@ template <int DIR> __device__ __forceinline__ float2 twid(float2 w) {
   return w;
 }
 
-// 16-point DFT in registers, v[q] <- sum_r v[r] exp(DIR 2 pi i q r / 16):
-// radix-4 over r = 4 r1 + r2, internal twiddles exp(DIR 2 pi i q1 r2 / 16),
-// radix-4 over r2, output q = q1 + 4 q2.
-template <int DIR> __device__ __forceinline__ void bfly16(float2* v) {
-  const float c1 = 0.92387953251128675613f, s1 = 0.38268343236508977173f;   // cos, sin(pi/8)
-  const float r2 = 0.70710678118654752440f;
-  float2 y[4][4];
-#pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    y[b][0] = v[b];
-    y[b][1] = v[b + 4];
-    y[b][2] = v[b + 8];
-    y[b][3] = v[b + 12];
-    Bfly<float2, 4, DIR>::run(y[b]);
-  }
-  // y[r2][q1] *= exp(DIR 2 pi i q1 r2 / 16)
-  auto rot = [](float2 a, float c, float s) {   // a * (c + DIR i s)
-    return cmk<float2>(a.x * c - float(DIR) * a.y * s, a.y * c + float(DIR) * a.x * s);
-  };
-  y[1][1] = rot(y[1][1], c1, s1);
-  y[1][2] = cmk<float2>((y[1][2].x - float(DIR) * y[1][2].y) * r2, (y[1][2].y + float(DIR) * y[1][2].x) * r2);
-  y[1][3] = rot(y[1][3], s1, c1);
-  y[2][1] = cmk<float2>((y[2][1].x - float(DIR) * y[2][1].y) * r2, (y[2][1].y + float(DIR) * y[2][1].x) * r2);
-  y[2][2] = cmul_i<float2, DIR>(y[2][2]);
-  y[2][3] = cmk<float2>((-y[2][3].x - float(DIR) * y[2][3].y) * r2, (-y[2][3].y + float(DIR) * y[2][3].x) * r2);
-  y[3][1] = rot(y[3][1], s1, c1);
-  y[3][2] = cmk<float2>((-y[3][2].x - float(DIR) * y[3][2].y) * r2, (-y[3][2].y + float(DIR) * y[3][2].x) * r2);
-  y[3][3] = rot(y[3][3], -c1, -s1);   // exp(DIR i 9 pi / 8)
-#pragma unroll
-  for (int q1 = 0; q1 < 4; ++q1) {
-    float2 t[4] = {y[0][q1], y[1][q1], y[2][q1], y[3][q1]};
-    Bfly<float2, 4, DIR>::run(t);
-#pragma unroll
-    for (int q2 = 0; q2 < 4; ++q2) v[q1 + 4 * q2] = t[q2];
-  }
-}
-
 // Complex-to-real merge of one packed spectral value with its partner
 // X_{64-k}: (P + conj Q) + i conj(w) (P - conj Q), w = exp(-2 pi i k / 128).
 __device__ __forceinline__ float2 merge_inv(float2 p, float2 q, float2 w) {
@@ -253,7 +216,7 @@ __device__ __forceinline__ void forward_plane(float2* c0, float2* c1, float2* pl
     const float2* s = pl + wv * PITCH + ln;
 #pragma unroll
     for (int r = 0; r < 16; ++r) x[r] = s[8 * r * PITCH];
-    bfly16<-1>(x);
+    Bfly<float2, 16, -1>::run(x);
     __syncthreads();
     float2* d = pl + 16 * wv * PITCH + ln;
 #pragma unroll
@@ -347,7 +310,7 @@ k_plane128(const float2* spec, const float* vin, float* u, float* dst, const flo
     float2 x[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) x[r] = ld_b<float2>(sp, lo + unsigned(8 * r * H * 8));
-    bfly16<+1>(x);
+    Bfly<float2, 16, +1>::run(x);
     float2* d = pl + 16 * wv * PITCH + ln;
 #pragma unroll
     for (int k = 0; k < 16; ++k) d[k * PITCH] = x[k];
