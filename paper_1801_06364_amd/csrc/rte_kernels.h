@@ -397,16 +397,30 @@ k_rows_fwd(const T* __restrict__ src, typename cplx_of<T>::type* __restrict__ sp
 
 // --------------------------------------------------- C: moment coupling ---
 
-// For one spectral point (kx, ky, z) with all moments' xy spectra S_b in
-// registers and the z derivatives D_b in memory, the streaming term of
-// eq. (10) in the real basis is
+// For one spectral point (kx, ky, z) the streaming term of eq. (10) in the
+// real basis is
 //   W_a = s * ( -i (kx Bx + ky By)[a,b] S_b  -  Bz[a,b] D_b ),
-// with Bz non-zero only between equal orders m.
-template <typename V, typename T, int N, int A, int S>
-struct RowAcc {
+// S the moments' xy spectra, D their z derivatives. Bx and By join orders
+// |m| and |m| +- 1, Bz only equal orders (eq. 6; the real basis mixes m and
+// -m only). So the rows with even |m| read S at odd |m| and D at even |m|,
+// and the rows with odd |m| the other halves: two threads per point, one per
+// parity class P, read every input exactly once between them, and each
+// writes its rows over the D entries that only it reads.
+__host__ __device__ constexpr int m_parity(int a) {
+  const int l = isqrt_c(a), m = a - l * l - l;
+  return (m < 0 ? -m : m) & 1;
+}
+__host__ __device__ constexpr int parity_rows(int N, int P) {
+  int c = 0;
+  for (int a = 0; a < (N + 1) * (N + 1); ++a) c += m_parity(a) == P;
+  return c;
+}
+
+template <typename V, typename T, int N, int A, int S, int P>
+struct RowAccP {
   // acc: (re, im) of the x and y sums of S, then of the z sum of D; the
   // coefficients are instruction constants (one axis per non-zero)
-  static __device__ __forceinline__ void run(const V* in, const V* __restrict__ dcol, size_t mstride, T* acc) {
+  static __device__ __forceinline__ void run(const V* sr, const V* dr, T* acc) {
     constexpr int l = isqrt_c(A);
     constexpr int m = A - l * l - l;
     constexpr SlotList sl = slots_of(N, l, m);
@@ -415,80 +429,101 @@ struct RowAcc {
       constexpr double c0 = ct::real_coef(N, 0, A, b);
       constexpr double c1 = ct::real_coef(N, 1, A, b);
       constexpr double c2 = ct::real_coef(N, 2, A, b);
+      static_assert((c0 == 0.0 && c1 == 0.0) || m_parity(b) != P, "x, y coupling within one |m| parity");
+      static_assert(c2 == 0.0 || m_parity(b) == P, "z coupling across |m| parities");
       if constexpr (c0 != 0.0) {
-        acc[0] += T(c0) * in[b].x;
-        acc[1] += T(c0) * in[b].y;
+        acc[0] += T(c0) * sr[b].x;
+        acc[1] += T(c0) * sr[b].y;
       }
       if constexpr (c1 != 0.0) {
-        acc[2] += T(c1) * in[b].x;
-        acc[3] += T(c1) * in[b].y;
+        acc[2] += T(c1) * sr[b].x;
+        acc[3] += T(c1) * sr[b].y;
       }
       if constexpr (c2 != 0.0) {
-        const V d = dcol[b * mstride];
-        acc[4] += T(c2) * d.x;
-        acc[5] += T(c2) * d.y;
+        acc[4] += T(c2) * dr[b].x;
+        acc[5] += T(c2) * dr[b].y;
       }
-      RowAcc<V, T, N, A, S + 1>::run(in, dcol, mstride, acc);
+      RowAccP<V, T, N, A, S + 1, P>::run(sr, dr, acc);
     }
   }
 };
 
-template <typename V, int L, int N>
-__device__ __forceinline__ void load_shell(V* in, const V* __restrict__ sp, size_t mstride) {
-  if constexpr (L <= N) {
-#pragma unroll
-    for (int b = L * L; b < (L + 1) * (L + 1); ++b) in[b] = sp[b * mstride];
+// Shell L's inputs of class P: S at the other parity, D at this one.
+template <typename V, int N, int P, int B, int END>
+struct LoadShellP {
+  static __device__ __forceinline__ void run(V* sr, V* dr, const V* __restrict__ sp, const V* dp, size_t ms) {
+    if constexpr (B < END) {
+      if constexpr (m_parity(B) != P) sr[B] = sp[B * ms];
+      else dr[B] = dp[B * ms];
+      LoadShellP<V, N, P, B + 1, END>::run(sr, dr, sp, dp, ms);
+    }
   }
+};
+template <typename V, int L, int N, int P>
+__device__ __forceinline__ void load_shell_p(V* sr, V* dr, const V* __restrict__ sp, const V* dp, size_t ms) {
+  if constexpr (L <= N) LoadShellP<V, N, P, L * L, (L + 1) * (L + 1)>::run(sr, dr, sp, dp, ms);
 }
 
-// Outputs in shell order a = l^2 + l + m. Output shell l reads input
-// shells l - 1 and l + 1 only, so input shell l + 1 is loaded when output
-// shell l starts (before output shell l + 1 overwrites it in place); at most
-// three shells are live in registers.
-template <typename V, typename T, int N, int A>
-struct Rows {
-  static __device__ __forceinline__ void run(V* in, V* out, const V* __restrict__ dcol,
-                                             size_t mstride, T kx, T ky, T sc) {
+// Rows in shell order a = l^2 + l + m. Output shell l reads input shells
+// l - 1 and l + 1 only, so shell l + 1 is loaded when output shell l starts;
+// a row's own D entry was loaded one shell earlier, before the row is
+// written over it. At most three shells are live in registers.
+template <typename V, typename T, int N, int A, int P>
+struct RowsP {
+  static __device__ __forceinline__ void run(V* sr, V* dr, const V* __restrict__ sp, V* dp, size_t ms, T kx,
+                                             T ky, T sc) {
     if constexpr (A < (N + 1) * (N + 1)) {
       constexpr int l = isqrt_c(A);
       if constexpr (A == l * l && l >= 1) {
         // keep the scheduler from hoisting later shells' loads (register pressure)
         __builtin_amdgcn_sched_barrier(0);
-        load_shell<V, l + 1, N>(in, out, mstride);
+        load_shell_p<V, l + 1, N, P>(sr, dr, sp, dp, ms);
       }
-      T acc[6] = {0, 0, 0, 0, 0, 0};
-      RowAcc<V, T, N, A, 0>::run(in, dcol, mstride, acc);
-      const T re = kx * acc[0] + ky * acc[2], im = kx * acc[1] + ky * acc[3];
-      // -i (re + i im) - (dre + i dim)
-      out[A * mstride] = cmk<V>(sc * (im - acc[4]), sc * (-re - acc[5]));
-      Rows<V, T, N, A + 1>::run(in, out, dcol, mstride, kx, ky, sc);
+      if constexpr (m_parity(A) == P) {
+        T acc[6] = {0, 0, 0, 0, 0, 0};
+        RowAccP<V, T, N, A, 0, P>::run(sr, dr, acc);
+        const T re = kx * acc[0] + ky * acc[2], im = kx * acc[1] + ky * acc[3];
+        // -i (re + i im) - (dre + i dim)
+        dp[A * ms] = cmk<V>(sc * (im - acc[4]), sc * (-re - acc[5]));
+      }
+      RowsP<V, T, N, A + 1, P>::run(sr, dr, sp, dp, ms, kx, ky, sc);
     }
   }
 };
 
-// One thread per spectral point of the (z, ky) rows; the moments of a point
-// are strided by n^2 H in the spectrum. Coalesced along kx.
+template <typename V, typename T, int N, int P>
+__device__ __forceinline__ void couple_point(const V* __restrict__ sp, V* dp, size_t ms, T kx, T ky, T sc) {
+  constexpr int M = (N + 1) * (N + 1);
+  V sr[M], dr[M];
+  load_shell_p<V, 0, N, P>(sr, dr, sp, dp, ms);
+  load_shell_p<V, 1, N, P>(sr, dr, sp, dp, ms);
+  RowsP<V, T, N, 0, P>::run(sr, dr, sp, dp, ms, kx, ky, sc);
+}
+
+// Two blocks per kCBlock spectral points of the (z, ky) rows, one per parity
+// class (uniform per wavefront); the moments of a point are strided by
+// n^2 H. Coalesced along kx. W replaces D in dspec.
 template <typename T, int NN, int N>
 __global__ void __launch_bounds__(kCBlock)
-k_couple(typename cplx_of<T>::type* __restrict__ spec, const typename cplx_of<T>::type* __restrict__ dspec,
+k_couple(const typename cplx_of<T>::type* __restrict__ spec, typename cplx_of<T>::type* dspec,
          const T* __restrict__ kv, T sc, const Ctl* __restrict__ ctl, long long bs = 0) {
   using V = typename cplx_of<T>::type;
   constexpr int n = NN, H = NN / 2;
-  constexpr int M = (N + 1) * (N + 1);
   constexpr size_t MS = size_t(n) * n * H;      // moment stride
   spec = slot_ptr(spec, bs);
   dspec = slot_ptr(dspec, bs);
   kv = slot_ptr(kv, bs);
   ctl = slot_ptr(ctl, bs);
   if (ctl->stop) return;
-  const int pt = blockIdx.x * kCBlock + threadIdx.x;   // (z * n + ky) * H + kx
+  const int cls = blockIdx.x & 1;
+  const int pt = (blockIdx.x >> 1) * kCBlock + threadIdx.x;   // (z * n + ky) * H + kx
   if (pt >= n * n * H) return;
-  const int kx = pt % H;
-  const int ky = (pt / H) % n;
-  V in[M];
-  load_shell<V, 0, N>(in, spec + pt, MS);
-  load_shell<V, 1, N>(in, spec + pt, MS);
-  Rows<V, T, N, 0>::run(in, spec + pt, dspec + pt, MS, kv[kx], kv[ky], sc);
+  const T kx = kv[pt % H], ky = kv[(pt / H) % n];
+  if (cls == 0) {
+    couple_point<V, T, N, 0>(spec + pt, dspec + pt, MS, kx, ky, sc);
+  } else if constexpr (parity_rows(N, 1) > 0) {
+    couple_point<V, T, N, 1>(spec + pt, dspec + pt, MS, kx, ky, sc);
+  }
 }
 
 // High orders (more moments than registers hold): one thread per spectral
@@ -1731,10 +1766,10 @@ void enqueue_stage(const StepArgs& a, ProfRec* pr, double hs, double sgn, const 
   }
   launch_pencil<T, NN, PENCIL_ZDERIV>(st, spec, dspec, tw, kv, cctl, M, ns, bs);
   rec(PROF_ZDERIV);
-  V* coupled = spec;   // the inverse passes read the coupled spectrum from here
+  V* coupled = dspec;   // the inverse passes read the coupled spectrum from here
   if constexpr (N <= kDenseOrder) {
-    hipLaunchKernelGGL((k_couple<T, NN, N>), dim3(cblocks, ns), cblk, 0, st, spec, dspec, kv, T(sgn * hs / n2),
-                       cctl, bs);
+    hipLaunchKernelGGL((k_couple<T, NN, N>), dim3(2 * cblocks, ns), cblk, 0, st, spec, dspec, kv,
+                       T(sgn * hs / n2), cctl, bs);
   } else {
     coupled = static_cast<V*>(a.wspec);
     hipLaunchKernelGGL((k_couple_rt<T, NN>), dim3(cblocks), cblk, 0, st, spec, dspec, coupled, kv, a.ctab,
