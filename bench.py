@@ -138,7 +138,10 @@ def serving_bench(a):
     srv.service_times([ri.RequestSpec(-1, 32, 1, 5, 0, 0, 1.0)])
     print(f"[serving] {len(specs)} requests; measuring one-at-a-time service times",
           file=sys.stderr, flush=True)
-    alone = srv.service_times(specs)
+    alone = {}
+    for i in range(0, len(specs), 32):   # in groups, with a progress line after each
+        alone.update(srv.service_times(specs[i:i + 32]))
+        print(f"[serving] {len(alone)}/{len(specs)} measured alone", file=sys.stderr, flush=True)
     svc = np.array([r.finished - r.admitted for r in alone.values()])
     rate = 1.5 / svc.mean()
     arr = serving.poisson_arrivals(specs, rate)
