@@ -337,6 +337,35 @@ k_plane128(const float2* spec, const float* vin, float* u, float* dst, const flo
   const bool t0 = (t == 0);
   const int ja = t, jb = t0 ? 4 : 8 - t;
   float2* row = pl + y * PITCH;
+
+  // epilogue fields: uniform bases (scalar registers) and one 32-bit lane
+  // offset shared by every field (set up before the row FFT: computing them
+  // inside the epilogue made the middle-stage variant spill)
+  constexpr bool kLast = (MODE == EPI_LAST || MODE == EPI_EULER);
+  const int l = isqrt_c(b);
+  constexpr bool kSrc = (MODE == EPI_FIRST || MODE == EPI_MID || MODE == EPI_LAST || MODE == EPI_EULER);
+  const bool hasq = kSrc && (q != nullptr) && qflag[z];
+  const float qs = hasq ? float(source_weight(ctl, stage, step1)) : 0.f;
+  const size_t vbase = size_t(z) * n * n, pbase = size_t(b) * n * n * n + vbase;
+  const float* ub = u + pbase;
+  float* ubw = u + pbase;
+  const float* vb = vin + pbase;
+  float* db = dst + pbase;
+  const float* sb = sig + size_t(l) * n * n * n + vbase;
+  const float* qb = q + pbase;
+  double* pb = phi_int + vbase;
+  const unsigned off = unsigned(y * n + 4 * t) * 4u;   // bytes of a float field
+  auto epi_load = [&](int k, float4& uu, float4& vv, float4& ss, float4& qq) {
+    const unsigned e = off + 64u * unsigned(k);
+    if constexpr (MODE != EPI_SET) {
+      if constexpr (MODE != EPI_APPLY) uu = ld_b<float4>(ub, e);
+      else uu = make_float4(0.f, 0.f, 0.f, 0.f);
+      if constexpr (MODE == EPI_FIRST || MODE == EPI_EULER) vv = uu;
+      else vv = ld_b<float4>(vb, e);
+      ss = ld_b<float4>(sb, e);
+      qq = hasq ? ld_b<float4>(qb, e) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  };
   float2 a[8], bq[8];
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
@@ -372,22 +401,6 @@ k_plane128(const float2* spec, const float* vin, float* u, float* dst, const flo
   // ---- epilogue: element 2t + 8k holds reals x = 4t + 16k, 4t + 16k + 1
   double acc_d = 0.0, acc_o = 0.0;
   {
-    constexpr bool kLast = (MODE == EPI_LAST || MODE == EPI_EULER);
-    const int l = isqrt_c(b);
-    constexpr bool kSrc = (MODE == EPI_FIRST || MODE == EPI_MID || MODE == EPI_LAST || MODE == EPI_EULER);
-    const bool hasq = kSrc && (q != nullptr) && qflag[z];
-    const float qs = hasq ? float(source_weight(ctl, stage, step1)) : 0.f;
-    // uniform bases (scalar registers) and one 32-bit lane offset shared by
-    // every field
-    const size_t vbase = size_t(z) * n * n, pbase = size_t(b) * n * n * n + vbase;
-    const float* ub = u + pbase;
-    float* ubw = u + pbase;
-    const float* vb = vin + pbase;
-    float* db = dst + pbase;
-    const float* sb = sig + size_t(l) * n * n * n + vbase;
-    const float* qb = q + pbase;
-    double* pb = phi_int + vbase;
-    const unsigned off = unsigned(y * n + 4 * t) * 4u;   // bytes of a float field
     const bool fl = kLast && b == 0;
 #pragma unroll
     for (int half = 0; half < 8 / kEpiBatch; ++half) {
@@ -397,15 +410,7 @@ k_plane128(const float2* spec, const float* vin, float* u, float* dst, const flo
       float4 uu[kEpiBatch], vv[kEpiBatch], ss[kEpiBatch], qq[kEpiBatch];
 #pragma unroll
       for (int i = 0; i < kEpiBatch; ++i) {
-        const unsigned e = off + 64u * unsigned(kEpiBatch * half + i);
-        if constexpr (MODE != EPI_SET) {
-          if constexpr (MODE != EPI_APPLY) uu[i] = ld_b<float4>(ub, e);
-          else uu[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-          if constexpr (MODE == EPI_FIRST || MODE == EPI_EULER) vv[i] = uu[i];
-          else vv[i] = ld_b<float4>(vb, e);
-          ss[i] = ld_b<float4>(sb, e);
-          qq[i] = hasq ? ld_b<float4>(qb, e) : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
+        epi_load(kEpiBatch * half + i, uu[i], vv[i], ss[i], qq[i]);
       }
 #pragma unroll
       for (int i = 0; i < kEpiBatch; ++i) {
