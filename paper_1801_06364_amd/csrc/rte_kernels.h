@@ -976,29 +976,77 @@ k_growth_limit(const T* __restrict__ u, int M, long long V, double source_term, 
 constexpr int kDotBlocks = 1024;
 constexpr int kMaxBasis = 32;
 
+// 16-byte vectors of the working precision (4 floats or 2 doubles): the
+// vector kernels stream every field with one 16-byte access per lane.
+template <typename T> struct Vec16;
+template <> struct Vec16<float> {
+  using type = float4;
+  static constexpr int W = 4;
+  static __device__ __forceinline__ double get(const float4& v, int k) {
+    return double(k == 0 ? v.x : k == 1 ? v.y : k == 2 ? v.z : v.w);
+  }
+  static __device__ __forceinline__ void set(float4& v, int k, double x) {
+    const float f = float(x);
+    if (k == 0) v.x = f;
+    else if (k == 1) v.y = f;
+    else if (k == 2) v.z = f;
+    else v.w = f;
+  }
+};
+template <> struct Vec16<double> {
+  using type = double2;
+  static constexpr int W = 2;
+  static __device__ __forceinline__ double get(const double2& v, int k) { return k == 0 ? v.x : v.y; }
+  static __device__ __forceinline__ void set(double2& v, int k, double x) {
+    if (k == 0) v.x = x;
+    else v.y = x;
+  }
+};
+constexpr int kVecGroup = 8;   // basis vectors whose loads are in flight together
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_wdots(const T* __restrict__ basis, long long stride, int count, const T* __restrict__ w, int M,
         long long n3, double* __restrict__ partial, const Ctl* __restrict__ ctl) {
+  using VT = Vec16<T>;
+  using V = typename VT::type;
+  constexpr int W = VT::W;
   __shared__ double red[kBlock];
   if (ctl->stop) return;
   double acc[kMaxBasis];
 #pragma unroll
   for (int i = 0; i < kMaxBasis; ++i) acc[i] = 0.0;
   const long long step = (long long)gridDim.x * kBlock;
+  const long long nv = n3 / W;   // n3 is a multiple of 4 (even grid sizes)
   for (int a = 0; a < M; ++a) {
     const double wt = double(2 * isqrt_c(a) + 1);
-    const long long base = (long long)a * n3;
-    for (long long r = (long long)blockIdx.x * kBlock + threadIdx.x; r < n3; r += step) {
-      const double we = wt * double(w[base + r]);
+    const V* wa = reinterpret_cast<const V*>(w + (long long)a * n3);
+    for (long long r = (long long)blockIdx.x * kBlock + threadIdx.x; r < nv; r += step) {
+      const V wv = wa[r];
+      double we[W];
 #pragma unroll
-      for (int i = 0; i < kMaxBasis; ++i)
-        if (i < count) acc[i] += we * double(basis[i * stride + base + r]);
+      for (int k = 0; k < W; ++k) we[k] = wt * VT::get(wv, k);
+#pragma unroll
+      for (int g = 0; g < kMaxBasis; g += kVecGroup) {
+        if (g < count) {   // count is uniform over the grid
+          V bv[kVecGroup];
+#pragma unroll
+          for (int i = 0; i < kVecGroup; ++i)
+            if (g + i < count) bv[i] = reinterpret_cast<const V*>(basis + (g + i) * stride + (long long)a * n3)[r];
+#pragma unroll
+          for (int i = 0; i < kVecGroup; ++i)
+            if (g + i < count) {
+              // elements in index order, as the scalar loop summed them
+#pragma unroll
+              for (int k = 0; k < W; ++k) acc[g + i] += we[k] * VT::get(bv[i], k);
+            }
+        }
+      }
     }
   }
 #pragma unroll
   for (int i = 0; i < kMaxBasis; ++i) {
-    if (i < count) {   // count is uniform over the grid
+    if (i < count) {
       red[threadIdx.x] = acc[i];
       __syncthreads();
       for (int s = kBlock / 2; s > 0; s >>= 1) {
@@ -1011,27 +1059,64 @@ k_wdots(const T* __restrict__ basis, long long stride, int count, const T* __res
   }
 }
 
+// One workgroup per basis vector i: each thread adds the partials of blocks
+// t, t + kBlock, ... in order, then a fixed tree (deterministic).
 template <typename T>   // instantiated per working precision (one copy per translation unit)
 __global__ void __launch_bounds__(kBlock)
 k_cols_sum(const double* __restrict__ partial, int nblocks, int count, double* __restrict__ out,
            const Ctl* __restrict__ ctl) {
-  const int i = threadIdx.x;
+  __shared__ double red[kBlock];
+  const int i = blockIdx.x;
   if (ctl->stop || i >= count) return;
   double s = 0.0;
-  for (int b = 0; b < nblocks; ++b) s += partial[(long long)b * kMaxBasis + i];
-  out[i] = s;
+  for (int b = threadIdx.x; b < nblocks; b += kBlock) s += partial[(long long)b * kMaxBasis + i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[i] = red[0];
 }
 
 // w <- sgn * w + sum_i coef[i] * basis_i  (coef on the device)
+// (len is a multiple of 4; per element the same operations in the same
+// order as a scalar loop, so the result does not depend on the vector width)
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_combine(T* __restrict__ w, double sgn, const T* __restrict__ basis, long long stride, int count,
           const double* __restrict__ coef, double cscale, long long len, const Ctl* __restrict__ ctl) {
+  using VT = Vec16<T>;
+  using V = typename VT::type;
+  constexpr int W = VT::W;
   if (ctl->stop) return;
-  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < len; e += (long long)gridDim.x * kBlock) {
-    double x = sgn * double(w[e]);
-    for (int i = 0; i < count; ++i) x += cscale * coef[i] * double(basis[i * stride + e]);
-    w[e] = T(x);
+  V* wv = reinterpret_cast<V*>(w);
+  const long long nv = len / W;
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < nv; e += (long long)gridDim.x * kBlock) {
+    const V w0 = wv[e];
+    double x[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) x[k] = sgn * VT::get(w0, k);
+#pragma unroll
+    for (int g = 0; g < kMaxBasis; g += kVecGroup) {
+      if (g < count) {
+        V bv[kVecGroup];
+#pragma unroll
+        for (int i = 0; i < kVecGroup; ++i)
+          if (g + i < count) bv[i] = reinterpret_cast<const V*>(basis + (g + i) * stride)[e];
+#pragma unroll
+        for (int i = 0; i < kVecGroup; ++i)
+          if (g + i < count) {
+            const double c = cscale * coef[g + i];
+#pragma unroll
+            for (int k = 0; k < W; ++k) x[k] += c * VT::get(bv[i], k);
+          }
+      }
+    }
+    V o;
+#pragma unroll
+    for (int k = 0; k < W; ++k) VT::set(o, k, x[k]);
+    wv[e] = o;
   }
 }
 
@@ -1040,10 +1125,20 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_scale_by(T* __restrict__ dst, const T* __restrict__ src, const double* __restrict__ s, long long len,
            const Ctl* __restrict__ ctl) {
+  using VT = Vec16<T>;
+  using V = typename VT::type;
+  constexpr int W = VT::W;
   if (ctl->stop) return;
   const double inv = 1.0 / s[0];
-  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < len; e += (long long)gridDim.x * kBlock)
-    dst[e] = T(double(src[e]) * inv);
+  const V* sv = reinterpret_cast<const V*>(src);
+  V* dv = reinterpret_cast<V*>(dst);
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < len / W; e += (long long)gridDim.x * kBlock) {
+    const V x = sv[e];
+    V o;
+#pragma unroll
+    for (int k = 0; k < W; ++k) VT::set(o, k, VT::get(x, k) * inv);
+    dv[e] = o;
+  }
 }
 
 // dst = b - dst (b may be null: zero right-hand side)
@@ -1985,8 +2080,8 @@ hipError_t enqueue_t(const StepArgs& a, const OpArgs& op, ProfRec* pr) {
       const long long len = (long long)M * nvox;
       hipLaunchKernelGGL((k_wdots<T>), dim3(kDotBlocks), dim3(kBlock), 0, st, static_cast<const T*>(op.x),
                          len, op.count, static_cast<const T*>(op.y), M, nvox, op.gmua, cctl);
-      hipLaunchKernelGGL((k_cols_sum<T>), dim3(1), dim3(kBlock), 0, st, op.gmua, kDotBlocks, op.count, op.gmus,
-                         cctl);
+      hipLaunchKernelGGL((k_cols_sum<T>), dim3(kMaxBasis), dim3(kBlock), 0, st, op.gmua, kDotBlocks, op.count,
+                         op.gmus, cctl);
       break;
     }
     case OP_COMBINE: {
