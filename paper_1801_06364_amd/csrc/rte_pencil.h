@@ -26,8 +26,9 @@ namespace pen {
 #define RTE_PEN_TZ256 16
 #endif
 
-// TZ columns per workgroup; J threads per column (the radix of the first
-// stage's butterflies); LDS holds the whole n x TZ tile.
+// TZ columns per workgroup; J = n / 16 threads per column, one per radix-16
+// butterfly of the first stage; LDS holds the whole n x TZ tile. TZ = 8 and
+// 32 measured no faster than 16 at either size.
 template <int NN> struct Shape;
 template <> struct Shape<128> {
   static constexpr int TZ = RTE_PEN_TZ128, NTILE = 64 / TZ, J = 8, THREADS = J * TZ;
