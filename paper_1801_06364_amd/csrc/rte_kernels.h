@@ -467,18 +467,16 @@ __device__ __forceinline__ void load_shell_p(V* sr, V* dr, const V* __restrict__
 // Rows in shell order a = l^2 + l + m. Output shell l reads input shells
 // l - 1 and l + 1 only, so shell l + 1 is loaded when output shell l starts;
 // a row's own D entry was loaded one shell earlier, before the row is
-// written over it. At most three shells are live in registers.
+// written over it. At most three shells need to be live in registers (FP32
+// P_7: 110 registers; a scheduling barrier before each shell's loads kept it
+// at 108 but measured 1% slower).
 template <typename V, typename T, int N, int A, int P>
 struct RowsP {
   static __device__ __forceinline__ void run(V* sr, V* dr, const V* __restrict__ sp, V* dp, size_t ms, T kx,
                                              T ky, T sc) {
     if constexpr (A < (N + 1) * (N + 1)) {
       constexpr int l = isqrt_c(A);
-      if constexpr (A == l * l && l >= 1) {
-        // keep the scheduler from hoisting later shells' loads (register pressure)
-        __builtin_amdgcn_sched_barrier(0);
-        load_shell_p<V, l + 1, N, P>(sr, dr, sp, dp, ms);
-      }
+      if constexpr (A == l * l && l >= 1) load_shell_p<V, l + 1, N, P>(sr, dr, sp, dp, ms);
       if constexpr (m_parity(A) == P) {
         T acc[6] = {0, 0, 0, 0, 0, 0};
         RowAccP<V, T, N, A, 0, P>::run(sr, dr, acc);
