@@ -69,6 +69,30 @@ def test_real_basis_tables_match_oracle(N):
         assert np.abs(mine - ref).max() < 1e-14
 
 
+@pytest.mark.parametrize("N", [1, 3, 5, 7, 21])
+def test_streaming_parity_structure_of_real_tables(N):
+    """The coupling pass splits each spectral point's rows by the parity of
+    |m|: it relies on Bx and By joining only orders of opposite |m| parity
+    and Bz only equal orders, and on every coupling changing the degree by
+    one. Checked on the oracle's tables (eq. 6 rotated by its own unitary),
+    independently of the library's."""
+    U = pn.real_basis_transform(N)
+    bx, by, bz = ((U.conj() @ B @ U.T).real for B in pn.coupling_matrices(N))
+    M = (N + 1) ** 2
+    l_of = np.array([int(np.floor(np.sqrt(a))) for a in range(M)])
+    m_of = np.arange(M) - l_of ** 2 - l_of
+    par = np.abs(m_of) % 2
+    for B, same in ((bx, False), (by, False), (bz, True)):
+        nz = np.argwhere(np.abs(B) > 1e-12)
+        assert len(nz) > 0
+        for a, b in nz:
+            assert abs(l_of[a] - l_of[b]) == 1
+            assert (par[a] == par[b]) == same
+    # Bz keeps the order m itself (not only its parity)
+    for a, b in np.argwhere(np.abs(bz) > 1e-12):
+        assert m_of[a] == m_of[b]
+
+
 def test_compile_time_coefficients_match_host_tables(tmp_path):
     """The streaming coefficients the exact-propagation kernel carries as
     compile-time constants equal the host tables (N = 0..7), built and run
