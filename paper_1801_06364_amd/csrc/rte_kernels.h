@@ -1338,10 +1338,9 @@ k_expo(typename cplx_of<T>::type* __restrict__ spec, const typename cplx_of<T>::
 // size N + 1 - |m| (degrees |m|..N). The block exponentials depend on |k|
 // only, i.e. on the integer f^2 = fx^2 + fy^2 + fz^2 of the grid frequencies:
 // k_expo_table builds, for every f^2 and m, E_m = exp(T M_z) and
-// Phi_m = int_0^T exp(s M_z) ds c (column by column, truncated Taylor series
-// with the same bounded remainder as k_expo), and k_expo_rot rotates each
-// point's moments and source to the k = z frame, applies the blocks and
-// rotates back. D(R) = X^T Rz(-theta) X Rz(-phi): Rz rotates the (m, -m)
+// Phi_m = int_0^T exp(s M_z) ds c (whole blocks, by scaling and squaring),
+// k_expo_frame rotates each point's moments and source to the k = z frame
+// and back, and k_expo_blocks applies the blocks in that frame. D(R) = X^T Rz(-theta) X Rz(-phi): Rz rotates the (m, -m)
 // pairs by m times the angle, X (rotation by 90 degrees about x, y -> z) is
 // a constant per-degree matrix computed once on the host.
 
@@ -1357,11 +1356,6 @@ constexpr int expo_block_offset(int N, int m) {
   return o;
 }
 constexpr int expo_row_size(int N) { return expo_block_offset(N, N + 1); }
-constexpr int expo_row_columns(int N) {   // sum over m >= 0 of 2 d
-  int c = 0;
-  for (int m = 0; m <= N; ++m) c += 2 * expo_block(N, m);
-  return c;
-}
 constexpr int xrot_size(int N) {
   int o = 0;
   for (int l = 0; l <= N; ++l) o += (2 * l + 1) * (2 * l + 1);
@@ -1374,94 +1368,96 @@ constexpr int expo_table_offset(int N) {
   return o + (o & 1);
 }
 
-// One thread per (f^2, m, column): column j < d of E_m, or column j - d of
-// Phi_m, as the result of propagating the unit vector (with a unit source in
-// the Phi case) over time T. bz[2a], bz[2a+1]: B_z couplings of row a to
-// (l-1, m) and (l+1, m).
+// Block exponentials by scaling and squaring, one wavefront per (f^2, m)
+// block, in FP64 for both working precisions (the FP64 vector rate equals
+// the unpacked FP32 rate). Lane (i, j) = (lane / d, lane % d) of the d x d
+// block (d = N + 1 - m <= 8: at most 64 lanes) holds E_ij = exp(h A)_ij and
+// P_ij = (int_0^h exp(s A) ds)_ij, A = -i |k| B_z - Sigma on the degrees
+// m..N (per unit c: h runs up to c T). With h0 = c T / 2^q, q the fewest
+// halvings that bring nu = c T (|k| + max Sigma), a bound on ||c T A||,
+// to 1/2 or below, a Taylor series of kExpoTerms terms gives E and P at h0
+// (truncation below 2^-53); q doublings
+//   P <- P + E P,   E <- E E
+// give them at c T. exp(t A) is a contraction (A + A^H = -2 Sigma <= 0), so
+// a doubling at most doubles the error it inherits. bz[2a], bz[2a+1]: B_z
+// couplings of row a to (l-1, m) and (l+1, m).
+constexpr int kExpoTableWaves = 4;   // blocks (wavefronts) per workgroup
+constexpr int kExpoTerms = 14;       // 0.5^15 / 15! < 2^-53
+
+__host__ __device__ constexpr int expo_halvings(double nu) {
+  int q = 0;
+  for (double x = nu; x > 0.5; x *= 0.5) ++q;
+  return q;
+}
+
 template <typename T, int N>
-__global__ void __launch_bounds__(kEBlock)
+__global__ void __launch_bounds__(64 * kExpoTableWaves)
 k_expo_table(typename cplx_of<T>::type* __restrict__ tab, const T* __restrict__ bz, ExpoParams<T> p,
              double kunit, int nf2) {
   using V = typename cplx_of<T>::type;
-  constexpr int M = (N + 1) * (N + 1);
-  constexpr int D = N + 1;
-  constexpr int JMAX = TaylorMax<T>::value;
-  constexpr int C = expo_row_columns(N);
-  const long long gid = (long long)blockIdx.x * kEBlock + threadIdx.x;
-  if (gid >= (long long)nf2 * C) return;
-  const int f2 = int(gid / C);
-  int col = int(gid - (long long)f2 * C);
-  int m = 0;
-  while (col >= 2 * expo_block(N, m)) {
-    col -= 2 * expo_block(N, m);
-    ++m;
+  __shared__ double2 sE[kExpoTableWaves][64], sP[kExpoTableWaves][64];
+  const int wv = int(threadIdx.x) >> 6, ln = int(threadIdx.x) & 63;
+  const long long blk = (long long)blockIdx.x * kExpoTableWaves + wv;   // uniform per wavefront
+  if (blk >= (long long)nf2 * (N + 1)) return;
+  const int f2 = int(blk / (N + 1)), m = int(blk - (long long)f2 * (N + 1));
+  const int d = N + 1 - m;
+  const int i = ln / d, j = ln - i * d;
+  const bool act = ln < d * d;
+  const double kk = kunit * sqrt(double(f2));
+  const int q = expo_halvings(p.ct * (kk + p.sigmax));
+  const double h0 = ldexp(p.ct, -q);
+  double lo = 0.0, hi = 0.0, sg = 0.0;
+  if (act) {
+    const int l = m + i, a = l * l + l + m;
+    if (i > 0) lo = double(bz[2 * a]);
+    if (i + 1 < d) hi = double(bz[2 * a + 1]);
+    sg = double(p.sig[l]);
   }
-  const int am = m < 0 ? -m : m;
-  const int d = N + 1 - am;
-  const bool phi = col >= d;
-  const int j = phi ? col - d : col;
-  const double kk = kunit * std::sqrt(double(f2));
-  const double nu = p.ct * (kk + p.sigmax);
-  const int s = nu > p.theta ? int(std::ceil(nu / p.theta)) : 1;
-  const double nus = nu / s;
-  int J = 1;
-  double bound = 0.5 * nus * nus * std::exp(nus);
-  while (bound > p.eps && J < JMAX) {
-    ++J;
-    bound *= nus / (J + 1);
+  // neighbours (i -+ 1, j); a row without one has a zero coupling to it
+  const int up = (act && i > 0) ? ln - d : ln, dn = (act && i + 1 < d) ? ln + d : ln;
+  // Taylor terms X_t = (h0 A)^t / t! from X_0 = I
+  double xr = (act && i == j) ? 1.0 : 0.0, xi = 0.0;
+  double er = xr, ei = 0.0, pr = h0 * xr, pi = 0.0;
+  for (int t = 1; t <= kExpoTerms; ++t) {
+    const double ur = __shfl(xr, up), ui = __shfl(xi, up);
+    const double vr = __shfl(xr, dn), vi = __shfl(xi, dn);
+    const double re = lo * ur + hi * vr, im = lo * ui + hi * vi;
+    // A x = -i |k| (re + i im) - Sigma x
+    const double st = h0 / double(t);
+    const double nr = st * (kk * im - sg * xr), ni = st * (-kk * re - sg * xi);
+    xr = nr;
+    xi = ni;
+    er += xr;
+    ei += xi;
+    const double w = h0 / double(t + 1);
+    pr += w * xr;
+    pi += w * xi;
   }
-  const T h = T(p.ct / s), k = T(kk);
-  // rows i = l - |m|; coupling of row i to rows i -+ 1
-  T lo[D], hi[D], sg[D];
-#pragma unroll
-  for (int i = 0; i < D; ++i) {
-    const int l = am + i;
-    const int a = l * l + l + m;
-    lo[i] = i < d ? bz[2 * a] : T(0);
-    hi[i] = i + 1 < d ? bz[2 * a + 1] : T(0);
-    sg[i] = i < d ? p.sig[l] : T(0);
-  }
-  V x[D], t[D];
-#pragma unroll
-  for (int i = 0; i < D; ++i) x[i] = cmk<V>(T(!phi && i == j ? 1 : 0), T(0));
-  for (int sub = 0; sub < s; ++sub) {
-#pragma unroll
-    for (int i = 0; i < D; ++i) t[i] = x[i];
-    for (int jj = 1; jj <= J; ++jj) {
-      const T hj = h / T(jj);
-      V nt[D];
-#pragma unroll
-      for (int i = 0; i < D; ++i) {
-        // (M t / c)_i = -i |k| (lo t_{i-1} + hi t_{i+1}) - sigma t_i
-        T re = T(0), im = T(0);
-        if (i > 0) {
-          re += lo[i] * t[i - 1].x;
-          im += lo[i] * t[i - 1].y;
-        }
-        if (i + 1 < D) {
-          re += hi[i] * t[i + 1].x;
-          im += hi[i] * t[i + 1].y;
-        }
-        T ox = k * im - sg[i] * t[i].x;
-        T oy = -k * re - sg[i] * t[i].y;
-        if (phi && jj == 1 && i == j) ox += T(1);   // unit source in the first term
-        nt[i] = cmk<V>(hj * ox, hj * oy);
-      }
-#pragma unroll
-      for (int i = 0; i < D; ++i) {
-        t[i] = nt[i];
-        x[i] = cmk<V>(x[i].x + nt[i].x, x[i].y + nt[i].y);
+  for (int r = 0; r < q; ++r) {
+    sE[wv][ln] = make_double2(er, ei);
+    sP[wv][ln] = make_double2(pr, pi);
+    wave_sync();
+    double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
+    if (act) {
+      for (int k = 0; k < d; ++k) {
+        const double2 eik = sE[wv][i * d + k], ekj = sE[wv][k * d + j], pkj = sP[wv][k * d + j];
+        ar += eik.x * ekj.x - eik.y * ekj.y;
+        ai += eik.x * ekj.y + eik.y * ekj.x;
+        br += eik.x * pkj.x - eik.y * pkj.y;
+        bi += eik.x * pkj.y + eik.y * pkj.x;
       }
     }
+    wave_sync();   // every lane has read the block before the next writes
+    pr += br;
+    pi += bi;
+    er = ar;
+    ei = ai;
   }
-  V* out = tab + (size_t)f2 * expo_row_size(N);
-  // block of order m (m is a run-time value here)
-  int off = 0;
-  for (int mm = 0; mm < m; ++mm) off += 2 * expo_block(N, mm) * expo_block(N, mm);
-  out += off + (phi ? d * d : 0);
-#pragma unroll
-  for (int i = 0; i < D; ++i)
-    if (i < d) out[i * d + j] = x[i];
+  if (act) {
+    V* out = tab + (size_t)f2 * expo_row_size(N) + expo_block_offset(N, m);
+    out[i * d + j] = cmk<V>(T(er), T(ei));
+    out[d * d + i * d + j] = cmk<V>(T(pr), T(pi));
+  }
 }
 
 // Rotation of one degree shell L (2L+1 moments in registers): z-rotation
@@ -1492,6 +1488,9 @@ __device__ __forceinline__ void shell_rot_x(V* v, const T* xs) {
       im += c * v[j].y;
     }
     w[i] = cmk<V>(re, im);
+    // one row's matrix entries at a time (the scheduler would otherwise
+    // load the whole (2L+1)^2 block ahead and run out of registers)
+    __builtin_amdgcn_sched_barrier(0);
   }
 #pragma unroll
   for (int i = 0; i < d; ++i) v[i] = w[i];
@@ -1526,10 +1525,10 @@ __device__ __forceinline__ void k_angles(T kx, T ky, T kz, T* cp, T* sp, T* ct, 
 // Shells L..N of one point: to the k = z frame, D(R) = X^T Rz(-theta) X
 // Rz(-phi) (BACK: D(R)^T = Rz(phi) X^T Rz(theta) X), scaled by sc; one shell
 // in registers at a time.
-template <typename V, typename T, int N, bool BACK, int L = 0>
+template <typename V, typename T, int N, bool BACK, int L = 0, int LAST = N>
 __device__ __forceinline__ void frame_shells(V* v, size_t ms, const T* xs, const T* cp, const T* sp,
                                              const T* ct, const T* st, T sc) {
-  if constexpr (L <= N) {
+  if constexpr (L <= LAST) {
     constexpr int d = 2 * L + 1, a0 = L * L;
     V w[d];
 #pragma unroll
@@ -1557,12 +1556,26 @@ __device__ __forceinline__ void frame_shells(V* v, size_t ms, const T* xs, const
     }
 #pragma unroll
     for (int i = 0; i < d; ++i) v[(a0 + i) * ms] = w[i];
-    frame_shells<V, T, N, BACK, L + 1>(v, ms, xs, cp, sp, ct, st, sc);
+    frame_shells<V, T, N, BACK, L + 1, LAST>(v, ms, xs, cp, sp, ct, st, sc);
+  }
+}
+
+// Shell L (= blockIdx.y, uniform per workgroup) of every point.
+template <typename V, typename T, int N, bool BACK, int L = 0>
+__device__ __forceinline__ void frame_shell_of(int sh, V* v, size_t ms, const T* xs, const T* cp, const T* sp,
+                                               const T* ct, const T* st, T sc) {
+  if constexpr (L <= N) {
+    if (sh == L) frame_shells<V, T, N, BACK, L, L>(v, ms, xs, cp, sp, ct, st, sc);
+    else frame_shell_of<V, T, N, BACK, L + 1>(sh, v, ms, xs, cp, sp, ct, st, sc);
   }
 }
 
 // Every point's moments (scaled by sc) to (BACK: from) its k = z frame, in
-// place in the full spectrum [b][kz][ky][kx].
+// place in the full spectrum [b][kz][ky][kx]. The rotation is block
+// diagonal by degree, so the grid's second dimension runs over the degree
+// shells: a thread holds one shell of one point (at most 2N + 1 values),
+// which keeps the registers per thread low enough for the waves the
+// streaming access needs.
 template <typename T, int NN, int N, bool BACK>
 __global__ void __launch_bounds__(kEBlock)
 k_expo_frame(typename cplx_of<T>::type* __restrict__ v, const T* __restrict__ kv, const T* __restrict__ xrot,
@@ -1579,15 +1592,15 @@ k_expo_frame(typename cplx_of<T>::type* __restrict__ v, const T* __restrict__ kv
   const int xi = pt % H, yi = (pt / H) % n, zi = pt / (n * H);
   T cp[N + 1], sp[N + 1], ct[N + 1], st[N + 1];
   k_angles<T, N>(kv[xi], kv[yi], kv[zi], cp, sp, ct, st);
-  frame_shells<V, T, N, BACK>(v + pt, MS, xs, cp, sp, ct, st, sc);
+  frame_shell_of<V, T, N, BACK>(int(blockIdx.y), v + pt, MS, xs, cp, sp, ct, st, sc);
 }
 
 // a <- E_m a + Phi_m q on the degrees m..N of orders m and -m (same
 // blocks), for m = MM..N, with a and q (both in the k = z frame) read from
 // and a written to the spectrum
-template <typename V, typename T, int N, int MM = 0>
+template <typename V, typename T, int N, int MM = 0, int LAST = N>
 __device__ __forceinline__ void expo_blocks(V* a, const V* q, size_t ms, const V* row) {
-  if constexpr (MM <= N) {
+  if constexpr (MM <= LAST) {
     constexpr int d = N + 1 - MM;
     constexpr int NS = MM == 0 ? 1 : 2;   // the orders m and -m
     const V* E = row + expo_block_offset(N, MM);
@@ -1602,8 +1615,10 @@ __device__ __forceinline__ void expo_blocks(V* a, const V* q, size_t ms, const V
         x[sgn][j] = a[bj * ms];
         y[sgn][j] = q ? q[bj * ms] : cmk<V>(T(0), T(0));
       }
-    V w[NS][d];
-#pragma unroll
+    // rows one at a time (a run-time loop: unrolled, the compiler would load
+    // all 2 d^2 table entries at once), each written as soon as it is formed
+    // (the block's inputs are all in registers by then)
+#pragma unroll 1
     for (int i = 0; i < d; ++i) {
       T re[NS], im[NS];
 #pragma unroll
@@ -1618,17 +1633,20 @@ __device__ __forceinline__ void expo_blocks(V* a, const V* q, size_t ms, const V
           im[sgn] += e.x * x[sgn][j].y + e.y * x[sgn][j].x + f.x * y[sgn][j].y + f.y * y[sgn][j].x;
         }
       }
+      const int l = MM + i;
 #pragma unroll
-      for (int sgn = 0; sgn < NS; ++sgn) w[sgn][i] = cmk<V>(re[sgn], im[sgn]);
+      for (int sgn = 0; sgn < NS; ++sgn) a[(l * l + l + (sgn ? -MM : MM)) * ms] = cmk<V>(re[sgn], im[sgn]);
     }
-#pragma unroll
-    for (int sgn = 0; sgn < NS; ++sgn)
-#pragma unroll
-      for (int i = 0; i < d; ++i) {
-        const int m = sgn ? -MM : MM;
-        a[((MM + i) * (MM + i) + (MM + i) + m) * ms] = w[sgn][i];
-      }
-    expo_blocks<V, T, N, MM + 1>(a, q, ms, row);
+    expo_blocks<V, T, N, MM + 1, LAST>(a, q, ms, row);
+  }
+}
+
+// Order m (= blockIdx.y, uniform per workgroup) of one point.
+template <typename V, typename T, int N, int MM = 0>
+__device__ __forceinline__ void expo_block_of(int m, V* a, const V* q, size_t ms, const V* row) {
+  if constexpr (MM <= N) {
+    if (m == MM) expo_blocks<V, T, N, MM, MM>(a, q, ms, row);
+    else expo_block_of<V, T, N, MM + 1>(m, a, q, ms, row);
   }
 }
 
@@ -1699,7 +1717,10 @@ k_expo_blocks(typename cplx_of<T>::type* __restrict__ spec, const typename cplx_
   auto freq = [](int i) { return i < n / 2 ? i : (i == n / 2 ? 0 : i - n); };
   const int fy = freq(yi), fz = freq(zi);
   const int f2 = xi * xi + fy * fy + fz * fz;
-  expo_blocks<V, T, N>(spec + pt, qs ? qs + pt : nullptr, MS, tab + (size_t)f2 * expo_row_size(N));
+  // the blocks of different orders are independent: one order per grid row
+  // (blockIdx.y), which keeps a thread's registers to one block
+  expo_block_of<V, T, N>(int(blockIdx.y), spec + pt, qs ? qs + pt : nullptr, MS,
+                         tab + (size_t)f2 * expo_row_size(N));
 }
 
 }  // namespace rte
@@ -1957,18 +1978,18 @@ hipError_t enqueue_expo(const StepArgs& a, const OpArgs& op, ProfRec* pr) {
     const T* bz = xrot + xrot_size(N);
     V* tab = reinterpret_cast<V*>(static_cast<T*>(a.v) + expo_table_offset(N));
     const int nf2 = expo_nf2(NN);
-    const long long tthreads = (long long)nf2 * expo_row_columns(N);
-    hipLaunchKernelGGL((k_expo_table<T, N>), dim3(unsigned((tthreads + kEBlock - 1) / kEBlock)), dim3(kEBlock), 0,
-                       st, tab, bz, p, op.kunit, nf2);
+    const long long tblocks = (long long)nf2 * (N + 1);
+    hipLaunchKernelGGL((k_expo_table<T, N>), dim3(unsigned((tblocks + kExpoTableWaves - 1) / kExpoTableWaves)),
+                       dim3(64 * kExpoTableWaves), 0, st, tab, bz, p, op.kunit, nf2);
     rec(PROF_EXPO_TABLE);
     if (q)
-      hipLaunchKernelGGL((k_expo_frame<T, NN, N, false>), dim3(eblocks), dim3(kEBlock), 0, st, dspec, kv, xrot,
+      hipLaunchKernelGGL((k_expo_frame<T, NN, N, false>), dim3(eblocks, N + 1), dim3(kEBlock), 0, st, dspec, kv, xrot,
                          p.inv_n3);
-    hipLaunchKernelGGL((k_expo_frame<T, NN, N, false>), dim3(eblocks), dim3(kEBlock), 0, st, spec, kv, xrot,
+    hipLaunchKernelGGL((k_expo_frame<T, NN, N, false>), dim3(eblocks, N + 1), dim3(kEBlock), 0, st, spec, kv, xrot,
                        p.inv_n3);
-    hipLaunchKernelGGL((k_expo_blocks<T, NN, N>), dim3((ExpoQuad<NN>::THREADS + kEBlock - 1) / kEBlock),
+    hipLaunchKernelGGL((k_expo_blocks<T, NN, N>), dim3((ExpoQuad<NN>::THREADS + kEBlock - 1) / kEBlock, N + 1),
                        dim3(kEBlock), 0, st, spec, q ? dspec : nullptr, tab);
-    hipLaunchKernelGGL((k_expo_frame<T, NN, N, true>), dim3(eblocks), dim3(kEBlock), 0, st, spec, kv, xrot, T(1));
+    hipLaunchKernelGGL((k_expo_frame<T, NN, N, true>), dim3(eblocks, N + 1), dim3(kEBlock), 0, st, spec, kv, xrot, T(1));
   } else {
     hipLaunchKernelGGL((k_expo<T, NN, N>), dim3(eblocks), dim3(kEBlock), 0, st, spec, q ? dspec : nullptr, kv, p);
   }
