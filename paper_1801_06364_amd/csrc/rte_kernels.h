@@ -621,7 +621,7 @@ __device__ __forceinline__ void epilogue(V* pl, int y0, int b, int z, const T* v
   const size_t poff = (size_t(b) * n + z) * n * n + size_t(y0) * n;
   const size_t voff = size_t(z) * n * n + size_t(y0) * n;
   const T* sg = sig + size_t(l) * n * n * n + voff;
-#pragma unroll (kEpiUnroll)
+#pragma unroll kEpiUnroll
   for (int i = threadIdx.x; i < RB * H; i += BLOCK) {
     const int y = i / H, j = i - y * H;
     const int e = y * n + 2 * j;
@@ -1838,7 +1838,6 @@ template <typename T, int NN, int N, int MODE, bool FUSE = false>
 void enqueue_stage(const StepArgs& a, ProfRec* pr, double hs, double sgn, const T* src, T* u, T* out,
                    int stage = 0, long long step1 = 0) {
   using V = typename cplx_of<T>::type;
-  using Z = ZdShape<T, NN>;
   constexpr int M = (N + 1) * (N + 1);
   hipStream_t st = reinterpret_cast<hipStream_t>(a.stream);
   V* spec = static_cast<V*>(a.spec);
