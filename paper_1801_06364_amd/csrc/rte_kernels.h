@@ -525,9 +525,16 @@ k_couple(const typename cplx_of<T>::type* __restrict__ spec, typename cplx_of<T>
 }
 
 // High orders (more moments than registers hold): one thread per spectral
-// point walks the rows at run time with the slot table, reading each input
-// from the spectrum (neighbouring shells stay in L1/L2 across rows) and
-// writing W to a separate buffer, since later rows still need the inputs.
+// point and row slice (blockIdx.y: kRtSlices slices of the M rows, so that
+// the small grids of high orders still give every SIMD several wavefronts)
+// walks its rows with the slot table, reading each input from the spectrum
+// (neighbouring shells stay in the caches across rows) and writing W to a
+// separate buffer, since later rows still need the inputs. All kMaxSlots
+// loads of a row are issued before any is used (a padding slot, code -1,
+// re-reads the row's first input and adds nothing), so a row costs one
+// memory latency instead of one per input.
+constexpr int kRtSlices = 4;
+
 template <typename T, int NN>
 __global__ void __launch_bounds__(kCBlock)
 k_couple_rt(const typename cplx_of<T>::type* __restrict__ spec,
@@ -540,20 +547,38 @@ k_couple_rt(const typename cplx_of<T>::type* __restrict__ spec,
   if (ctl->stop) return;
   const int pt = blockIdx.x * kCBlock + threadIdx.x;   // (z * n + ky) * H + kx
   if (pt >= n * n * H) return;
+  const int a0 = int((long long)M * blockIdx.y / kRtSlices);
+  const int a1 = int((long long)M * (blockIdx.y + 1) / kRtSlices);
   const T kx = kv[pt % H], ky = kv[(pt / H) % n];
-  for (int a = 0; a < M; ++a) {
+  for (int a = a0; a < a1; ++a) {
+    const int* cr = code + size_t(a) * kMaxSlots;
+    const T* vr = val + size_t(a) * kMaxSlots;
+    const int c0 = max(cr[0], 0);   // (moment 0, x) if a row had no slot
+    V x[kMaxSlots];
+    int ax[kMaxSlots];
+    T w[kMaxSlots];
+#pragma unroll
+    for (int k = 0; k < kMaxSlots; ++k) {
+      const int c = cr[k];
+      const int cc = c >= 0 ? c : c0;
+      ax[k] = c >= 0 ? (c & 3) : 3;
+      w[k] = vr[k];
+      x[k] = ((cc & 3) == 2 ? dspec : spec)[size_t(cc >> 2) * MS + pt];
+    }
+    // per-axis weights by selects (no branches, so the weight loads stay
+    // ahead of the input loads)
     T acc[6] = {0, 0, 0, 0, 0, 0};
-    for (int s = 0; s < kMaxSlots; ++s) {
-      const int c = code[a * kMaxSlots + s];
-      if (c < 0) break;
-      const int b = c >> 2, ax = c & 3;
-      const T w = val[a * kMaxSlots + s];
-      const V x = ax == 2 ? dspec[b * MS + pt] : spec[b * MS + pt];
-      acc[2 * ax] += w * x.x;
-      acc[2 * ax + 1] += w * x.y;
+#pragma unroll
+    for (int k = 0; k < kMaxSlots; ++k) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const T wd = ax[k] == d ? w[k] : T(0);
+        acc[2 * d] += wd * x[k].x;
+        acc[2 * d + 1] += wd * x[k].y;
+      }
     }
     const T re = kx * acc[0] + ky * acc[2], im = kx * acc[1] + ky * acc[3];
-    out[a * MS + pt] = cmk<V>(sc * (im - acc[4]), sc * (-re - acc[5]));
+    out[size_t(a) * MS + pt] = cmk<V>(sc * (im - acc[4]), sc * (-re - acc[5]));
   }
 }
 
@@ -1885,7 +1910,7 @@ void enqueue_stage(const StepArgs& a, ProfRec* pr, double hs, double sgn, const 
                        T(sgn * hs / n2), cctl, bs);
   } else {
     coupled = static_cast<V*>(a.wspec);
-    hipLaunchKernelGGL((k_couple_rt<T, NN>), dim3(cblocks), cblk, 0, st, spec, dspec, coupled, kv, a.ctab,
+    hipLaunchKernelGGL((k_couple_rt<T, NN>), dim3(cblocks, kRtSlices), cblk, 0, st, spec, dspec, coupled, kv, a.ctab,
                        static_cast<const T*>(a.cval), M, T(sgn * hs / n2), cctl);
   }
   rec(PROF_COUPLE);

@@ -12,10 +12,10 @@
 // first stage of the inverse transform follow in registers on exactly those
 // outputs, then one more exchange and the inverse's last stage, written
 // straight to HBM. Plans (verified against a direct DFT): 256 = 16 x 16 both
-// ways; 128 = 16 x 8 forward, 8 x 16 inverse; 96 = 24 x 4 both ways (four
-// threads per column, 24 points each, the radix-24 stage as 8 x 3 with
-// constant twiddles). Twiddles between the stages come from an LDS copy of
-// the table exp(-2 pi i t / n).
+// ways; 128 = 16 x 8 forward, 8 x 16 inverse; 96 = 24 x 4 and 64 = 16 x 4
+// both ways (four threads per column, 24 or 16 points each, the radix-24
+// stage as 8 x 3 with constant twiddles). Twiddles between the stages come
+// from an LDS copy of the table exp(-2 pi i t / n).
 #pragma once
 
 namespace rte {
@@ -38,16 +38,19 @@ template <> struct Shape<128> {
 template <> struct Shape<256> {
   static constexpr int TZ = RTE_PEN_TZ256, NTILE = 128 / TZ, J = 16, THREADS = J * TZ;
 };
-// 96: J = 4 threads per column (radix-24 first stage), TZ = 16 of the 48 kx
-// columns per workgroup (one wavefront)
+// 96 and 64: J = 4 threads per column (radix-24 / radix-16 first stage),
+// TZ = 16 kx columns per workgroup (one wavefront)
 template <> struct Shape<96> {
   static constexpr int TZ = 16, NTILE = 48 / TZ, J = 4, THREADS = J * TZ;
+};
+template <> struct Shape<64> {
+  static constexpr int TZ = 16, NTILE = 32 / TZ, J = 4, THREADS = J * TZ;
 };
 
 // FP32 pencils of these grids and modes run here; the others (FP64, the
 // full 3D transforms of the exact propagation) in k_pencil.
 template <typename T, int NN, int MODE> constexpr bool use_reg() {
-  return std::is_same<T, float>::value && (NN == 96 || NN == 128 || NN == 256) &&
+  return std::is_same<T, float>::value && (NN == 64 || NN == 96 || NN == 128 || NN == 256) &&
          (MODE == PENCIL_ZDERIV || (NN == 256 && (MODE == PENCIL_YFWD || MODE == PENCIL_YINV)));
 }
 
@@ -98,6 +101,13 @@ template <int DIR> __device__ __forceinline__ void dft24(float2* x) {
   }
 }
 
+// R-point DFT in registers (natural order in and out) of the four-thread
+// column plans
+template <int R, int DIR> __device__ __forceinline__ void dft_col(float2* x) {
+  if constexpr (R == 24) dft24<DIR>(x);
+  else Bfly<float2, R, DIR>::run(x);
+}
+
 template <int NN, int MODE>
 __global__ void __launch_bounds__(Shape<NN>::THREADS)
 k_pencil_reg(const float2* src, float2* dst,   // may alias (in place)
@@ -112,9 +122,9 @@ k_pencil_reg(const float2* src, float2* dst,   // may alias (in place)
   kv = slot_ptr(kv, bs);
   ctl = slot_ptr(ctl, bs);
   if (ctl->stop) return;
-  // 96: the four 24-row blocks of the tile sit PAD entries apart, so that
+  // 96 / 64: the four row blocks of the tile sit PAD entries apart, so that
   // the four row groups of one wavefront access fall in different banks
-  constexpr int PAD = NN == 96 ? 16 : 0;
+  constexpr int PAD = (NN == 96 || NN == 64) ? 16 : 0;
   __shared__ float2 tw[n];
   __shared__ float2 col[n * TZ + 4 * PAD];
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -127,47 +137,48 @@ k_pencil_reg(const float2* src, float2* dst,   // may alias (in place)
   const float2* s = src + base + kx;
   float2* d = dst + base + kx;
   constexpr float inv_n = 1.0f / float(n);
-  if constexpr (NN == 96) {
-    static_assert(MODE == PENCIL_ZDERIV, "96-point register pencils do the z derivative only");
-    // thread j < 4: stage 1 radix 24 over rows j + 4 r -> Y_j[k1]; stage 2
-    // radix 4 over j for k1 = j + 4 t (t < 6) -> X[k1 + 24 k2], with the
-    // twiddles exp(-2 pi i j k1 / 96) applied after the exchange
-    auto at = [&](int blk, int row) { return (24 * blk + row) * TZ + blk * PAD + kx; };
-    float2 x[24];
+  if constexpr (NN == 96 || NN == 64) {
+    static_assert(MODE == PENCIL_ZDERIV, "96- and 64-point register pencils do the z derivative only");
+    // R = n / 4. Thread j < 4: stage 1 radix R over rows j + 4 r -> Y_j[k1];
+    // stage 2 radix 4 over j for k1 = j + 4 t (t < R / 4) -> X[k1 + R k2],
+    // with the twiddles exp(-2 pi i j k1 / n) applied after the exchange
+    constexpr int R = NN / 4, NT = R / 4;
+    auto at = [&](int blk, int row) { return (R * blk + row) * TZ + blk * PAD + kx; };
+    float2 x[R];
 #pragma unroll
-    for (int r = 0; r < 24; ++r) x[r] = s[size_t(j + 4 * r) * AX];
-    dft24<-1>(x);
+    for (int r = 0; r < R; ++r) x[r] = s[size_t(j + 4 * r) * AX];
+    dft_col<R, -1>(x);
 #pragma unroll
-    for (int k1 = 0; k1 < 24; ++k1) col[at(j, k1)] = x[k1];
+    for (int k1 = 0; k1 < R; ++k1) col[at(j, k1)] = x[k1];
     __syncthreads();
-    float2 y[6][4];
+    float2 y[NT][4];
 #pragma unroll
-    for (int t = 0; t < 6; ++t) {
+    for (int t = 0; t < NT; ++t) {
       const int k1 = j + 4 * t;
 #pragma unroll
       for (int jj = 0; jj < 4; ++jj) y[t][jj] = col[at(jj, k1)];
 #pragma unroll
       for (int jj = 1; jj < 4; ++jj) y[t][jj] = cmul(y[t][jj], tw_dir<-1>(tw[jj * k1]));
-      Bfly<float2, 4, -1>::run(y[t]);   // element k1 + 24 k2
+      Bfly<float2, 4, -1>::run(y[t]);   // element k1 + R k2
 #pragma unroll
-      for (int k2 = 0; k2 < 4; ++k2) y[t][k2] = times_ik(y[t][k2], kv[k1 + 24 * k2] * inv_n);
-      // inverse: radix 4 over k2 -> Z[k1][p], times exp(2 pi i k1 p / 96)
+      for (int k2 = 0; k2 < 4; ++k2) y[t][k2] = times_ik(y[t][k2], kv[k1 + R * k2] * inv_n);
+      // inverse: radix 4 over k2 -> Z[k1][p], times exp(2 pi i k1 p / n)
       Bfly<float2, 4, +1>::run(y[t]);
 #pragma unroll
       for (int p = 1; p < 4; ++p) y[t][p] = cmul(y[t][p], tw_dir<+1>(tw[k1 * p]));
     }
     __syncthreads();
 #pragma unroll
-    for (int t = 0; t < 6; ++t)
+    for (int t = 0; t < NT; ++t)
 #pragma unroll
       for (int p = 0; p < 4; ++p) col[at(p, j + 4 * t)] = y[t][p];
     __syncthreads();
-    // thread p = j: radix 24 over k1 -> output rows p + 4 s
+    // thread p = j: radix R over k1 -> output rows p + 4 s
 #pragma unroll
-    for (int k1 = 0; k1 < 24; ++k1) x[k1] = col[at(j, k1)];
-    dft24<+1>(x);
+    for (int k1 = 0; k1 < R; ++k1) x[k1] = col[at(j, k1)];
+    dft_col<R, +1>(x);
 #pragma unroll
-    for (int q = 0; q < 24; ++q) d[size_t(j + 4 * q) * AX] = x[q];
+    for (int q = 0; q < R; ++q) d[size_t(j + 4 * q) * AX] = x[q];
   } else if constexpr (NN == 256) {
     // j < 16: stage 1 radix 16 over rows j + 16 r, stage 2 radix 16 (butterfly j)
     float2 x[16];
