@@ -831,7 +831,7 @@ def main():
     print(f"[bench] timed {a.steps} steps: {ms:.2f} ms (wall {wall:.3f} s)", file=sys.stderr,
           flush=True)
 
-    upd_step = wl.n ** 3 * wl.M * 4
+    upd_step = wl.n ** 3 * wl.M * (1 if wl.scheme == "euler" else 4)   # stages per step
     value = upd_step * a.steps / (ms / 1e3)
     sbytes = 8 if wl.precision == "f64" else 4
 
