@@ -525,14 +525,17 @@ k_couple(const typename cplx_of<T>::type* __restrict__ spec, typename cplx_of<T>
 }
 
 // High orders (more moments than registers hold): one thread per spectral
-// point and row slice (blockIdx.y: kRtSlices slices of the M rows, so that
-// the small grids of high orders still give every SIMD several wavefronts)
-// walks its rows with the slot table, reading each input from the spectrum
+// point and row slice (blockIdx.y: the order groups |m| = g, g + kRtSlices,
+// ..., so that the small grids of high orders still give every SIMD several
+// wavefronts) walks its rows with the slot table, reading each input from the spectrum
 // (neighbouring shells stay in the caches across rows) and writing W to a
 // separate buffer, since later rows still need the inputs. All kMaxSlots
 // loads of a row are issued before any is used (a padding slot, code -1,
 // re-reads the row's first input and adds nothing), so a row costs one
-// memory latency instead of one per input.
+// memory latency instead of one per input. Rows go by order group, degree
+// ascending, (l, g) then (l, -g): their inputs are the degrees l +- 1 at
+// orders g and g +- 1, so rows l and l + 2 of a group share half of them
+// while they are still in L2 (and (l, +-g) share them in L1).
 constexpr int kRtSlices = 4;
 
 template <typename T, int NN>
@@ -547,10 +550,12 @@ k_couple_rt(const typename cplx_of<T>::type* __restrict__ spec,
   if (ctl->stop) return;
   const int pt = blockIdx.x * kCBlock + threadIdx.x;   // (z * n + ky) * H + kx
   if (pt >= n * n * H) return;
-  const int a0 = int((long long)M * blockIdx.y / kRtSlices);
-  const int a1 = int((long long)M * (blockIdx.y + 1) / kRtSlices);
+  const int N = isqrt_c(M - 1);
   const T kx = kv[pt % H], ky = kv[(pt / H) % n];
-  for (int a = a0; a < a1; ++a) {
+  for (int g = int(blockIdx.y); g <= N; g += kRtSlices)
+  for (int l = g; l <= N; ++l)
+  for (int sg = 0; sg < (g > 0 ? 2 : 1); ++sg) {
+    const int a = l * l + l + (sg ? -g : g);
     const int* cr = code + size_t(a) * kMaxSlots;
     const T* vr = val + size_t(a) * kMaxSlots;
     const int c0 = max(cr[0], 0);   // (moment 0, x) if a row had no slot
