@@ -12,9 +12,9 @@
 // first stage of the inverse transform follow in registers on exactly those
 // outputs, then one more exchange and the inverse's last stage, written
 // straight to HBM. Plans (verified against a direct DFT): 256 = 16 x 16 both
-// ways; 128 = 16 x 8 forward, 8 x 16 inverse; 96 = 24 x 4 and 64 = 16 x 4
-// both ways (four threads per column, 24 or 16 points each, the radix-24
-// stage as 8 x 3 with constant twiddles). Twiddles between the stages come
+// ways; 128 = 16 x 8 forward, 8 x 16 inverse; 96 = 24 x 4, 64 = 16 x 4 and
+// 32 = 8 x 4 both ways (four threads per column, 24, 16 or 8 points each,
+// the radix-24 stage as 8 x 3 with constant twiddles). Twiddles between the stages come
 // from an LDS copy of the table exp(-2 pi i t / n).
 #pragma once
 
@@ -38,7 +38,7 @@ template <> struct Shape<128> {
 template <> struct Shape<256> {
   static constexpr int TZ = RTE_PEN_TZ256, NTILE = 128 / TZ, J = 16, THREADS = J * TZ;
 };
-// 96 and 64: J = 4 threads per column (radix-24 / radix-16 first stage),
+// 96, 64 and 32: J = 4 threads per column (radix-24 / 16 / 8 first stage),
 // TZ = 16 kx columns per workgroup (one wavefront)
 template <> struct Shape<96> {
   static constexpr int TZ = 16, NTILE = 48 / TZ, J = 4, THREADS = J * TZ;
@@ -46,11 +46,14 @@ template <> struct Shape<96> {
 template <> struct Shape<64> {
   static constexpr int TZ = 16, NTILE = 32 / TZ, J = 4, THREADS = J * TZ;
 };
+template <> struct Shape<32> {
+  static constexpr int TZ = 16, NTILE = 16 / TZ, J = 4, THREADS = J * TZ;
+};
 
 // FP32 pencils of these grids and modes run here; the others (FP64, the
 // full 3D transforms of the exact propagation) in k_pencil.
 template <typename T, int NN, int MODE> constexpr bool use_reg() {
-  return std::is_same<T, float>::value && (NN == 64 || NN == 96 || NN == 128 || NN == 256) &&
+  return std::is_same<T, float>::value && (NN == 32 || NN == 64 || NN == 96 || NN == 128 || NN == 256) &&
          (MODE == PENCIL_ZDERIV || (NN == 256 && (MODE == PENCIL_YFWD || MODE == PENCIL_YINV)));
 }
 
@@ -122,9 +125,9 @@ k_pencil_reg(const float2* src, float2* dst,   // may alias (in place)
   kv = slot_ptr(kv, bs);
   ctl = slot_ptr(ctl, bs);
   if (ctl->stop) return;
-  // 96 / 64: the four row blocks of the tile sit PAD entries apart, so that
-  // the four row groups of one wavefront access fall in different banks
-  constexpr int PAD = (NN == 96 || NN == 64) ? 16 : 0;
+  // 96 / 64 / 32: the four row blocks of the tile sit PAD entries apart, so
+  // that the four row groups of one wavefront access fall in different banks
+  constexpr int PAD = (NN == 96 || NN == 64 || NN == 32) ? 16 : 0;
   __shared__ float2 tw[n];
   __shared__ float2 col[n * TZ + 4 * PAD];
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -137,8 +140,8 @@ k_pencil_reg(const float2* src, float2* dst,   // may alias (in place)
   const float2* s = src + base + kx;
   float2* d = dst + base + kx;
   constexpr float inv_n = 1.0f / float(n);
-  if constexpr (NN == 96 || NN == 64) {
-    static_assert(MODE == PENCIL_ZDERIV, "96- and 64-point register pencils do the z derivative only");
+  if constexpr (NN == 96 || NN == 64 || NN == 32) {
+    static_assert(MODE == PENCIL_ZDERIV, "96-, 64- and 32-point register pencils do the z derivative only");
     // R = n / 4. Thread j < 4: stage 1 radix R over rows j + 4 r -> Y_j[k1];
     // stage 2 radix 4 over j for k1 = j + 4 t (t < R / 4) -> X[k1 + R k2],
     // with the twiddles exp(-2 pi i j k1 / n) applied after the exchange
