@@ -527,9 +527,9 @@ k_couple(const typename cplx_of<T>::type* __restrict__ spec, typename cplx_of<T>
 // High orders (more moments than registers hold): one thread per spectral
 // point and row slice (blockIdx.y: the order groups |m| = g, g + kRtSlices,
 // ..., so that the small grids of high orders still give every SIMD several
-// wavefronts) walks its rows with the slot table, reading each input from the spectrum
-// (neighbouring shells stay in the caches across rows) and writing W to a
-// separate buffer, since later rows still need the inputs. All kMaxSlots
+// wavefronts) walks its rows with the slot table, reading each input from
+// the spectrum (neighbouring shells stay in the caches across rows) and
+// writing W to a separate buffer, since later rows still need the inputs. All kMaxSlots
 // loads of a row are issued before any is used (a padding slot, code -1,
 // re-reads the row's first input and adds nothing), so a row costs one
 // memory latency instead of one per input. Rows go by order group, degree

@@ -1,20 +1,22 @@
-// Pencil passes of FP32 128^3 and 256^3 grids with the FFT stages that
-// touch HBM kept in registers.
+// Pencil passes of FP32 grids with the FFT stages that touch HBM kept in
+// registers: the z derivative at 32^3, 64^3, 96^3, 128^3 and 256^3, the y
+// passes of 256^3 grids.
 //
 // A workgroup owns TZ kx columns of one pencil (all n points along the
 // pencil axis, z for the z derivative, y for the y passes of 256^3 grids).
-// Thread (kx, j) loads the 16 points j + (n/16) r of its column straight
-// from HBM (one row segment of TZ complex values per wavefront
-// load) and applies the first radix-16 Stockham stage in registers; one
-// exchange through LDS (row pitch TZ: the 16 lanes of one LDS cycle touch
-// 16 consecutive columns of a row) feeds the last stage, whose outputs are
-// in natural order. For the z derivative the product with i k_z / n and the
-// first stage of the inverse transform follow in registers on exactly those
-// outputs, then one more exchange and the inverse's last stage, written
-// straight to HBM. Plans (verified against a direct DFT): 256 = 16 x 16 both
-// ways; 128 = 16 x 8 forward, 8 x 16 inverse; 96 = 24 x 4, 64 = 16 x 4 and
-// 32 = 8 x 4 both ways (four threads per column, 24, 16 or 8 points each,
-// the radix-24 stage as 8 x 3 with constant twiddles). Twiddles between the stages come
+// At 128 and 256, thread (kx, j) loads the 16 points j + (n/16) r of its
+// column straight from HBM (one row segment of TZ complex values per
+// wavefront load) and applies the first radix-16 Stockham stage in
+// registers; one exchange through LDS (row pitch TZ: the 16 lanes of one LDS
+// cycle touch 16 consecutive columns of a row) feeds the last stage, whose
+// outputs are in natural order. For the z derivative the product with
+// i k_z / n and the first stage of the inverse transform follow in registers
+// on exactly those outputs, then one more exchange and the inverse's last
+// stage, written straight to HBM. At 96, 64 and 32 four threads share a
+// column, each loading the n/4 points j + 4 r. Plans (verified against a
+// direct DFT): 256 = 16 x 16 both ways; 128 = 16 x 8 forward, 8 x 16
+// inverse; 96 = 24 x 4, 64 = 16 x 4 and 32 = 8 x 4 both ways (the radix-24
+// stage as 8 x 3 with constant twiddles). Twiddles between the stages come
 // from an LDS copy of the table exp(-2 pi i t / n).
 #pragma once
 
