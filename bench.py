@@ -47,6 +47,12 @@ def source_sha() -> str:
     return h.hexdigest()
 
 
+def stages_per_step(scheme: str) -> int:
+    """Operator evaluations (stages) per time step: four for RK4, one for
+    the forward-Euler step of eq. (11)."""
+    return 1 if scheme == "euler" else 4
+
+
 def algorithmic_bytes(kind: str, n: int, M: int, N: int, s: int) -> float:
     """Compulsory HBM bytes of one launch of each kernel class.
 
@@ -831,7 +837,7 @@ def main():
     print(f"[bench] timed {a.steps} steps: {ms:.2f} ms (wall {wall:.3f} s)", file=sys.stderr,
           flush=True)
 
-    upd_step = wl.n ** 3 * wl.M * (1 if wl.scheme == "euler" else 4)   # stages per step
+    upd_step = wl.n ** 3 * wl.M * stages_per_step(wl.scheme)
     value = upd_step * a.steps / (ms / 1e3)
     sbytes = 8 if wl.precision == "f64" else 4
 
